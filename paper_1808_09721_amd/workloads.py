@@ -1,0 +1,226 @@
+"""Seeded synthetic initial data for the resistive / two-fluid SRMHD workloads.
+
+This module holds no arithmetic of the numerical method: it only lays out initial
+primitive fields (density, velocity, pressure, B, E) on a grid from closed-form profiles
+and ``numpy.random.default_rng(seed)`` draws.  Conversion to conserved variables is done
+by whoever consumes the data.
+
+Every generator returns a :class:`Workload`: grid and physics parameters plus interior
+arrays ``prims[var][ny][nx]`` and ``EB[6][ny][nx]`` (Bx, By, Bz, Ex, Ey, Ez), float64,
+with ``ny = 1`` in 1-D.  Primitive order: single fluid (rho, vx, vy, vz, p); two fluid
+(rho1, v1x, v1y, v1z, p1, rho2, v2x, v2y, v2z, p2).
+
+Set-ups follow the paper's Sec. 4 (Brio-Wu shock tube, self-similar current sheet,
+Kelvin-Helmholtz instability) with the concrete sizes of the benchmark workloads.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SINGLE_FLUID, TWO_FLUID = 0, 1
+BC_OUTFLOW, BC_PERIODIC = 0, 1
+
+
+@dataclass
+class Workload:
+    name: str
+    model: int
+    ndim: int
+    nx: int
+    ny: int
+    x0: float
+    x1: float
+    y0: float
+    y1: float
+    gamma: float
+    sigma: float
+    bc: int
+    cfl: float = 0.5
+    mu1: float = 0.0
+    mu2: float = 0.0
+    kappa: float = 1.0
+    steps: int = 100
+    t_end: float | None = None
+    prims: np.ndarray = field(default=None, repr=False)
+    EB: np.ndarray = field(default=None, repr=False)
+    sigma_cell: np.ndarray | None = field(default=None, repr=False)  # interior [ny][nx] or None
+
+    @property
+    def dx(self) -> float:
+        return (self.x1 - self.x0) / self.nx
+
+    @property
+    def dy(self) -> float:
+        return (self.y1 - self.y0) / self.ny if self.ndim == 2 else 1.0
+
+    @property
+    def ncons(self) -> int:
+        return 14 if self.model == SINGLE_FLUID else 18
+
+    @property
+    def nprim(self) -> int:
+        return 5 if self.model == SINGLE_FLUID else 10
+
+    @property
+    def cells(self) -> int:
+        return self.nx * (self.ny if self.ndim == 2 else 1)
+
+
+def _centres(n: int, lo: float, hi: float) -> np.ndarray:
+    return lo + (np.arange(n) + 0.5) * (hi - lo) / n
+
+
+def brio_wu_1d(nx: int = 400, sigma: float = 100.0, seed: int = 1, noise: float = 1e-6) -> Workload:
+    """1-D resistive Brio-Wu shock tube on [0, 1] (Sec. 4.1): left state (rho, p, By, Bx) =
+    (1, 1, 1, 0.5), right (0.125, 0.1, -1, 0.5), v = E = 0, Gamma = 2, outflow boundaries,
+    split at x = 1/2, seeded uniform noise of amplitude ``noise`` on rho, t_end = 0.4."""
+    rng = np.random.default_rng(seed)
+    x = _centres(nx, 0.0, 1.0)
+    left = x < 0.5
+    prims = np.zeros((5, 1, nx))
+    EB = np.zeros((6, 1, nx))
+    prims[0, 0] = np.where(left, 1.0, 0.125) + noise * rng.uniform(-1.0, 1.0, nx)
+    prims[4, 0] = np.where(left, 1.0, 0.1)
+    EB[0, 0] = 0.5
+    EB[1, 0] = np.where(left, 1.0, -1.0)
+    return Workload("brio_wu_1d", SINGLE_FLUID, 1, nx, 1, 0.0, 1.0, 0.0, 1.0, gamma=2.0, sigma=sigma,
+                    bc=BC_OUTFLOW, steps=320, t_end=0.4, prims=prims, EB=EB)
+
+
+def kelvin_helmholtz_2d(nx: int = 256, ny: int = 512, sigma: float = 1e3, seed: int = 2,
+                        steps: int = 100) -> Workload:
+    """2-D resistive Kelvin-Helmholtz set-up on [-1/2, 1/2] x [-1, 1], periodic (Sec. 4.4):
+    shear layers at |y| = 1/2 of width a = 0.01 with v_x = 0.5 tanh((|y| - 1/2)/a),
+    rho = 0.55 - 0.45 tanh((|y| - 1/2)/a) (1 between the layers, 0.1 outside), p = 1,
+    B_z = 0.1, E = 0, Gamma = 4/3, and a seeded random v_y = 0.01 xi exp(-(|y| - 1/2)^2/l^2)
+    with xi ~ U(-1, 1) per cell and l = 0.1."""
+    rng = np.random.default_rng(seed)
+    x = _centres(nx, -0.5, 0.5)
+    y = _centres(ny, -1.0, 1.0)
+    Y = np.broadcast_to(y[:, None], (ny, nx))
+    a, l = 0.01, 0.1
+    t = np.tanh((np.abs(Y) - 0.5) / a)
+    prims = np.zeros((5, ny, nx))
+    EB = np.zeros((6, ny, nx))
+    prims[0] = 0.55 - 0.45 * t
+    prims[1] = 0.5 * t
+    prims[2] = 0.01 * rng.uniform(-1.0, 1.0, (ny, nx)) * np.exp(-((np.abs(Y) - 0.5) ** 2) / l ** 2)
+    prims[4] = 1.0
+    EB[2] = 0.1
+    del x
+    return Workload("kelvin_helmholtz_2d", SINGLE_FLUID, 2, nx, ny, -0.5, 0.5, -1.0, 1.0, gamma=4.0 / 3.0,
+                    sigma=sigma, bc=BC_PERIODIC, steps=steps, prims=prims, EB=EB)
+
+
+def two_fluid_sheet_2d(nx: int = 512, ny: int = 512, sigma: float = 1e4, mu: float = 1000.0, seed: int = 3,
+                       noise: float = 1e-3, delta: float = 0.05, steps: int = 100,
+                       sigma_range: tuple[float, float] | None = None) -> Workload:
+    """2-D two-fluid current sheet on [-1/2, 1/2)^2, periodic: two species with charge-to-
+    mass ratios +mu and -mu, rho_s = p_s = 1, Gamma = 4/3, B_y = tanh(x/d) - tanh((x - 1/2)/d)
+    - tanh((x + 1/2)/d) (the sheet at x = 0 plus its periodic return sheet at x = +-1/2),
+    E = 0, and seeded uniform velocity noise of amplitude ``noise`` per component, species
+    and cell.  With ``sigma_range`` the conductivity is drawn per cell, log-uniform."""
+    rng = np.random.default_rng(seed)
+    x = _centres(nx, -0.5, 0.5)
+    X = np.broadcast_to(x[None, :], (ny, nx))
+    prims = np.zeros((10, ny, nx))
+    EB = np.zeros((6, ny, nx))
+    for s in range(2):
+        prims[5 * s + 0] = 1.0
+        prims[5 * s + 4] = 1.0
+        for c in range(3):
+            prims[5 * s + 1 + c] = noise * rng.uniform(-1.0, 1.0, (ny, nx))
+    EB[1] = np.tanh(X / delta) - np.tanh((X - 0.5) / delta) - np.tanh((X + 0.5) / delta)
+    sigma_cell = None
+    if sigma_range is not None:
+        lo, hi = np.log10(sigma_range[0]), np.log10(sigma_range[1])
+        sigma_cell = 10.0 ** rng.uniform(lo, hi, (ny, nx))
+    return Workload("two_fluid_sheet_2d", TWO_FLUID, 2, nx, ny, -0.5, 0.5, -0.5, 0.5, gamma=4.0 / 3.0,
+                    sigma=sigma, bc=BC_PERIODIC, mu1=mu, mu2=-mu, steps=steps, prims=prims, EB=EB,
+                    sigma_cell=sigma_cell)
+
+
+def entropy_wave_1d(nx: int, sigma: float = 1e6, model: int = SINGLE_FLUID, mu: float = 1000.0,
+                    amplitude: float = 0.5, vx: float = 0.5, t_end: float = 2.0) -> Workload:
+    """Smooth advected density wave on the periodic unit interval: rho = 1 + A sin(2 pi x),
+    v = (vx, 0, 0), p = 1, B = (0, 0, 0.1) and E = -v x B = (0, vx B_z, 0), so the fluid is
+    force free and current free and the exact solution is rho(x - vx t).  Two fluid: both
+    species carry the same density profile and velocity (rho_s = rho/2, p_s = 1/2)."""
+    x = _centres(nx, 0.0, 1.0)
+    Bz = 0.1
+    EB = np.zeros((6, 1, nx))
+    EB[2] = Bz
+    EB[4] = vx * Bz
+    rho = 1.0 + amplitude * np.sin(2.0 * np.pi * x)
+    if model == SINGLE_FLUID:
+        prims = np.zeros((5, 1, nx))
+        prims[0, 0] = rho
+        prims[1, 0] = vx
+        prims[4, 0] = 1.0
+        return Workload("entropy_wave_1d", SINGLE_FLUID, 1, nx, 1, 0.0, 1.0, 0.0, 1.0, gamma=4.0 / 3.0,
+                        sigma=sigma, bc=BC_PERIODIC, t_end=t_end, steps=0, prims=prims, EB=EB)
+    prims = np.zeros((10, 1, nx))
+    for s in range(2):
+        prims[5 * s + 0, 0] = 0.5 * rho
+        prims[5 * s + 1, 0] = vx
+        prims[5 * s + 4, 0] = 0.5
+    return Workload("entropy_wave_1d_tf", TWO_FLUID, 1, nx, 1, 0.0, 1.0, 0.0, 1.0, gamma=4.0 / 3.0,
+                    sigma=sigma, bc=BC_PERIODIC, mu1=mu, mu2=-mu, t_end=t_end, steps=0, prims=prims, EB=EB)
+
+
+def current_sheet_1d(nx: int = 50, sigma: float = 100.0, model: int = SINGLE_FLUID, mu: float = 1000.0,
+                     t0: float = 1.0, half_width: float = 1.5) -> Workload:
+    """Self-similar current sheet (Sec. 4.2): rho = 1, p = 50, v = 0, E = 0 and
+    B_y = erf(x sqrt(sigma / t0) / 2) at the start time t0 = 1, on [-1.5, 1.5] with outflow
+    boundaries (the domain is not printed).  Two fluid: a pair plasma with rho_s = 1/2,
+    p_s = 25 and charge-to-mass ratios +-mu."""
+    from math import erf
+    x = _centres(nx, -half_width, half_width)
+    EB = np.zeros((6, 1, nx))
+    EB[1, 0] = [erf(0.5 * xi * np.sqrt(sigma / t0)) for xi in x]
+    if model == SINGLE_FLUID:
+        prims = np.zeros((5, 1, nx))
+        prims[0, 0] = 1.0
+        prims[4, 0] = 50.0
+        return Workload("current_sheet_1d", SINGLE_FLUID, 1, nx, 1, -half_width, half_width, 0.0, 1.0,
+                        gamma=4.0 / 3.0, sigma=sigma, bc=BC_OUTFLOW, prims=prims, EB=EB, steps=0)
+    prims = np.zeros((10, 1, nx))
+    for s in range(2):
+        prims[5 * s + 0, 0] = 0.5
+        prims[5 * s + 4, 0] = 25.0
+    return Workload("current_sheet_1d_tf", TWO_FLUID, 1, nx, 1, -half_width, half_width, 0.0, 1.0,
+                    gamma=4.0 / 3.0, sigma=sigma, bc=BC_OUTFLOW, mu1=mu, mu2=-mu, prims=prims, EB=EB, steps=0)
+
+
+def random_states(n: int, model: int, seed: int, w_max: float = 10.0, field_max: float = 10.0,
+                  log_rho: tuple[float, float] = (-2.0, 2.0), log_p_over_rho: tuple[float, float] = (-3.0, 3.0),
+                  drift: float | None = None):
+    """Random physical cell states for per-cell tests: Lorentz factor uniform in [1, w_max]
+    with isotropic direction, rho log-uniform over ``log_rho`` (decades), p/rho log-uniform
+    over ``log_p_over_rho``, E and B components uniform in [-field_max, field_max].  Two
+    fluid: each species drawn independently, or, with ``drift``, species 2 copies species 1's
+    density and pressure up to a relative perturbation in [-drift, drift] and its velocity up
+    to an absolute drift in [-drift, drift] per component (a quasi-neutral plasma carrying a
+    current).  Returns (prims[n][nprim], EB[n][6])."""
+    rng = np.random.default_rng(seed)
+    nsp = 1 if model == SINGLE_FLUID else 2
+    prims = np.zeros((n, 5 * nsp))
+    for s in range(nsp):
+        W = rng.uniform(1.0, w_max, n)
+        vmag = np.sqrt(1.0 - 1.0 / W ** 2)
+        d = rng.normal(size=(n, 3))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        rho = 10.0 ** rng.uniform(log_rho[0], log_rho[1], n)
+        prims[:, 5 * s + 0] = rho
+        prims[:, 5 * s + 1:5 * s + 4] = vmag[:, None] * d
+        prims[:, 5 * s + 4] = rho * 10.0 ** rng.uniform(log_p_over_rho[0], log_p_over_rho[1], n)
+    if nsp == 2 and drift is not None:
+        prims[:, 5] = prims[:, 0] * (1.0 + drift * rng.uniform(-1.0, 1.0, n))
+        prims[:, 9] = prims[:, 4] * (1.0 + drift * rng.uniform(-1.0, 1.0, n))
+        v2 = prims[:, 1:4] + drift * rng.uniform(-1.0, 1.0, (n, 3))
+        speed = np.linalg.norm(v2, axis=1, keepdims=True)
+        prims[:, 6:9] = np.where(speed < 0.999, v2, v2 * 0.999 / speed)
+    EB = rng.uniform(-field_max, field_max, (n, 6))
+    return prims, EB
