@@ -1,0 +1,145 @@
+#!/usr/bin/env python3
+"""Benchmark: FP64 cell-updates/s of the SSP2(222) IMEX step on one MI355X.
+
+Workload: 2-D resistive single-fluid Kelvin-Helmholtz set-up, 256 x 512 cells on
+[-1/2, 1/2] x [-1, 1], periodic, Gamma = 4/3, sigma = 1e3, seeded random v_y perturbation,
+FP64 (the configuration the headline metric is quoted on).  One step = one full
+SSP2(222) IMEX step over the whole grid: two implicit-stage solves (Newton per cell with
+nested primitive recovery), two FVS + WENO3 flux passes fused with the stage combiners,
+and the primitive recovery of the new state.  State is resident in HBM throughout.
+
+Prints one JSON line.  ``--gpus`` above 1 is refused: this build measures one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def cpu_baseline(budget_s: float = 12.0) -> dict:
+    """The CPU oracle on the same workload, on this host's cores (OpenMP over cells)."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from oracle import oracle as O
+    from oracle_runs import advance, initial_state
+    from paper_1808_09721_amd import workloads as WL
+    wl = WL.kelvin_helmholtz_2d()
+    g, cons, prims = initial_state(wl)
+    dt = O.dt(g, wl.cfl)
+    t0 = time.perf_counter()
+    advance(g, cons, prims, dt, steps=1)
+    t1 = time.perf_counter() - t0
+    steps = max(1, min(100, int(budget_s / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    advance(g, cons, prims, dt, steps=steps)
+    el = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": wl.cells * steps / el, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"kelvin_helmholtz_2d 256x512, {steps} SSP2(222) steps after 1 untimed, "
+                      f"OpenMP over cells ({cores} threads), {el:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--timing-steps", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures a single GPU; --gpus {args.gpus} is not supported "
+              "(the path shards by domain slabs, see DESIGN.md)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_1808_09721_amd import perfmodel as PM
+    from paper_1808_09721_amd import rmhd as R
+    from paper_1808_09721_amd import workloads as WL
+
+    torch.cuda.set_device(0)
+    wl = WL.kelvin_helmholtz_2d()
+    solver = R.Solver(R.params_from(wl))
+    cons, prims = solver.initial_state(wl.prims, wl.EB)
+    dt = solver.dt()
+    for _ in range(args.warmup):
+        solver.step(dt, cons, prims)
+    solver.stats(reset=True)
+
+    # timed region: K whole steps on torch's current stream (the library's stream)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        solver.step(dt, cons, prims)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = e0.elapsed_time(e1)
+    st = solver.stats(reset=True)
+    cells = wl.cells
+    value = cells * args.steps / (ms / 1e3)
+
+    # per-kernel pass: HIP events around every launch on the same stream
+    R.rmhd_set_timing(solver.ctx, True)
+    R.rmhd_get_timing(solver.ctx, reset=True)
+    for _ in range(args.timing_steps):
+        solver.step(dt, cons, prims)
+    tm = R.rmhd_get_timing(solver.ctx, reset=True)
+    st2 = solver.stats(reset=True)
+    R.rmhd_set_timing(solver.ctx, False)
+    stage_ms = tm["stage_ms"] / tm["stage_launches"]
+    flux_ms = tm["flux_ms"] / tm["flux_launches"]
+    c2p_ms = tm["c2p_ms"] / tm["c2p_launches"]
+    flops = PM.stage_flops(wl.model, st2["stage_cells"], st2["residual_evals"], st2["newton_iters"],
+                           st2["c2p_iters"])
+    stage_tflops = flops / tm["stage_launches"] / (stage_ms / 1e3) / 1e12
+    flux_bytes = 0.5 * (PM.flux_bytes_per_cell(wl.model, "first") + PM.flux_bytes_per_cell(wl.model, "second"))
+    flux_gbs = flux_bytes * cells / (flux_ms / 1e3) / 1e9
+    kernels = {
+        "implicit_stage": {"bound": "alu", "achieved": stage_tflops, "peak": PM.PEAK_FP64_VECTOR_TFLOPS,
+                           "unit": "TFLOP/s", "frac": stage_tflops / PM.PEAK_FP64_VECTOR_TFLOPS,
+                           "ms_per_launch": stage_ms, "flops_per_cell": flops / st2["stage_cells"]},
+        "flux": {"bound": "hbm", "achieved": flux_gbs, "peak": PM.PEAK_HBM_GBS, "unit": "GB/s",
+                 "frac": flux_gbs / PM.PEAK_HBM_GBS, "ms_per_launch": flux_ms, "bytes_per_cell": flux_bytes},
+        "c2p": {"ms_per_launch": c2p_ms},
+    }
+    dominant = "implicit_stage" if 2 * stage_ms >= 2 * flux_ms else "flux"
+    roof = {k: kernels[dominant][k] for k in ("bound", "achieved", "peak", "unit", "frac")}
+    roof["kernel"] = dominant
+    roof["traffic"] = None
+
+    out = {
+        "metric": "FP64 cell-updates/s per IMEX step + Newton iters/cell, plain vs batched+learned",
+        "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "kelvin_helmholtz_2d 256x512 resistive single fluid, sigma=1e3, periodic, "
+                               "SSP2(222) IMEX + FVS/WENO3, plain form", "cells": cells,
+                   "parallelism": "single GPU"},
+        "newton_iters_per_cell_stage": st["newton_iters"] / max(1, st["stage_cells"]),
+        "newton_iters_max": st["newton_max"],
+        "c2p_iters_per_residual": st["c2p_iters"] / max(1, st["residual_evals"]),
+        "failures": st["failures"],
+        "wall_s": wall,
+        "roofline": roof,
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"]["gpu_speedup"] = value / out["cpu_baseline"]["value"]
+    print(json.dumps(out), flush=True)
+    solver.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

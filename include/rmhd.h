@@ -1,0 +1,172 @@
+/*
+ * rmhd.h -- C ABI of librmhd.so: the MI355X (gfx950) hot path of the finite-volume IMEX
+ * scheme for resistive single-fluid and two-fluid special-relativistic MHD of Wright &
+ * Hawke, "Resistive and multi-fluid RMHD on graphics processing units" (arXiv:1808.09721).
+ *
+ * The problem is the balance law  d_t q = L(q) + Psi(q)  (Sec. 2.2.1, Eq. 9) with
+ * L(q) = -d_k f^k(q) from Lax-Friedrichs flux-vector splitting and WENO3 (Sec. 2.2.2,
+ * Eq. 12) and the stiff source Psi (Sec. 2.1.1 Eq. 1; Appendix A Eq. A2), advanced by the
+ * SSP2(222) IMEX Runge-Kutta scheme (Sec. 2.2.1, Eqs. 10-11, Table 2).
+ *
+ * Memory.  Every array argument is a DEVICE pointer owned by the caller; the library never
+ * frees or reallocates it.  Arrays are FP64 structure-of-arrays: variable v of cell (i, j)
+ * lives at  base[v * plane + j * pitch + i],  i = 0 .. nx+3 (two ghost cells each side),
+ * j = 0 .. ny+3 in 2-D and j = 0 in 1-D; interior cells are i = 2 .. nx+1 (and
+ * j = 2 .. ny+1 in 2-D).  pitch and plane come from rmhd_layout_of(); pitch is nx+4 rounded
+ * up to a multiple of 8 doubles; columns beyond nx+3 are padding that is never read.
+ * Status arrays (int8) and iteration arrays (int32) use one plane of the same indexing.
+ *
+ * Variable orders:
+ *   single fluid  conserved (14): D, Sx, Sy, Sz, tau, Bx, By, Bz, Ex, Ey, Ez, rho_e, psi, phi
+ *                 primitive  (5): rho, vx, vy, vz, p
+ *   two fluid     conserved (18): D, Sx, Sy, Sz, tau, Dbar, Sbx, Sby, Sbz, taubar,
+ *                                 Bx, By, Bz, Ex, Ey, Ez, psi, phi
+ *                 primitive (10): rho1, v1x, v1y, v1z, p1, rho2, v2x, v2y, v2z, p2
+ *   fields EB (6, init only):     Bx, By, Bz, Ex, Ey, Ez
+ *
+ * Streams.  All work is enqueued on the HIP stream given to rmhd_create() and is ordered
+ * with the caller's other work on that stream; calls return before the GPU finishes,
+ * except rmhd_get_stats(), which synchronises the stream.
+ *
+ * Errors.  Functions return RMHD_OK (0) or a negative code; the message is available from
+ * rmhd_last_error(ctx) (or rmhd_last_error(NULL) for failures before a context exists).
+ * A cell whose root-finds do not converge is NOT an error return: it is reported in the
+ * per-cell status array and in the counters of rmhd_get_stats().  No C++ exception crosses
+ * this interface.  A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef RMHD_H
+#define RMHD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RMHD_SINGLE_FLUID 0
+#define RMHD_TWO_FLUID 1
+#define RMHD_BC_OUTFLOW 0  /* zero-gradient copy of the nearest interior cell */
+#define RMHD_BC_PERIODIC 1
+
+#define RMHD_OK 0
+#define RMHD_EINVAL (-1)
+#define RMHD_EHIP (-2)
+#define RMHD_ENOMEM (-3)
+
+/* per-cell status codes */
+#define RMHD_CELL_OK 0
+#define RMHD_CELL_C2P_NOCONV 1
+#define RMHD_CELL_C2P_UNPHYSICAL 2
+#define RMHD_CELL_NEWTON_NOCONV 3
+#define RMHD_CELL_LINESEARCH 4
+
+typedef struct rmhd_params {
+    int32_t model;            /* RMHD_SINGLE_FLUID or RMHD_TWO_FLUID */
+    int32_t ndim;             /* 1 or 2 */
+    int32_t nx, ny;           /* interior cells (ny = 1 in 1-D) */
+    int32_t bc;               /* RMHD_BC_OUTFLOW or RMHD_BC_PERIODIC, all sides */
+    int32_t max_c2p_iter;     /* primitive-recovery iteration cap (e.g. 100) */
+    int32_t max_newton_iter;  /* implicit-stage iteration cap (e.g. 50) */
+    int32_t friction_covariant; /* two-fluid friction: 0 = eta (J - rho_e u) as printed in
+                                   Eq. A2, 1 = eta (J - rho_0 u) with the rest-frame charge */
+    double x0, x1, y0, y1;    /* domain; dx = (x1-x0)/nx, dy = (y1-y0)/ny */
+    double gamma_eos;         /* Gamma-law index (both species) */
+    double sigma;             /* conductivity; two-fluid resistivity eta = 1/sigma */
+    const double *sigma_cell; /* optional device plane of per-cell conductivities (ghosts
+                                 included, same indexing as a state plane), or NULL */
+    double mu1, mu2;          /* two-fluid charge-to-mass ratios */
+    double kappa;             /* divergence-cleaning damping rate (1 in the paper) */
+    double cfl;               /* CFL number for rmhd_dt() */
+    double c2p_tol;           /* primitive-recovery residual tolerance (1e-13, Sec. 2.1.3) */
+    double newton_tol;        /* implicit-stage residual tolerance (e.g. 1e-12) */
+} rmhd_params;
+
+typedef struct rmhd_layout {
+    int64_t nxg, nyg;         /* cells per row / rows, ghosts included */
+    int64_t pitch;            /* doubles between rows */
+    int64_t plane;            /* doubles between variables */
+    int32_t ncons, nprim;
+} rmhd_layout;
+
+typedef struct rmhd_stats {
+    int64_t stage_cells;      /* cell solves counted (interior cells x implicit stages) */
+    int64_t newton_iters;     /* their Newton iterations, summed */
+    int64_t residual_evals;   /* their residual evaluations (Newton trials included), summed */
+    int64_t c2p_iters;        /* primitive-recovery iterations inside them, summed */
+    int32_t newton_max;       /* largest Newton iteration count of one cell */
+    int32_t failures;         /* cell solves that ended with a nonzero status */
+} rmhd_stats;
+
+/* Per-kernel GPU time of rmhd_imex_step, from HIP events recorded on the context's stream
+ * around every launch while timing is enabled (rmhd_set_timing). */
+typedef struct rmhd_timing {
+    double stage_ms;          /* implicit-stage kernel, summed */
+    double flux_ms;           /* flux-divergence + combiner kernel, summed */
+    double c2p_ms;            /* primitive-recovery kernel, summed */
+    int64_t stage_launches, flux_launches, c2p_launches;
+    int64_t steps;
+} rmhd_timing;
+
+typedef struct rmhd_ctx rmhd_ctx;
+
+/* Array geometry for a parameter set (no GPU work).  Returns RMHD_EINVAL on bad sizes. */
+int rmhd_layout_of(const rmhd_params *params, rmhd_layout *out);
+
+/* Create a context on the current HIP device: validates params, allocates the library's
+ * own scratch (stage buffers, counters) and binds the stream (hipStream_t, NULL = default).
+ * The params (and sigma_cell pointer) are copied; sigma_cell must stay valid. */
+int rmhd_create(const rmhd_params *params, void *hip_stream, rmhd_ctx **out);
+void rmhd_destroy(rmhd_ctx *ctx);
+
+/* Initial data (Sec. 2.1.1, Eq. 2; Sec. 2.1.2, Eq. 6): cons on every cell from the interior
+ * primitives and fields; rho_e = div E by second-order central differences (Gauss's law,
+ * Sec. 2.1.1); psi = phi = 0; ghost cells of cons are filled by the boundary condition.
+ * prims/EB: interior read only.  cons: written everywhere. */
+int rmhd_init_state(rmhd_ctx *ctx, const double *prims, const double *EB, double *cons);
+
+/* Primitive recovery (Sec. 2.1.3) on every cell, ghosts included.  prims holds the pressure
+ * guesses on entry (non-physical values are replaced by a bracket midpoint) and the
+ * primitives on exit.  status/iters (int8 / int32 planes) may be NULL. */
+int rmhd_cons2prim(rmhd_ctx *ctx, const double *cons, double *prims, int8_t *status, int32_t *iters);
+
+/* L(q) = -d_k f^k(q) (Eq. 9; FVS + WENO3, Sec. 2.2.2) on the interior cells.  First fills the
+ * ghost cells of cons and prims in place from their interior by the boundary condition.
+ * L: written on the interior only. */
+int rmhd_F(rmhd_ctx *ctx, double *cons, double *prims, double *L);
+
+/* Implicit stage (Sec. 2.2.1, Eq. 10): solve Q = R + a Psi(Q) per cell, a = a_ii dt, on every
+ * cell including ghosts (so Q's ghosts follow R's).  guess: optional array of conserved
+ * variables whose source-carrying components start Newton (NULL = the plain guess R).
+ * prims: pressure guesses on entry, primitives of Q on exit.  Q may alias R.  status and
+ * iters (Newton iterations) may be NULL. */
+int rmhd_implicit_stage(rmhd_ctx *ctx, double a, const double *R, const double *guess, double *Q,
+                        double *prims, int8_t *status, int32_t *iters);
+
+/* One SSP2(222) IMEX step of size dt (Sec. 2.2.1, Eqs. 10-11, Table 2, gamma = 1 - 1/sqrt 2).
+ * cons (ghosts valid) is advanced in place; prims holds the primitives of cons on entry
+ * (used as root-find starting points) and those of the new cons on exit, ghosts included.
+ * Counters of the two stage solves are accumulated into the context's statistics. */
+int rmhd_imex_step(rmhd_ctx *ctx, double dt, double *cons, double *prims);
+
+/* Time step CFL / sum_d (1/dx_d) (maximum signal speed c = 1). */
+double rmhd_dt(const rmhd_ctx *ctx);
+
+/* Copy the accumulated statistics (synchronises the stream); reset != 0 zeroes them. */
+int rmhd_get_stats(rmhd_ctx *ctx, rmhd_stats *out, int reset);
+
+/* Enable (1) or disable (0) per-kernel event timing of rmhd_imex_step.  While enabled each
+ * step waits for its own kernels to finish (to read the events), so it is meant for a
+ * measurement pass, not for production stepping. */
+int rmhd_set_timing(rmhd_ctx *ctx, int enable);
+
+/* Copy the accumulated per-kernel times; reset != 0 zeroes them. */
+int rmhd_get_timing(rmhd_ctx *ctx, rmhd_timing *out, int reset);
+
+/* Message of the last failing call on ctx (or of the last failing rmhd_create/layout call
+ * when ctx is NULL).  Owned by the library; valid until the next call on the same ctx. */
+const char *rmhd_last_error(const rmhd_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

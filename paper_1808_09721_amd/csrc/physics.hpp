@@ -1,0 +1,409 @@
+// physics.hpp -- device-side physics of the resistive single-fluid and two-fluid SRMHD
+// model of Wright & Hawke (arXiv:1808.09721) for the gfx950 kernels: conserved <-> primitive
+// maps, flux vectors, sources, and the per-cell implicit-stage Newton solve.
+//
+// Everything here is FP64 (Sec. 3: the 1e-13 recovery tolerance needs double precision).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+namespace rmhd {
+
+// ---------------------------------------------------------------------------------------
+// variable orders (as documented in include/rmhd.h)
+// ---------------------------------------------------------------------------------------
+namespace sf {
+enum { D, SX, SY, SZ, TAU, BX, BY, BZ, EX, EY, EZ, RHOE, PSI, PHI, NC };
+constexpr int NP = 5;
+}  // namespace sf
+namespace tf {
+enum { D, SX, SY, SZ, TAU, DB, SBX, SBY, SBZ, TAUB, BX, BY, BZ, EX, EY, EZ, PSI, PHI, NC };
+constexpr int NP = 10;
+}  // namespace tf
+
+enum CellStatus { CELL_OK = 0, CELL_C2P_NOCONV = 1, CELL_C2P_UNPHYS = 2, CELL_NEWTON_NOCONV = 3,
+                  CELL_LINESEARCH = 4 };
+
+// Per-launch physics constants (by value in every kernel).
+struct Phys {
+    double gamma;      // Gamma-law index
+    double gk;         // (Gamma - 1) / Gamma
+    double hk;         // Gamma / (Gamma - 1):  rho h = rho + hk p
+    double sigma;      // scalar conductivity (two fluid: eta = 1/sigma)
+    const double *sigma_cell;  // per-cell conductivity plane or nullptr
+    double mu1, mu2, kappa;
+    double c2p_tol, newton_tol;
+    int max_c2p, max_newton;
+    int friction_covariant;
+    int pad_;
+};
+
+__device__ __forceinline__ double cell_sigma(const Phys &P, long idx)
+{
+    return P.sigma_cell ? P.sigma_cell[idx] : P.sigma;
+}
+
+// ---------------------------------------------------------------------------------------
+// forward-mode dual number (one tangent) for the exact stage Jacobian
+// ---------------------------------------------------------------------------------------
+struct dual {
+    double v, d;
+};
+__device__ __forceinline__ dual mk(double v, double d = 0.0) { return dual{v, d}; }
+__device__ __forceinline__ dual operator+(dual a, dual b) { return {a.v + b.v, a.d + b.d}; }
+__device__ __forceinline__ dual operator-(dual a, dual b) { return {a.v - b.v, a.d - b.d}; }
+__device__ __forceinline__ dual operator-(dual a) { return {-a.v, -a.d}; }
+__device__ __forceinline__ dual operator*(dual a, dual b) { return {a.v * b.v, a.v * b.d + a.d * b.v}; }
+__device__ __forceinline__ dual operator+(dual a, double b) { return {a.v + b, a.d}; }
+__device__ __forceinline__ dual operator+(double b, dual a) { return {a.v + b, a.d}; }
+__device__ __forceinline__ dual operator-(dual a, double b) { return {a.v - b, a.d}; }
+__device__ __forceinline__ dual operator-(double b, dual a) { return {b - a.v, -a.d}; }
+__device__ __forceinline__ dual operator*(dual a, double b) { return {a.v * b, a.d * b}; }
+__device__ __forceinline__ dual operator*(double b, dual a) { return {a.v * b, a.d * b}; }
+__device__ __forceinline__ dual recip(dual a)
+{
+    const double r = 1.0 / a.v;
+    return {r, -a.d * r * r};
+}
+__device__ __forceinline__ dual dsqrt(dual a)
+{
+    const double s = sqrt(a.v);
+    return {s, 0.5 * a.d / s};
+}
+template <class T>
+__device__ __forceinline__ T lift(double v);
+template <>
+__device__ __forceinline__ double lift<double>(double v) { return v; }
+template <>
+__device__ __forceinline__ dual lift<dual>(double v) { return dual{v, 0.0}; }
+__device__ __forceinline__ double recip(double a) { return 1.0 / a; }
+__device__ __forceinline__ double dsqrt(double a) { return sqrt(a); }
+__device__ __forceinline__ double value(double a) { return a; }
+__device__ __forceinline__ double value(dual a) { return a.v; }
+
+template <class T>
+struct vec3 {
+    T x, y, z;
+};
+template <class T>
+__device__ __forceinline__ vec3<T> v3(T a, T b, T c) { return vec3<T>{a, b, c}; }
+template <class T, class U>
+__device__ __forceinline__ auto dot(const vec3<T> &a, const vec3<U> &b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+template <class T, class U>
+__device__ __forceinline__ auto cross(const vec3<T> &a, const vec3<U> &b)
+{
+    using R = decltype(a.x * b.x);
+    return vec3<R>{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+
+// ---------------------------------------------------------------------------------------
+// Primitive recovery of one fluid (Sec. 2.1.3).
+// Unknown z = rho h W^2 (= taut + D + p).  With v^2 = s^2/z^2, 1/W = sqrt(1 - v^2),
+// rho = D/W, the Gamma law gives p(z) = (Gamma-1)/Gamma (z (1 - v^2) - D/W), and the root of
+// g(z) = z - Eh - p(z), Eh = taut + D, is sought.  g is increasing for Gamma <= 2 on the
+// physical bracket z in (max(s, Eh), Gamma Eh].  Newton, safeguarded by bisection, stops at
+// |g| <= tol max(1, p) and then takes one more Newton step.
+// ---------------------------------------------------------------------------------------
+struct Root {
+    double z;    // rho h W^2 at the root
+    double iW;   // 1/W
+    int status;  // CELL_OK / CELL_C2P_NOCONV / CELL_C2P_UNPHYS
+    int iters;
+};
+
+__device__ __forceinline__ Root fluid_root(double D, double s2, double Eh, double zguess, const Phys &P)
+{
+    Root r;
+    r.iters = 0;
+    r.z = zguess;
+    r.iW = 1.0;
+    const double s = sqrt(s2);
+    double lo = fmax(s, Eh);
+    double hi = P.gamma * Eh;
+    if (!(D > 0.0) || !(Eh > 0.0) || !(hi > lo)) {
+        r.status = CELL_C2P_UNPHYS;
+        return r;
+    }
+    double z = (zguess > lo && zguess < hi) ? zguess : 0.5 * (lo + hi);
+    r.status = CELL_C2P_NOCONV;
+    for (int it = 1; it <= P.max_c2p; ++it) {
+        const double iz = 1.0 / z;
+        const double v2 = s2 * iz * iz;
+        const double iW = sqrt(1.0 - v2);
+        const double p = P.gk * (z * (1.0 - v2) - D * iW);
+        const double g = z - Eh - p;
+        const double dg = 1.0 - P.gk * (1.0 + v2 - D * v2 * iz / iW);
+        if (g < 0.0) lo = z; else hi = z;
+        double zn = z - g / dg;
+        if (fabs(g) <= P.c2p_tol * fmax(1.0, p)) {
+            if (zn > s && zn >= Eh) z = zn;
+            r.status = CELL_OK;
+            r.iters = it;
+            break;
+        }
+        if (!(zn > lo && zn < hi)) zn = 0.5 * (lo + hi);
+        z = zn;
+        r.iters = it;
+    }
+    r.z = z;
+    const double iz = 1.0 / z;
+    r.iW = sqrt(1.0 - s2 * iz * iz);
+    if (r.status == CELL_OK && !(r.iW > 0.0)) r.status = CELL_C2P_UNPHYS;
+    return r;
+}
+
+// Tangent of the root z through the implicit-function theorem: with z fixed at the root,
+// dg = dg/ds2 ds2 + dg/dEh dEh, and dz = -(dg/ds2 ds2 + dg/dEh dEh) / (dg/dz).
+__device__ __forceinline__ dual root_tangent(const Root &r, double D, dual s2, dual Eh, const Phys &P)
+{
+    const double z = r.z, iz = 1.0 / z, iW = r.iW;
+    const double v2 = s2.v * iz * iz;
+    const double dgdz = 1.0 - P.gk * (1.0 + v2 - D * v2 * iz / iW);
+    const double dgds2 = P.gk * (iz - 0.5 * D * iz * iz / iW);
+    return dual{z, (Eh.d - dgds2 * s2.d) / dgdz};
+}
+__device__ __forceinline__ double root_tangent(const Root &r, double, double, double, const Phys &) { return r.z; }
+
+// ---------------------------------------------------------------------------------------
+// Single fluid (Sec. 2.1.1, Eqs. 1-2)
+// ---------------------------------------------------------------------------------------
+// Ohm's law J = rho_e v + W sigma [E + v x B - (v.E) v]
+template <class T>
+__device__ __forceinline__ vec3<T> sf_current(const vec3<T> &v, T W, const vec3<T> &E, const vec3<double> &B,
+                                               double rhoe, double sig)
+{
+    const vec3<T> vxB = cross(v, B);
+    const T vE = dot(v, E);
+    const T sW = sig * W;
+    return v3<T>(rhoe * v.x + sW * (E.x + vxB.x - vE * v.x), rhoe * v.y + sW * (E.y + vxB.y - vE * v.y),
+                 rhoe * v.z + sW * (E.z + vxB.z - vE * v.z));
+}
+
+// prim (rho, v, p), B, E, rho_e -> 14 conserved
+__device__ inline void sf_prim2cons(const double *w, const double *EB, double rhoe, const Phys &P, double *q)
+{
+    const vec3<double> v = v3(w[1], w[2], w[3]), B = v3(EB[0], EB[1], EB[2]), E = v3(EB[3], EB[4], EB[5]);
+    const double W2 = 1.0 / (1.0 - dot(v, v));
+    const double W = sqrt(W2);
+    const double A = (w[0] + P.hk * w[4]) * W2;  // rho h W^2
+    const vec3<double> ExB = cross(E, B);
+    q[sf::D] = w[0] * W;
+    q[sf::SX] = A * v.x + ExB.x;
+    q[sf::SY] = A * v.y + ExB.y;
+    q[sf::SZ] = A * v.z + ExB.z;
+    q[sf::TAU] = A - w[4] - w[0] * W + 0.5 * (dot(E, E) + dot(B, B));
+    q[sf::BX] = B.x; q[sf::BY] = B.y; q[sf::BZ] = B.z;
+    q[sf::EX] = E.x; q[sf::EY] = E.y; q[sf::EZ] = E.z;
+    q[sf::RHOE] = rhoe;
+    q[sf::PSI] = 0.0;
+    q[sf::PHI] = 0.0;
+}
+
+// 14 conserved -> (rho, v, p); w[4] holds the pressure guess on entry
+__device__ inline int sf_cons2prim(const double *q, double *w, const Phys &P, int &iters)
+{
+    const vec3<double> B = v3(q[sf::BX], q[sf::BY], q[sf::BZ]), E = v3(q[sf::EX], q[sf::EY], q[sf::EZ]);
+    const vec3<double> ExB = cross(E, B);
+    const vec3<double> St = v3(q[sf::SX] - ExB.x, q[sf::SY] - ExB.y, q[sf::SZ] - ExB.z);
+    const double Eh = q[sf::TAU] - 0.5 * (dot(E, E) + dot(B, B)) + q[sf::D];
+    const Root r = fluid_root(q[sf::D], dot(St, St), Eh, Eh + w[4], P);
+    iters = r.iters;
+    const double iz = 1.0 / r.z;
+    w[0] = q[sf::D] * r.iW;
+    w[1] = St.x * iz; w[2] = St.y * iz; w[3] = St.z * iz;
+    w[4] = r.z - Eh;
+    return r.status;
+}
+
+// Flux vectors f^x and f^y and source Psi of one cell from (q, w).
+__device__ inline void sf_flux_source(const double *q, const double *w, double sig, const Phys &P, double *fx,
+                                      double *fy, double *src)
+{
+    const vec3<double> v = v3(w[1], w[2], w[3]);
+    const vec3<double> B = v3(q[sf::BX], q[sf::BY], q[sf::BZ]), E = v3(q[sf::EX], q[sf::EY], q[sf::EZ]);
+    const double W2 = 1.0 / (1.0 - dot(v, v));
+    const double W = sqrt(W2);
+    const double A = (w[0] + P.hk * w[4]) * W2;
+    const double pt = w[4] + 0.5 * (dot(E, E) + dot(B, B));
+    const vec3<double> J = sf_current(v, W, E, B, q[sf::RHOE], sig);
+    // x
+    fx[sf::D] = q[sf::D] * v.x;
+    fx[sf::SX] = A * v.x * v.x + pt - E.x * E.x - B.x * B.x;
+    fx[sf::SY] = A * v.y * v.x - E.y * E.x - B.y * B.x;
+    fx[sf::SZ] = A * v.z * v.x - E.z * E.x - B.z * B.x;
+    fx[sf::TAU] = q[sf::SX] - q[sf::D] * v.x;
+    fx[sf::BX] = q[sf::PHI]; fx[sf::BY] = -E.z; fx[sf::BZ] = E.y;
+    fx[sf::EX] = q[sf::PSI]; fx[sf::EY] = B.z; fx[sf::EZ] = -B.y;
+    fx[sf::RHOE] = J.x;
+    fx[sf::PSI] = E.x;
+    fx[sf::PHI] = B.x;
+    // y
+    fy[sf::D] = q[sf::D] * v.y;
+    fy[sf::SX] = A * v.x * v.y - E.x * E.y - B.x * B.y;
+    fy[sf::SY] = A * v.y * v.y + pt - E.y * E.y - B.y * B.y;
+    fy[sf::SZ] = A * v.z * v.y - E.z * E.y - B.z * B.y;
+    fy[sf::TAU] = q[sf::SY] - q[sf::D] * v.y;
+    fy[sf::BX] = E.z; fy[sf::BY] = q[sf::PHI]; fy[sf::BZ] = -E.x;
+    fy[sf::EX] = -B.z; fy[sf::EY] = q[sf::PSI]; fy[sf::EZ] = B.x;
+    fy[sf::RHOE] = J.y;
+    fy[sf::PSI] = E.y;
+    fy[sf::PHI] = B.y;
+    // source: only E, psi, phi carry one
+    for (int k = 0; k < sf::NC; ++k) src[k] = 0.0;
+    src[sf::EX] = -J.x; src[sf::EY] = -J.y; src[sf::EZ] = -J.z;
+    src[sf::PSI] = q[sf::RHOE] - P.kappa * q[sf::PSI];
+    src[sf::PHI] = -P.kappa * q[sf::PHI];
+}
+
+// ---------------------------------------------------------------------------------------
+// Two fluid (Sec. 2.1.2 Eq. 6; Appendix A Eqs. A1-A3)
+// ---------------------------------------------------------------------------------------
+__device__ inline void tf_prim2cons(const double *w, const double *EB, const Phys &P, double *q)
+{
+    const vec3<double> B = v3(EB[0], EB[1], EB[2]), E = v3(EB[3], EB[4], EB[5]);
+    const double mu[2] = {P.mu1, P.mu2};
+    double Dn = 0, Db = 0, tn = 0, tb = 0;
+    vec3<double> Sn = v3(0.0, 0.0, 0.0), Sb = v3(0.0, 0.0, 0.0);
+    for (int s = 0; s < 2; ++s) {
+        const double *ws = w + 5 * s;
+        const vec3<double> v = v3(ws[1], ws[2], ws[3]);
+        const double W2 = 1.0 / (1.0 - dot(v, v));
+        const double Ds = ws[0] * sqrt(W2);
+        const double A = (ws[0] + P.hk * ws[4]) * W2;
+        const double ts = A - ws[4] - Ds;
+        Dn += Ds; Db += mu[s] * Ds;
+        tn += ts; tb += mu[s] * ts;
+        Sn.x += A * v.x; Sn.y += A * v.y; Sn.z += A * v.z;
+        Sb.x += mu[s] * A * v.x; Sb.y += mu[s] * A * v.y; Sb.z += mu[s] * A * v.z;
+    }
+    const vec3<double> ExB = cross(E, B);
+    q[tf::D] = Dn;
+    q[tf::SX] = Sn.x + ExB.x; q[tf::SY] = Sn.y + ExB.y; q[tf::SZ] = Sn.z + ExB.z;
+    q[tf::TAU] = tn + 0.5 * (dot(E, E) + dot(B, B));
+    q[tf::DB] = Db;
+    q[tf::SBX] = Sb.x; q[tf::SBY] = Sb.y; q[tf::SBZ] = Sb.z;
+    q[tf::TAUB] = tb;
+    q[tf::BX] = B.x; q[tf::BY] = B.y; q[tf::BZ] = B.z;
+    q[tf::EX] = E.x; q[tf::EY] = E.y; q[tf::EZ] = E.z;
+    q[tf::PSI] = 0.0;
+    q[tf::PHI] = 0.0;
+}
+
+// Species split of the hydrodynamic parts (Sec. 2.1.3, Eqs. 7-8): X_1 = (Xbar - mu2 X)/(mu1 - mu2),
+// X_2 = (Xbar - mu1 X)/(mu2 - mu1), X = D, St (= S - E x B), taut (= tau - (E^2+B^2)/2).
+__device__ inline int tf_cons2prim(const double *q, double *w, const Phys &P, int &iters)
+{
+    const vec3<double> B = v3(q[tf::BX], q[tf::BY], q[tf::BZ]), E = v3(q[tf::EX], q[tf::EY], q[tf::EZ]);
+    const vec3<double> ExB = cross(E, B);
+    const vec3<double> St = v3(q[tf::SX] - ExB.x, q[tf::SY] - ExB.y, q[tf::SZ] - ExB.z);
+    const double tt = q[tf::TAU] - 0.5 * (dot(E, E) + dot(B, B));
+    const double i12 = 1.0 / (P.mu1 - P.mu2);
+    int status = CELL_OK;
+    iters = 0;
+    for (int s = 0; s < 2; ++s) {
+        // species 1: (Xbar - mu2 X)/(mu1 - mu2); species 2: -(Xbar - mu1 X)/(mu1 - mu2)
+        const double m = s == 0 ? P.mu2 : P.mu1, sg = s == 0 ? i12 : -i12;
+        const double Ds = (q[tf::DB] - m * q[tf::D]) * sg;
+        const vec3<double> Ss = v3((q[tf::SBX] - m * St.x) * sg, (q[tf::SBY] - m * St.y) * sg,
+                                   (q[tf::SBZ] - m * St.z) * sg);
+        const double Eh = (q[tf::TAUB] - m * tt) * sg + Ds;
+        double *ws = w + 5 * s;
+        const Root r = fluid_root(Ds, dot(Ss, Ss), Eh, Eh + ws[4], P);
+        iters += r.iters;
+        const double iz = 1.0 / r.z;
+        ws[0] = Ds * r.iW;
+        ws[1] = Ss.x * iz; ws[2] = Ss.y * iz; ws[3] = Ss.z * iz;
+        ws[4] = r.z - Eh;
+        if (r.status != CELL_OK && status != CELL_C2P_UNPHYS) status = r.status;
+    }
+    return status;
+}
+
+// Two-fluid source from the primitives, arranged around omega_p^2 W = sum mu_s^2 D_s and
+// omega_p^2 u = sum mu_s^2 D_s v_s (D_s = rho_s W_s), so no division by omega_p^2 is needed
+// except in rho_0 = W rho_e - J.u.
+template <class T>
+struct TFSource {
+    vec3<T> Sb;  // Psi(Sbar)
+    T taub;      // Psi(taubar)
+    vec3<T> J;   // current; Psi(E) = -J
+};
+
+template <class T>
+__device__ __forceinline__ TFSource<T> tf_source_terms(const T Dw[2], const T rho[2], const vec3<T> v[2],
+                                                      const vec3<T> &E, const vec3<double> &B, double eta,
+                                                      const Phys &P)
+{
+    const double mu[2] = {P.mu1, P.mu2};
+    const T wp2 = mu[0] * mu[0] * rho[0] + mu[1] * mu[1] * rho[1];
+    const T M2 = mu[0] * mu[0] * Dw[0] + mu[1] * mu[1] * Dw[1];   // omega_p^2 W
+    const T rhoe = mu[0] * Dw[0] + mu[1] * Dw[1];                 // rho_e
+    const vec3<T> U = v3<T>(mu[0] * mu[0] * Dw[0] * v[0].x + mu[1] * mu[1] * Dw[1] * v[1].x,
+                            mu[0] * mu[0] * Dw[0] * v[0].y + mu[1] * mu[1] * Dw[1] * v[1].y,
+                            mu[0] * mu[0] * Dw[0] * v[0].z + mu[1] * mu[1] * Dw[1] * v[1].z);  // omega_p^2 u
+    const vec3<T> J = v3<T>(mu[0] * Dw[0] * v[0].x + mu[1] * Dw[1] * v[1].x,
+                            mu[0] * Dw[0] * v[0].y + mu[1] * Dw[1] * v[1].y,
+                            mu[0] * Dw[0] * v[0].z + mu[1] * Dw[1] * v[1].z);
+    const T rho0 = (M2 * rhoe - dot(J, U)) * recip(wp2);
+    const T fr = P.friction_covariant ? rho0 : rhoe;
+    const vec3<T> UxB = cross(U, B);
+    TFSource<T> s;
+    s.Sb = v3<T>(M2 * E.x + UxB.x - eta * (wp2 * J.x - fr * U.x), M2 * E.y + UxB.y - eta * (wp2 * J.y - fr * U.y),
+                 M2 * E.z + UxB.z - eta * (wp2 * J.z - fr * U.z));
+    s.taub = dot(U, E) - eta * (wp2 * rhoe - rho0 * M2);
+    s.J = J;
+    return s;
+}
+
+__device__ inline void tf_flux_source(const double *q, const double *w, double sig, const Phys &P, double *fx,
+                                      double *fy, double *src)
+{
+    const vec3<double> B = v3(q[tf::BX], q[tf::BY], q[tf::BZ]), E = v3(q[tf::EX], q[tf::EY], q[tf::EZ]);
+    const double mu[2] = {P.mu1, P.mu2};
+    const double em = 0.5 * (dot(E, E) + dot(B, B));
+    double Dw[2], rho[2], A[2], p[2];
+    vec3<double> v[2];
+    for (int s = 0; s < 2; ++s) {
+        const double *ws = w + 5 * s;
+        v[s] = v3(ws[1], ws[2], ws[3]);
+        const double W2 = 1.0 / (1.0 - dot(v[s], v[s]));
+        rho[s] = ws[0];
+        p[s] = ws[4];
+        Dw[s] = ws[0] * sqrt(W2);
+        A[s] = (ws[0] + P.hk * ws[4]) * W2;
+    }
+    for (int k = 0; k < tf::NC; ++k) { fx[k] = 0.0; fy[k] = 0.0; }
+    for (int s = 0; s < 2; ++s) {
+        const vec3<double> vs = v[s];
+        const double Sxx = A[s] * vs.x * vs.x + p[s], Syx = A[s] * vs.y * vs.x, Szx = A[s] * vs.z * vs.x;
+        const double Syy = A[s] * vs.y * vs.y + p[s], Szy = A[s] * vs.z * vs.y;
+        fx[tf::D] += Dw[s] * vs.x;               fy[tf::D] += Dw[s] * vs.y;
+        fx[tf::SX] += Sxx; fx[tf::SY] += Syx; fx[tf::SZ] += Szx;
+        fy[tf::SX] += Syx; fy[tf::SY] += Syy; fy[tf::SZ] += Szy;
+        fx[tf::DB] += mu[s] * Dw[s] * vs.x;      fy[tf::DB] += mu[s] * Dw[s] * vs.y;
+        fx[tf::SBX] += mu[s] * Sxx; fx[tf::SBY] += mu[s] * Syx; fx[tf::SBZ] += mu[s] * Szx;
+        fy[tf::SBX] += mu[s] * Syx; fy[tf::SBY] += mu[s] * Syy; fy[tf::SBZ] += mu[s] * Szy;
+        fx[tf::TAUB] += mu[s] * (A[s] - Dw[s]) * vs.x;
+        fy[tf::TAUB] += mu[s] * (A[s] - Dw[s]) * vs.y;
+    }
+    fx[tf::SX] += em - E.x * E.x - B.x * B.x; fx[tf::SY] += -E.y * E.x - B.y * B.x; fx[tf::SZ] += -E.z * E.x - B.z * B.x;
+    fy[tf::SX] += -E.x * E.y - B.x * B.y; fy[tf::SY] += em - E.y * E.y - B.y * B.y; fy[tf::SZ] += -E.z * E.y - B.z * B.y;
+    fx[tf::TAU] = q[tf::SX] - fx[tf::D];
+    fy[tf::TAU] = q[tf::SY] - fy[tf::D];
+    fx[tf::BX] = q[tf::PHI]; fx[tf::BY] = -E.z; fx[tf::BZ] = E.y;
+    fx[tf::EX] = q[tf::PSI]; fx[tf::EY] = B.z; fx[tf::EZ] = -B.y;
+    fy[tf::BX] = E.z; fy[tf::BY] = q[tf::PHI]; fy[tf::BZ] = -E.x;
+    fy[tf::EX] = -B.z; fy[tf::EY] = q[tf::PSI]; fy[tf::EZ] = B.x;
+    fx[tf::PSI] = E.x; fx[tf::PHI] = B.x;
+    fy[tf::PSI] = E.y; fy[tf::PHI] = B.y;
+    const TFSource<double> S = tf_source_terms<double>(Dw, rho, v, E, B, 1.0 / sig, P);
+    for (int k = 0; k < tf::NC; ++k) src[k] = 0.0;
+    src[tf::SBX] = S.Sb.x; src[tf::SBY] = S.Sb.y; src[tf::SBZ] = S.Sb.z;
+    src[tf::TAUB] = S.taub;
+    src[tf::EX] = -S.J.x; src[tf::EY] = -S.J.y; src[tf::EZ] = -S.J.z;
+    src[tf::PSI] = q[tf::DB] - P.kappa * q[tf::PSI];
+    src[tf::PHI] = -P.kappa * q[tf::PHI];
+}
+
+}  // namespace rmhd

@@ -1,0 +1,378 @@
+// stage.hpp -- per-cell implicit-stage solve of the SSP2(222) IMEX scheme (Sec. 2.2.1, Eq. 10):
+// Q = R + a Psi(Q).  Components with zero source equal R; phi and psi are linear:
+//   phi = R_phi / (1 + a kappa),  psi = (R_psi + a rho_e) / (1 + a kappa);
+// the remaining unknowns solve a small nonlinear system whose every residual evaluation
+// runs the nested primitive recovery:
+//   single fluid  x = E                              (3 unknowns)
+//   two fluid     x = (Sbar/|mu1|, taubar/|mu1|, E)   (7 unknowns, barred parts scaled to O(1))
+// Newton with the exact Jacobian: each column is one forward-mode (dual-number) pass
+// through the residual, in which the recovery root z = rho h W^2 is differentiated by the
+// implicit-function theorem at the converged root instead of iterating in dual arithmetic.
+// Steps are halved (up to 30 times) until the primitives stay physical and ||G||_inf drops;
+// at ||G||_inf <= tol max(1, ||R_x||_inf) one further Newton step is taken, so the answer sits
+// at round-off whatever the starting point.
+#pragma once
+
+#include "physics.hpp"
+
+namespace rmhd {
+
+template <int N>
+__device__ __forceinline__ double maxabs(const double (&g)[N])
+{
+    double m = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) m = fmax(m, fabs(g[i]));
+    return m;
+}
+
+// A x = b for a small dense A held in registers: Gaussian elimination with partial pivoting
+// (pivot rows are bubbled into place with compile-time indices, so nothing spills to scratch).
+template <int N>
+__device__ __forceinline__ bool dense_solve(double (&A)[N][N], double (&b)[N])
+{
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+#pragma unroll
+        for (int r = k + 1; r < N; ++r) {
+            const bool sw = fabs(A[r][k]) > fabs(A[k][k]);
+#pragma unroll
+            for (int c = k; c < N; ++c) {
+                const double t = A[k][c];
+                A[k][c] = sw ? A[r][c] : t;
+                A[r][c] = sw ? t : A[r][c];
+            }
+            const double t = b[k];
+            b[k] = sw ? b[r] : t;
+            b[r] = sw ? t : b[r];
+        }
+        if (!(A[k][k] != 0.0) || !isfinite(A[k][k])) return false;
+        const double inv = 1.0 / A[k][k];
+#pragma unroll
+        for (int r = k + 1; r < N; ++r) {
+            const double m = A[r][k] * inv;
+#pragma unroll
+            for (int c = k + 1; c < N; ++c) A[r][c] -= m * A[k][c];
+            b[r] -= m * b[k];
+        }
+    }
+#pragma unroll
+    for (int r = N - 1; r >= 0; --r) {
+        double acc = b[r];
+#pragma unroll
+        for (int c = r + 1; c < N; ++c) acc -= A[r][c] * b[c];
+        b[r] = acc / A[r][r];
+    }
+    return true;
+}
+
+// ---------------------------------------------------------------------------------------
+// single fluid
+// ---------------------------------------------------------------------------------------
+struct SFCell {
+    double D, tau, rhoe, B2, a, sig;
+    vec3<double> S, B, RE;
+};
+
+// Hydrodynamic inputs of the recovery at field E: St = S - E x B, Eh = tau - (E^2 + B^2)/2 + D.
+template <class T>
+__device__ __forceinline__ void sf_split(const SFCell &c, const vec3<T> &E, vec3<T> &St, T &s2, T &Eh)
+{
+    const auto ExB = cross(E, c.B);
+    St = v3<T>(c.S.x - ExB.x, c.S.y - ExB.y, c.S.z - ExB.z);
+    s2 = dot(St, St);
+    Eh = c.tau + c.D - 0.5 * (dot(E, E) + c.B2);
+}
+
+template <class T>
+__device__ __forceinline__ void sf_finish(const SFCell &c, const vec3<T> &E, const vec3<T> &St, T z, T (&G)[3])
+{
+    const T iz = recip(z);
+    const vec3<T> v = v3<T>(St.x * iz, St.y * iz, St.z * iz);
+    const T W = recip(dsqrt(1.0 - dot(v, v)));
+    const vec3<T> J = sf_current(v, W, E, c.B, c.rhoe, c.sig);
+    G[0] = E.x - c.RE.x + c.a * J.x;
+    G[1] = E.y - c.RE.y + c.a * J.y;
+    G[2] = E.z - c.RE.z + c.a * J.z;
+}
+
+// Primal residual; solves the recovery from the pressure guess pg. Returns a cell status.
+__device__ __forceinline__ int sf_residual(const SFCell &c, const double (&x)[3], double pg, const Phys &P,
+                                           double (&G)[3], Root &r, double &Eh, int &c2p_it)
+{
+    const vec3<double> E = v3(x[0], x[1], x[2]);
+    vec3<double> St;
+    double s2;
+    sf_split(c, E, St, s2, Eh);
+    r = fluid_root(c.D, s2, Eh, Eh + pg, P);
+    c2p_it += r.iters;
+    if (r.status != CELL_OK) return r.status;
+    sf_finish(c, E, St, r.z, G);
+    if (!isfinite(G[0]) || !isfinite(G[1]) || !isfinite(G[2])) return CELL_C2P_UNPHYS;
+    return CELL_OK;
+}
+
+__device__ __forceinline__ void sf_jacobian(const SFCell &c, const double (&x)[3], const Root &r, const Phys &P,
+                                            double (&A)[3][3])
+{
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const vec3<dual> E = v3(mk(x[0], k == 0), mk(x[1], k == 1), mk(x[2], k == 2));
+        vec3<dual> St;
+        dual s2, Eh;
+        sf_split(c, E, St, s2, Eh);
+        const dual z = root_tangent(r, c.D, s2, Eh, P);
+        dual G[3];
+        sf_finish(c, E, St, z, G);
+        A[0][k] = G[0].d;
+        A[1][k] = G[1].d;
+        A[2][k] = G[2].d;
+    }
+}
+
+// Solve one single-fluid cell.  R: the 14 conserved right-hand-side values; x: start of E on
+// entry, solution on exit; w: pressure guess in w[4] on entry, primitives on exit.
+__device__ inline int sf_stage(const double *R, double a, double sig, const Phys &P, double (&x)[3], double *w,
+                               int &newton_it, int &c2p_it, int &res_it)
+{
+    SFCell c;
+    c.D = R[sf::D];
+    c.tau = R[sf::TAU];
+    c.rhoe = R[sf::RHOE];
+    c.S = v3(R[sf::SX], R[sf::SY], R[sf::SZ]);
+    c.B = v3(R[sf::BX], R[sf::BY], R[sf::BZ]);
+    c.B2 = dot(c.B, c.B);
+    c.RE = v3(R[sf::EX], R[sf::EY], R[sf::EZ]);
+    c.a = a;
+    c.sig = sig;
+    newton_it = 0;
+    double G[3], Eh;
+    Root r;
+    double pg = w[4];
+    res_it = 1;
+    int st = sf_residual(c, x, pg, P, G, r, Eh, c2p_it);
+    if (st == CELL_OK) {
+        const double target = P.newton_tol * fmax(1.0, fmax(fabs(c.RE.x), fmax(fabs(c.RE.y), fabs(c.RE.z))));
+        st = CELL_NEWTON_NOCONV;
+        for (int it = 0; it < P.max_newton; ++it) {
+            const double nrm = maxabs(G);
+            const bool conv = nrm <= target;
+            double A[3][3], dx[3] = {-G[0], -G[1], -G[2]};
+            sf_jacobian(c, x, r, P, A);
+            if (!dense_solve<3>(A, dx)) { st = CELL_LINESEARCH; break; }
+            double lam = 1.0, xt[3], Gt[3], Eht;
+            Root rt;
+            bool ok = false;
+            const double pcur = r.z - Eh;
+            for (int h = 0; h <= 30; ++h) {
+#pragma unroll
+                for (int i = 0; i < 3; ++i) xt[i] = x[i] + lam * dx[i];
+                ++res_it;
+                if (sf_residual(c, xt, pcur, P, Gt, rt, Eht, c2p_it) == CELL_OK && (conv || maxabs(Gt) < nrm)) {
+                    ok = true;
+                    break;
+                }
+                lam *= 0.5;
+            }
+            if (!ok) { st = conv ? CELL_OK : CELL_LINESEARCH; break; }
+#pragma unroll
+            for (int i = 0; i < 3; ++i) { x[i] = xt[i]; G[i] = Gt[i]; }
+            r = rt;
+            Eh = Eht;
+            newton_it = it + 1;
+            if (conv) { st = CELL_OK; break; }
+        }
+    }
+    // primitives at the final point
+    const vec3<double> E = v3(x[0], x[1], x[2]);
+    vec3<double> St;
+    double s2;
+    sf_split(c, E, St, s2, Eh);
+    const double iz = 1.0 / r.z;
+    w[0] = c.D * r.iW;
+    w[1] = St.x * iz; w[2] = St.y * iz; w[3] = St.z * iz;
+    w[4] = r.z - Eh;
+    return st;
+}
+
+// ---------------------------------------------------------------------------------------
+// two fluid
+// ---------------------------------------------------------------------------------------
+struct TFCell {
+    double D, tau, B2, a, eta, sc, Ds[2], rhoe;
+    vec3<double> S, B, RSb, RE;
+    double Rtb;
+};
+
+// Species recovery inputs at unknowns x (Sec. 2.1.3, Eqs. 7-8).
+template <class T>
+__device__ __forceinline__ void tf_split(const TFCell &c, const T (&x)[7], const Phys &P, vec3<T> (&Ss)[2],
+                                         T (&s2)[2], T (&Eh)[2])
+{
+    const vec3<T> E = v3<T>(x[4], x[5], x[6]);
+    const vec3<T> Sb = v3<T>(x[0] * c.sc, x[1] * c.sc, x[2] * c.sc);
+    const T tb = x[3] * c.sc;
+    const auto ExB = cross(E, c.B);
+    const vec3<T> St = v3<T>(c.S.x - ExB.x, c.S.y - ExB.y, c.S.z - ExB.z);
+    const T tt = c.tau - 0.5 * (dot(E, E) + c.B2);
+    const double i12 = 1.0 / (P.mu1 - P.mu2);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const double m = s == 0 ? P.mu2 : P.mu1, sg = s == 0 ? i12 : -i12;
+        Ss[s] = v3<T>((Sb.x - m * St.x) * sg, (Sb.y - m * St.y) * sg, (Sb.z - m * St.z) * sg);
+        s2[s] = dot(Ss[s], Ss[s]);
+        Eh[s] = (tb - m * tt) * sg + c.Ds[s];
+    }
+}
+
+template <class T>
+__device__ __forceinline__ void tf_finish(const TFCell &c, const T (&x)[7], const vec3<T> (&Ss)[2], const T (&z)[2],
+                                          const Phys &P, T (&G)[7])
+{
+    T Dw[2], rho[2];
+    vec3<T> v[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const T iz = recip(z[s]);
+        v[s] = v3<T>(Ss[s].x * iz, Ss[s].y * iz, Ss[s].z * iz);
+        rho[s] = c.Ds[s] * dsqrt(1.0 - dot(v[s], v[s]));
+        Dw[s] = lift<T>(c.Ds[s]);  // rho_s W_s = D_s, fixed during the stage
+    }
+    const vec3<T> E = v3<T>(x[4], x[5], x[6]);
+    const TFSource<T> src = tf_source_terms<T>(Dw, rho, v, E, c.B, c.eta, P);
+    const double isc = 1.0 / c.sc;
+    G[0] = x[0] - (c.RSb.x + c.a * src.Sb.x) * isc;
+    G[1] = x[1] - (c.RSb.y + c.a * src.Sb.y) * isc;
+    G[2] = x[2] - (c.RSb.z + c.a * src.Sb.z) * isc;
+    G[3] = x[3] - (c.Rtb + c.a * src.taub) * isc;
+    G[4] = x[4] - c.RE.x + c.a * src.J.x;
+    G[5] = x[5] - c.RE.y + c.a * src.J.y;
+    G[6] = x[6] - c.RE.z + c.a * src.J.z;
+}
+
+__device__ __forceinline__ int tf_residual(const TFCell &c, const double (&x)[7], const double (&pg)[2],
+                                           const Phys &P, double (&G)[7], Root (&r)[2], double (&Eh)[2],
+                                           int &c2p_it)
+{
+    vec3<double> Ss[2];
+    double s2[2];
+    tf_split(c, x, P, Ss, s2, Eh);
+    double z[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        r[s] = fluid_root(c.Ds[s], s2[s], Eh[s], Eh[s] + pg[s], P);
+        c2p_it += r[s].iters;
+        if (r[s].status != CELL_OK) return r[s].status;
+        z[s] = r[s].z;
+    }
+    tf_finish(c, x, Ss, z, P, G);
+#pragma unroll
+    for (int i = 0; i < 7; ++i)
+        if (!isfinite(G[i])) return CELL_C2P_UNPHYS;
+    return CELL_OK;
+}
+
+__device__ __forceinline__ void tf_jacobian(const TFCell &c, const double (&x)[7], const Root (&r)[2], const Phys &P,
+                                            double (&A)[7][7])
+{
+#pragma unroll 1
+    for (int k = 0; k < 7; ++k) {
+        dual xd[7];
+#pragma unroll
+        for (int i = 0; i < 7; ++i) xd[i] = mk(x[i], i == k ? 1.0 : 0.0);
+        vec3<dual> Ss[2];
+        dual s2[2], Eh[2], z[2], G[7];
+        tf_split(c, xd, P, Ss, s2, Eh);
+#pragma unroll
+        for (int s = 0; s < 2; ++s) z[s] = root_tangent(r[s], c.Ds[s], s2[s], Eh[s], P);
+        tf_finish(c, xd, Ss, z, P, G);
+#pragma unroll
+        for (int i = 0; i < 7; ++i) {
+            // column k, selected without dynamic register indexing
+#pragma unroll
+            for (int kk = 0; kk < 7; ++kk)
+                if (kk == k) A[i][kk] = G[i].d;
+        }
+    }
+}
+
+// Solve one two-fluid cell.  x: start (scaled unknowns) on entry, solution on exit;
+// w: pressure guesses w[4], w[9] on entry, primitives on exit.
+__device__ inline int tf_stage(const double *R, double a, double sig, const Phys &P, double (&x)[7], double *w,
+                               int &newton_it, int &c2p_it, int &res_it)
+{
+    TFCell c;
+    c.D = R[tf::D];
+    c.tau = R[tf::TAU];
+    c.S = v3(R[tf::SX], R[tf::SY], R[tf::SZ]);
+    c.B = v3(R[tf::BX], R[tf::BY], R[tf::BZ]);
+    c.B2 = dot(c.B, c.B);
+    c.RSb = v3(R[tf::SBX], R[tf::SBY], R[tf::SBZ]);
+    c.Rtb = R[tf::TAUB];
+    c.RE = v3(R[tf::EX], R[tf::EY], R[tf::EZ]);
+    c.a = a;
+    c.eta = 1.0 / sig;
+    c.sc = fabs(P.mu1);
+    const double i12 = 1.0 / (P.mu1 - P.mu2);
+    c.Ds[0] = (R[tf::DB] - P.mu2 * c.D) * i12;
+    c.Ds[1] = -(R[tf::DB] - P.mu1 * c.D) * i12;
+    c.rhoe = R[tf::DB];
+    newton_it = 0;
+    double G[7], Eh[2];
+    Root r[2];
+    double pg[2] = {w[4], w[9]};
+    res_it = 1;
+    int st = tf_residual(c, x, pg, P, G, r, Eh, c2p_it);
+    if (st == CELL_OK) {
+        double rx = 0.0;
+        rx = fmax(rx, fabs(c.RSb.x / c.sc)); rx = fmax(rx, fabs(c.RSb.y / c.sc)); rx = fmax(rx, fabs(c.RSb.z / c.sc));
+        rx = fmax(rx, fabs(c.Rtb / c.sc));
+        rx = fmax(rx, fabs(c.RE.x)); rx = fmax(rx, fabs(c.RE.y)); rx = fmax(rx, fabs(c.RE.z));
+        const double target = P.newton_tol * fmax(1.0, rx);
+        st = CELL_NEWTON_NOCONV;
+        for (int it = 0; it < P.max_newton; ++it) {
+            const double nrm = maxabs(G);
+            const bool conv = nrm <= target;
+            double A[7][7], dx[7];
+#pragma unroll
+            for (int i = 0; i < 7; ++i) dx[i] = -G[i];
+            tf_jacobian(c, x, r, P, A);
+            if (!dense_solve<7>(A, dx)) { st = CELL_LINESEARCH; break; }
+            double lam = 1.0, xt[7], Gt[7], Eht[2];
+            Root rt[2];
+            bool ok = false;
+            const double pcur[2] = {r[0].z - Eh[0], r[1].z - Eh[1]};
+            for (int h = 0; h <= 30; ++h) {
+#pragma unroll
+                for (int i = 0; i < 7; ++i) xt[i] = x[i] + lam * dx[i];
+                ++res_it;
+                if (tf_residual(c, xt, pcur, P, Gt, rt, Eht, c2p_it) == CELL_OK && (conv || maxabs(Gt) < nrm)) {
+                    ok = true;
+                    break;
+                }
+                lam *= 0.5;
+            }
+            if (!ok) { st = conv ? CELL_OK : CELL_LINESEARCH; break; }
+#pragma unroll
+            for (int i = 0; i < 7; ++i) { x[i] = xt[i]; G[i] = Gt[i]; }
+            r[0] = rt[0]; r[1] = rt[1];
+            Eh[0] = Eht[0]; Eh[1] = Eht[1];
+            newton_it = it + 1;
+            if (conv) { st = CELL_OK; break; }
+        }
+    }
+    vec3<double> Ss[2];
+    double s2[2];
+    tf_split(c, x, P, Ss, s2, Eh);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const double iz = 1.0 / r[s].z;
+        double *ws = w + 5 * s;
+        ws[0] = c.Ds[s] * r[s].iW;
+        ws[1] = Ss[s].x * iz; ws[2] = Ss[s].y * iz; ws[3] = Ss[s].z * iz;
+        ws[4] = r[s].z - Eh[s];
+    }
+    return st;
+}
+
+}  // namespace rmhd

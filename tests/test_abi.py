@@ -1,0 +1,67 @@
+"""Host-side checks of the C ABI: librmhd.so loads, exports every function declared in
+include/rmhd.h, and validates parameters (no GPU work is issued)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1808_09721_amd import rmhd as R
+from paper_1808_09721_amd import workloads as WL
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "rmhd.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rmhd_\w+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(R.LIB_PATH):
+        pytest.skip("librmhd.so not built")
+    names = declared_functions()
+    assert names, "no declarations found"
+    lib = ctypes.CDLL(R.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sorted(R.EXPORTS) == names
+
+
+def test_layout_of_pads_rows_and_counts_variables():
+    p = R.params_from(WL.kelvin_helmholtz_2d(10, 7, steps=1))
+    L = R.rmhd_layout_of(p)
+    assert (L.nxg, L.nyg) == (14, 11)
+    assert L.pitch == 16 and L.plane == 16 * 11
+    assert (L.ncons, L.nprim) == (14, 5)
+    p = R.params_from(WL.two_fluid_sheet_2d(12, 8, steps=1))
+    L = R.rmhd_layout_of(p)
+    assert (L.pitch, L.nyg, L.ncons, L.nprim) == (16, 12, 18, 10)
+    p = R.params_from(WL.brio_wu_1d(400))
+    L = R.rmhd_layout_of(p)
+    assert (L.nxg, L.nyg, L.pitch, L.plane) == (404, 1, 408, 408)
+
+
+@pytest.mark.parametrize("field,value,msg", [("nx", 2, "nx >= 4"), ("model", 5, "model"), ("gamma_eos", 2.5, "gamma"),
+                                             ("bc", 3, "bc"), ("max_newton_iter", 0, "iteration")])
+def test_layout_of_rejects_bad_parameters(field, value, msg):
+    p = R.params_from(WL.kelvin_helmholtz_2d(16, 16, steps=1))
+    setattr(p, field, value)
+    with pytest.raises(R.RmhdError, match=msg):
+        R.rmhd_layout_of(p)
+
+
+def test_two_fluid_needs_distinct_charge_to_mass_ratios():
+    wl = WL.two_fluid_sheet_2d(16, 16, steps=1)
+    p = R.params_from(wl)
+    p.mu2 = p.mu1
+    with pytest.raises(R.RmhdError, match="mu1 != mu2"):
+        R.rmhd_layout_of(p)
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(R, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(R, "_lib", None)
+    with pytest.raises(R.RmhdError, match="missing"):
+        R.lib()

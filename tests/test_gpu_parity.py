@@ -1,0 +1,321 @@
+"""GPU (HIP, through the C ABI) against the CPU oracle, element by element.
+
+Tolerances: straight-line maps (prim -> cons) to 1e-14; root-finds and fluxes to 1e-12
+(both sides iterate to round-off); full SSP2(222) runs to 1e-9 relative L-infinity after
+100 steps.  Relative L-infinity per variable v is max|gpu - oracle| / max(||oracle_v||_inf,
+1e-8 max_v ||oracle_v||_inf), maximised over variables.
+"""
+import numpy as np
+import pytest
+
+from paper_1808_09721_amd import workloads as WL
+from tests.oracle_runs import advance, grid_of, initial_state
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1808_09721_amd import rmhd
+    rmhd.lib()
+    return rmhd
+
+
+@pytest.fixture(scope="module")
+def O(oracle_lib):
+    return oracle_lib
+
+
+def banner(msg):
+    print(f"\n[gpu-case] {msg}", flush=True)
+
+
+def rel_linf(gpu, ref):
+    """Per-variable relative L-infinity error (arrays shaped [var, ...])."""
+    g = gpu.reshape(gpu.shape[0], -1)
+    o = ref.reshape(ref.shape[0], -1)
+    scale = np.abs(o).max(axis=1)
+    den = np.maximum(scale, 1e-8 * scale.max())
+    den = np.where(den > 0, den, 1.0)
+    return np.abs(g - o).max(axis=1) / den
+
+
+def gpu_solver(R, wl, **kw):
+    sigma_cell = None
+    if wl.sigma_cell is not None:
+        import torch
+        params = R.params_from(wl)
+        grid = R.Grid(params)
+        sc = grid.alloc(1)
+        full = np.zeros((1, grid.layout.nyg, grid.layout.nxg))
+        og = grid_of(wl)
+        full[0] = og.sigma_cell
+        grid.all_view(sc)[...] = torch.from_numpy(full).cuda()
+        sigma_cell = sc
+    s = R.Solver(R.params_from(wl, sigma_cell=sigma_cell, **kw))
+    s._sigma_cell = sigma_cell
+    return s
+
+
+def upload_all(R, grid, arr):
+    import torch
+    t = grid.alloc(arr.shape[0], fill=float("nan"))
+    grid.all_view(t)[...] = torch.from_numpy(np.ascontiguousarray(arr)).cuda()
+    return t
+
+
+# ------------------------------------------------------------------------------------------
+# per-kernel parity
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("case", ["brio_wu", "khi", "sheet"])
+def test_init_and_cons2prim_match_oracle(R, O, case):
+    banner(f"init/cons2prim {case}")
+    wl = {"brio_wu": WL.brio_wu_1d(), "khi": WL.kelvin_helmholtz_2d(70, 37, steps=1),
+          "sheet": WL.two_fluid_sheet_2d(70, 37, steps=1)}[case]
+    s = gpu_solver(R, wl)
+    cons, prims = s.initial_state(wl.prims, wl.EB)
+    g, ocons, oprims = initial_state(wl)
+    gc = s.grid.download_all(cons)
+    gp = s.grid.download_all(prims)
+    assert np.all(rel_linf(gc, ocons) < 1e-14)
+    assert np.all(rel_linf(gp, oprims) < 1e-12)
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_cons2prim_random_states(R, O, model):
+    banner(f"cons2prim random states model={model}")
+    import torch
+    n = 4000
+    if model == 0:
+        og = O.Grid(model=0, ndim=1, nx=n, ny=1, dx=1.0 / n, dy=1.0, gamma=4.0 / 3.0, sigma=1.0, bc=0)
+        prims, EB = WL.random_states(n, 0, seed=201, w_max=10.0, field_max=1.0, log_rho=(-1, 1),
+                                     log_p_over_rho=(-1, 3))
+    else:
+        og = O.Grid(model=1, ndim=1, nx=n, ny=1, dx=1.0 / n, dy=1.0, gamma=4.0 / 3.0, sigma=1.0, bc=0,
+                    mu1=1000.0, mu2=-1000.0)
+        prims, EB = WL.random_states(n, 1, seed=202, w_max=3.0, field_max=1.0, log_rho=(-0.3, 0.3),
+                                     log_p_over_rho=(-1, 1))
+    q = np.stack([O.prim2cons_cell(og, prims[k], EB[k]) for k in range(n)], axis=1)
+    wl = WL.brio_wu_1d(n) if model == 0 else WL.two_fluid_sheet_2d(8, 8, steps=1)
+    if model == 1:
+        wl = WL.Workload("rand", 1, 1, n, 1, 0.0, 1.0, 0.0, 1.0, gamma=4.0 / 3.0, sigma=1.0, bc=0, mu1=1000.0,
+                         mu2=-1000.0)
+    wl.gamma = 4.0 / 3.0
+    s = gpu_solver(R, wl)
+    full_q = np.zeros((og.ncons, 1, n + 4))
+    full_q[:, 0, 2:-2] = q
+    full_q[:, 0, :2] = q[:, :1]
+    full_q[:, 0, -2:] = q[:, -1:]
+    cons = upload_all(R, s.grid, full_q)
+    pr = s.grid.alloc(og.nprim, fill=-1.0)
+    status = torch.zeros((1, s.grid.layout.nyg, s.grid.layout.pitch), dtype=torch.int8, device="cuda")
+    R.rmhd_cons2prim(s.ctx, cons, pr, status)
+    torch.cuda.synchronize()
+    w = s.grid.download_interior(pr)[:, 0]
+    assert int(s.grid.interior_view(status).abs().max()) == 0
+    for sp in range(og.nprim // 5):
+        b = 5 * sp
+        np.testing.assert_allclose(w[b], prims[:, b], rtol=1e-12)
+        np.testing.assert_allclose(w[b + 4], prims[:, b + 4], rtol=1e-12)
+        np.testing.assert_allclose(w[b + 1:b + 4], prims[:, b + 1:b + 4].T, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("case", ["brio_wu", "khi", "sheet"])
+def test_flux_divergence_matches_oracle(R, O, case):
+    banner(f"F(U) {case}")
+    wl = {"brio_wu": WL.brio_wu_1d(), "khi": WL.kelvin_helmholtz_2d(70, 37, steps=1),
+          "sheet": WL.two_fluid_sheet_2d(70, 37, steps=1)}[case]
+    g, ocons, oprims = initial_state(wl)
+    advance(g, ocons, oprims, O.dt(g, 0.5), steps=3)   # a state with structure in every field
+    L_ref = O.rhs(g, ocons, oprims)
+    s = gpu_solver(R, wl)
+    cons = upload_all(R, s.grid, ocons)
+    prims = upload_all(R, s.grid, oprims)
+    Lg = s.grid.alloc(g.ncons, fill=float("nan"))
+    R.rmhd_F(s.ctx, cons, prims, Lg)
+    err = rel_linf(s.grid.download_interior(Lg), g.interior(L_ref))
+    assert np.all(err < 1e-12), err
+
+
+@pytest.mark.parametrize("case,scale", [("brio_wu", 1.0), ("khi", 1.0), ("khi", 30.0), ("sheet", 1.0),
+                                        ("sheet", 10.0)])
+def test_implicit_stage_matches_oracle(R, O, case, scale):
+    banner(f"implicit stage {case} a-scale={scale}")
+    import torch
+    wl = {"brio_wu": WL.brio_wu_1d(), "khi": WL.kelvin_helmholtz_2d(70, 37, steps=1),
+          "sheet": WL.two_fluid_sheet_2d(70, 37, steps=1)}[case]
+    g, ocons, oprims = initial_state(wl)
+    advance(g, ocons, oprims, O.dt(g, 0.5), steps=3)
+    a = (1 - 1 / np.sqrt(2)) * O.dt(g, 0.5) * scale
+    Qo, wo, sto, _ = O.implicit(g, a, ocons, oprims)
+    assert (g.interior(sto) == 0).all()
+    s = gpu_solver(R, wl)
+    Rg = upload_all(R, s.grid, ocons)
+    prims = upload_all(R, s.grid, oprims)
+    Qg = s.grid.alloc(g.ncons, fill=float("nan"))
+    status = torch.full((1, s.grid.layout.nyg, s.grid.layout.pitch), 9, dtype=torch.int8, device="cuda")
+    R.rmhd_implicit_stage(s.ctx, a, Rg, None, Qg, prims, status, None)
+    torch.cuda.synchronize()
+    assert int(s.grid.all_view(status).abs().max()) == 0
+    Qgpu = s.grid.download_all(Qg)
+    assert np.all(rel_linf(g.interior(Qgpu), g.interior(Qo)) < 1e-12)
+    assert np.all(rel_linf(g.interior(s.grid.download_all(prims)), g.interior(wo)) < 1e-12)
+    # the oracle's own residual at the GPU's solution, cell by cell
+    Rc = g.interior(ocons).reshape(g.ncons, -1)
+    Qc = g.interior(Qgpu).reshape(g.ncons, -1)
+    for k in range(0, Rc.shape[1], max(1, Rc.shape[1] // 300)):
+        G, st = O.implicit_residual_cell(g, a, Rc[:, k], Qc[:, k])
+        assert st == 0 and np.max(np.abs(G)) <= 1e-12 * max(1.0, np.max(np.abs(Qc[:, k])))
+
+
+def test_implicit_stage_start_independent(R, O):
+    """A different starting point (the stage-free state) reaches the same root."""
+    banner("implicit stage start independence")
+    import torch
+    wl = WL.kelvin_helmholtz_2d(70, 37, steps=1)
+    g, ocons, oprims = initial_state(wl)
+    advance(g, ocons, oprims, O.dt(g, 0.5), steps=3)
+    a = 5.0 * O.dt(g, 0.5)
+    s = gpu_solver(R, wl)
+    Rg = upload_all(R, s.grid, ocons)
+    guess = Rg.clone()
+    guess[8:11] *= 0.5
+    Q1 = s.grid.alloc(g.ncons)
+    Q2 = s.grid.alloc(g.ncons)
+    p1 = upload_all(R, s.grid, oprims)
+    p2 = upload_all(R, s.grid, oprims)
+    R.rmhd_implicit_stage(s.ctx, a, Rg, None, Q1, p1)
+    R.rmhd_implicit_stage(s.ctx, a, Rg, guess, Q2, p2)
+    torch.cuda.synchronize()
+    assert np.all(rel_linf(s.grid.download_interior(Q2), s.grid.download_interior(Q1)) < 1e-13)
+
+
+# ------------------------------------------------------------------------------------------
+# full SSP2(222) runs
+# ------------------------------------------------------------------------------------------
+def run_both(R, O, wl, steps, t_end=None):
+    g, ocons, oprims = initial_state(wl)
+    dt = O.dt(g, wl.cfl)
+    advance(g, ocons, oprims, dt, steps=steps, t_end=t_end)
+    s = gpu_solver(R, wl)
+    cons, prims = s.initial_state(wl.prims, wl.EB)
+    assert abs(s.dt() - dt) <= 1e-16 * dt
+    t, n = 0.0, 0
+    while (steps is None or n < steps) and (t_end is None or t < t_end - 1e-12):
+        h = dt if t_end is None else min(dt, t_end - t)
+        s.step(h, cons, prims)
+        t += h
+        n += 1
+    st = s.stats()
+    return g, ocons, oprims, s.grid.download_all(cons), s.grid.download_all(prims), st
+
+
+@pytest.mark.parametrize("steps,t_end", [(100, None), (None, 0.4)])
+def test_brio_wu_steps_match_oracle(R, O, steps, t_end):
+    banner(f"Brio-Wu 400 cells steps={steps} t_end={t_end}")
+    wl = WL.brio_wu_1d()
+    g, oc, op, gc, gp, st = run_both(R, O, wl, steps, t_end)
+    assert st["failures"] == 0
+    assert np.all(rel_linf(g.interior(gc), g.interior(oc)) < 1e-9)
+    assert np.all(rel_linf(g.interior(gp), g.interior(op)) < 1e-9)
+
+
+def test_khi_small_ragged_tiles_100_steps(R, O):
+    banner("KHI 70x37 (ragged tiles) 100 steps")
+    wl = WL.kelvin_helmholtz_2d(70, 37, steps=100, seed=12)
+    g, oc, op, gc, gp, st = run_both(R, O, wl, 100)
+    assert st["failures"] == 0
+    assert np.all(rel_linf(gc, oc) < 1e-9)     # ghosts included
+    assert np.all(rel_linf(gp, op) < 1e-9)
+
+
+def test_khi_full_size_100_steps(R, O):
+    """Kelvin-Helmholtz at 256 x 512, sigma = 1e3, 100 steps: the benchmark workload."""
+    banner("KHI 256x512 100 steps")
+    wl = WL.kelvin_helmholtz_2d()
+    g, oc, op, gc, gp, st = run_both(R, O, wl, 100)
+    assert st["failures"] == 0 and st["stage_cells"] == 2 * 100 * wl.cells
+    err = rel_linf(g.interior(gc), g.interior(oc))
+    print("rel Linf per variable", err)
+    assert np.all(err < 1e-9)
+
+
+def test_two_fluid_sheet_128_100_steps(R, O):
+    banner("two-fluid sheet 128x128 100 steps")
+    wl = WL.two_fluid_sheet_2d(128, 128, steps=100)
+    g, oc, op, gc, gp, st = run_both(R, O, wl, 100)
+    assert st["failures"] == 0
+    err = rel_linf(g.interior(gc), g.interior(oc))
+    print("rel Linf per variable", err)
+    assert np.all(err < 1e-9)
+    assert np.all(rel_linf(g.interior(gp), g.interior(op)) < 1e-9)
+
+
+def test_two_fluid_sheet_full_size_properties(R, O):
+    """512 x 512 two-fluid sheet: the stage solution at sampled cells matches the oracle's
+    per-cell solve, and 100 steps conserve D, S, tau, Dbar and B to round-off."""
+    banner("two-fluid sheet 512x512")
+    import torch
+    wl = WL.two_fluid_sheet_2d()
+    s = gpu_solver(R, wl)
+    cons, prims = s.initial_state(wl.prims, wl.EB)
+    g = grid_of(wl)
+    a = (1 - 1 / np.sqrt(2)) * s.dt()
+    Q = s.grid.alloc(g.ncons)
+    p = prims.clone()
+    R.rmhd_implicit_stage(s.ctx, a, cons, None, Q, p)
+    torch.cuda.synchronize()
+    Rh = g.interior(s.grid.download_all(cons)).reshape(g.ncons, -1)
+    Qh = g.interior(s.grid.download_all(Q)).reshape(g.ncons, -1)
+    rng = np.random.default_rng(5)
+    for k in rng.choice(Rh.shape[1], 400, replace=False):
+        Qo, _, st, _ = O.implicit_cell(g, a, Rh[:, k])
+        assert st == 0
+        np.testing.assert_allclose(Qh[:, k], Qo, rtol=1e-12, atol=1e-12 * np.abs(Qo).max())
+    tot0 = g.interior(s.grid.download_all(cons)).sum(axis=(1, 2))
+    scale = np.abs(g.interior(s.grid.download_all(cons))).sum(axis=(1, 2))
+    s.stats(reset=True)
+    for _ in range(100):
+        s.step(s.dt(), cons, prims)
+    st = s.stats()
+    assert st["failures"] == 0 and st["stage_cells"] == 2 * 100 * wl.cells
+    tot = g.interior(s.grid.download_all(cons)).sum(axis=(1, 2))
+    for v in (0, 1, 2, 3, 4, 5, 10, 11, 12):
+        assert abs(tot[v] - tot0[v]) <= 1e-13 * scale[v] + 1e-300
+
+
+def test_periodic_conservation_khi_full(R, O):
+    banner("KHI 256x512 conservation")
+    wl = WL.kelvin_helmholtz_2d()
+    s = gpu_solver(R, wl)
+    cons, prims = s.initial_state(wl.prims, wl.EB)
+    g = grid_of(wl)
+    c0 = g.interior(s.grid.download_all(cons))
+    for _ in range(100):
+        s.step(s.dt(), cons, prims)
+    c1 = g.interior(s.grid.download_all(cons))
+    scale = np.abs(c0).sum(axis=(1, 2))
+    for v in (0, 1, 2, 3, 4, 5, 6, 7, 11):
+        assert abs(c1[v].sum() - c0[v].sum()) <= 1e-13 * scale[v] + 1e-300, v
+
+
+def test_padding_is_never_read(R, O):
+    """NaN in the row padding of every input leaves every output finite and unchanged."""
+    banner("NaN padding")
+    import torch
+    wl = WL.kelvin_helmholtz_2d(70, 37, steps=1)
+    s = gpu_solver(R, wl)
+    cons, prims = s.initial_state(wl.prims, wl.EB)
+    c2, p2 = cons.clone(), prims.clone()
+    nxg = s.grid.layout.nxg
+    c2[..., nxg:] = float("nan")
+    p2[..., nxg:] = float("nan")
+    for _ in range(3):
+        s.step(s.dt(), cons, prims)
+        s.step(s.dt(), c2, p2)
+    torch.cuda.synchronize()
+    a, b = s.grid.download_all(cons), s.grid.download_all(c2)
+    assert np.all(np.isfinite(b))
+    np.testing.assert_array_equal(a, b)
