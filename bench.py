@@ -51,6 +51,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--timing-steps", type=int, default=20)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (traffic calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures a single GPU; --gpus {args.gpus} is not supported "
@@ -89,6 +91,14 @@ def main() -> int:
     value = cells * args.steps / (ms / 1e3)
 
     # per-kernel pass: HIP events around every launch on the same stream
+    if args.copy_mib:
+        src = torch.empty(args.copy_mib << 17, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    args.timing_steps = max(1, args.timing_steps)
     R.rmhd_set_timing(solver.ctx, True)
     R.rmhd_get_timing(solver.ctx, reset=True)
     for _ in range(args.timing_steps):

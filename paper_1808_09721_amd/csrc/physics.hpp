@@ -45,6 +45,30 @@ __device__ __forceinline__ double cell_sigma(const Phys &P, long idx)
 }
 
 // ---------------------------------------------------------------------------------------
+// reciprocal and reciprocal square root: the hardware estimate (v_rcp_f64 / v_rsq_f64)
+// refined by two Newton-Raphson steps in FMA form, accurate to about one ulp for the normal,
+// finite, positive arguments used here (instead of the IEEE-exact division and square-root
+// sequences with their scaling and fix-up instructions)
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ double frcp(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-d, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ double frsqrt(double x)
+{
+    double r = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    double e = fma(-h * r, r, 0.5);
+    r = fma(r, e, r);
+    e = fma(-h * r, r, 0.5);
+    return fma(r, e, r);
+}
+
+// ---------------------------------------------------------------------------------------
 // forward-mode dual number (one tangent) for the exact stage Jacobian
 // ---------------------------------------------------------------------------------------
 struct dual {
@@ -63,7 +87,7 @@ __device__ __forceinline__ dual operator*(dual a, double b) { return {a.v * b, a
 __device__ __forceinline__ dual operator*(double b, dual a) { return {a.v * b, a.d * b}; }
 __device__ __forceinline__ dual recip(dual a)
 {
-    const double r = 1.0 / a.v;
+    const double r = frcp(a.v);
     return {r, -a.d * r * r};
 }
 __device__ __forceinline__ dual dsqrt(dual a)
@@ -71,13 +95,56 @@ __device__ __forceinline__ dual dsqrt(dual a)
     const double s = sqrt(a.v);
     return {s, 0.5 * a.d / s};
 }
+// three tangents at once: one forward pass yields a whole 3x3 Jacobian
+struct dual3 {
+    double v, d0, d1, d2;
+};
+__device__ __forceinline__ dual3 operator+(dual3 a, dual3 b) { return {a.v + b.v, a.d0 + b.d0, a.d1 + b.d1, a.d2 + b.d2}; }
+__device__ __forceinline__ dual3 operator-(dual3 a, dual3 b) { return {a.v - b.v, a.d0 - b.d0, a.d1 - b.d1, a.d2 - b.d2}; }
+__device__ __forceinline__ dual3 operator-(dual3 a) { return {-a.v, -a.d0, -a.d1, -a.d2}; }
+__device__ __forceinline__ dual3 operator*(dual3 a, dual3 b)
+{
+    return {a.v * b.v, a.v * b.d0 + a.d0 * b.v, a.v * b.d1 + a.d1 * b.v, a.v * b.d2 + a.d2 * b.v};
+}
+__device__ __forceinline__ dual3 operator+(dual3 a, double b) { return {a.v + b, a.d0, a.d1, a.d2}; }
+__device__ __forceinline__ dual3 operator+(double b, dual3 a) { return {a.v + b, a.d0, a.d1, a.d2}; }
+__device__ __forceinline__ dual3 operator-(dual3 a, double b) { return {a.v - b, a.d0, a.d1, a.d2}; }
+__device__ __forceinline__ dual3 operator-(double b, dual3 a) { return {b - a.v, -a.d0, -a.d1, -a.d2}; }
+__device__ __forceinline__ dual3 operator*(dual3 a, double b) { return {a.v * b, a.d0 * b, a.d1 * b, a.d2 * b}; }
+__device__ __forceinline__ dual3 operator*(double b, dual3 a) { return {a.v * b, a.d0 * b, a.d1 * b, a.d2 * b}; }
+__device__ __forceinline__ dual3 recip(dual3 a)
+{
+    const double r = frcp(a.v), m = -r * r;
+    return {r, a.d0 * m, a.d1 * m, a.d2 * m};
+}
+__device__ __forceinline__ dual3 dsqrt(dual3 a)
+{
+    const double s = sqrt(a.v), h = 0.5 / s;
+    return {s, a.d0 * h, a.d1 * h, a.d2 * h};
+}
+
+// 1/sqrt for scalars and duals
+__device__ __forceinline__ double rsqrt_t(double a) { return frsqrt(a); }
+__device__ __forceinline__ dual rsqrt_t(dual a)
+{
+    const double r = frsqrt(a.v);
+    return {r, -0.5 * a.d * r * r * r};
+}
+__device__ __forceinline__ dual3 rsqrt_t(dual3 a)
+{
+    const double r = frsqrt(a.v), m = -0.5 * r * r * r;
+    return {r, a.d0 * m, a.d1 * m, a.d2 * m};
+}
+
 template <class T>
 __device__ __forceinline__ T lift(double v);
 template <>
 __device__ __forceinline__ double lift<double>(double v) { return v; }
 template <>
 __device__ __forceinline__ dual lift<dual>(double v) { return dual{v, 0.0}; }
-__device__ __forceinline__ double recip(double a) { return 1.0 / a; }
+template <>
+__device__ __forceinline__ dual3 lift<dual3>(double v) { return dual3{v, 0.0, 0.0, 0.0}; }
+__device__ __forceinline__ double recip(double a) { return frcp(a); }
 __device__ __forceinline__ double dsqrt(double a) { return sqrt(a); }
 __device__ __forceinline__ double value(double a) { return a; }
 __device__ __forceinline__ double value(dual a) { return a.v; }
@@ -128,14 +195,16 @@ __device__ __forceinline__ Root fluid_root(double D, double s2, double Eh, doubl
     double z = (zguess > lo && zguess < hi) ? zguess : 0.5 * (lo + hi);
     r.status = CELL_C2P_NOCONV;
     for (int it = 1; it <= P.max_c2p; ++it) {
-        const double iz = 1.0 / z;
+        const double iz = frcp(z);
         const double v2 = s2 * iz * iz;
-        const double iW = sqrt(1.0 - v2);
-        const double p = P.gk * (z * (1.0 - v2) - D * iW);
+        const double u = 1.0 - v2;
+        const double W = frsqrt(u);
+        const double iW = u * W;
+        const double p = P.gk * (z * u - D * iW);
         const double g = z - Eh - p;
-        const double dg = 1.0 - P.gk * (1.0 + v2 - D * v2 * iz / iW);
+        const double dg = 1.0 - P.gk * (1.0 + v2 - D * v2 * iz * W);
         if (g < 0.0) lo = z; else hi = z;
-        double zn = z - g / dg;
+        double zn = z - g * frcp(dg);
         if (fabs(g) <= P.c2p_tol * fmax(1.0, p)) {
             if (zn > s && zn >= Eh) z = zn;
             r.status = CELL_OK;
@@ -147,8 +216,9 @@ __device__ __forceinline__ Root fluid_root(double D, double s2, double Eh, doubl
         r.iters = it;
     }
     r.z = z;
-    const double iz = 1.0 / z;
-    r.iW = sqrt(1.0 - s2 * iz * iz);
+    const double iz = frcp(z);
+    const double u = 1.0 - s2 * iz * iz;
+    r.iW = u * frsqrt(u);
     if (r.status == CELL_OK && !(r.iW > 0.0)) r.status = CELL_C2P_UNPHYS;
     return r;
 }
@@ -157,11 +227,20 @@ __device__ __forceinline__ Root fluid_root(double D, double s2, double Eh, doubl
 // dg = dg/ds2 ds2 + dg/dEh dEh, and dz = -(dg/ds2 ds2 + dg/dEh dEh) / (dg/dz).
 __device__ __forceinline__ dual root_tangent(const Root &r, double D, dual s2, dual Eh, const Phys &P)
 {
-    const double z = r.z, iz = 1.0 / z, iW = r.iW;
+    const double z = r.z, iz = frcp(z), W = frcp(r.iW);
     const double v2 = s2.v * iz * iz;
-    const double dgdz = 1.0 - P.gk * (1.0 + v2 - D * v2 * iz / iW);
-    const double dgds2 = P.gk * (iz - 0.5 * D * iz * iz / iW);
-    return dual{z, (Eh.d - dgds2 * s2.d) / dgdz};
+    const double idgdz = frcp(1.0 - P.gk * (1.0 + v2 - D * v2 * iz * W));
+    const double dgds2 = P.gk * (iz - 0.5 * D * iz * iz * W);
+    return dual{z, (Eh.d - dgds2 * s2.d) * idgdz};
+}
+__device__ __forceinline__ dual3 root_tangent(const Root &r, double D, dual3 s2, dual3 Eh, const Phys &P)
+{
+    const double z = r.z, iz = frcp(z), W = frcp(r.iW);
+    const double v2 = s2.v * iz * iz;
+    const double idgdz = frcp(1.0 - P.gk * (1.0 + v2 - D * v2 * iz * W));
+    const double dgds2 = P.gk * (iz - 0.5 * D * iz * iz * W);
+    return dual3{z, (Eh.d0 - dgds2 * s2.d0) * idgdz, (Eh.d1 - dgds2 * s2.d1) * idgdz,
+                 (Eh.d2 - dgds2 * s2.d2) * idgdz};
 }
 __device__ __forceinline__ double root_tangent(const Root &r, double, double, double, const Phys &) { return r.z; }
 
@@ -209,7 +288,7 @@ __device__ inline int sf_cons2prim(const double *q, double *w, const Phys &P, in
     const double Eh = q[sf::TAU] - 0.5 * (dot(E, E) + dot(B, B)) + q[sf::D];
     const Root r = fluid_root(q[sf::D], dot(St, St), Eh, Eh + w[4], P);
     iters = r.iters;
-    const double iz = 1.0 / r.z;
+    const double iz = frcp(r.z);
     w[0] = q[sf::D] * r.iW;
     w[1] = St.x * iz; w[2] = St.y * iz; w[3] = St.z * iz;
     w[4] = r.z - Eh;
@@ -222,8 +301,8 @@ __device__ inline void sf_flux_source(const double *q, const double *w, double s
 {
     const vec3<double> v = v3(w[1], w[2], w[3]);
     const vec3<double> B = v3(q[sf::BX], q[sf::BY], q[sf::BZ]), E = v3(q[sf::EX], q[sf::EY], q[sf::EZ]);
-    const double W2 = 1.0 / (1.0 - dot(v, v));
-    const double W = sqrt(W2);
+    const double W = frsqrt(1.0 - dot(v, v));
+    const double W2 = W * W;
     const double A = (w[0] + P.hk * w[4]) * W2;
     const double pt = w[4] + 0.5 * (dot(E, E) + dot(B, B));
     const vec3<double> J = sf_current(v, W, E, B, q[sf::RHOE], sig);
@@ -311,7 +390,7 @@ __device__ inline int tf_cons2prim(const double *q, double *w, const Phys &P, in
         double *ws = w + 5 * s;
         const Root r = fluid_root(Ds, dot(Ss, Ss), Eh, Eh + ws[4], P);
         iters += r.iters;
-        const double iz = 1.0 / r.z;
+        const double iz = frcp(r.z);
         ws[0] = Ds * r.iW;
         ws[1] = Ss.x * iz; ws[2] = Ss.y * iz; ws[3] = Ss.z * iz;
         ws[4] = r.z - Eh;
@@ -367,10 +446,11 @@ __device__ inline void tf_flux_source(const double *q, const double *w, double s
     for (int s = 0; s < 2; ++s) {
         const double *ws = w + 5 * s;
         v[s] = v3(ws[1], ws[2], ws[3]);
-        const double W2 = 1.0 / (1.0 - dot(v[s], v[s]));
+        const double Wl = frsqrt(1.0 - dot(v[s], v[s]));
+        const double W2 = Wl * Wl;
         rho[s] = ws[0];
         p[s] = ws[4];
-        Dw[s] = ws[0] * sqrt(W2);
+        Dw[s] = ws[0] * Wl;
         A[s] = (ws[0] + P.hk * ws[4]) * W2;
     }
     for (int k = 0; k < tf::NC; ++k) { fx[k] = 0.0; fy[k] = 0.0; }

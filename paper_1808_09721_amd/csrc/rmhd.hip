@@ -146,6 +146,10 @@ __global__ __launch_bounds__(256) void k_c2p(CPlanes cons, Planes prims, int8_t 
 // ---------------------------------------------------------------------------------------
 // implicit stage
 // ---------------------------------------------------------------------------------------
+// statistics counters: STATS_SLOTS slots of STATS_STRIDE (128 bytes) each, summed on read
+constexpr int STATS_SLOTS = 64;
+constexpr int STATS_STRIDE = 16;
+
 struct StageArgs {
     CPlanes R, guess, win;
     Planes Q, wout;
@@ -222,20 +226,35 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs A)
         if (A.iters) A.iters[idx] = nit;
     }
     if (A.stats) {
+        // block reduction (wave shuffles, then LDS), one atomic per counter per block, spread
+        // over STATS_SLOTS padded slots so blocks rarely contend on one address
+        __shared__ unsigned long long red[4][6];
         const bool counted = live && is_interior(g, i, j);
-        const unsigned long long c = wave_sum(counted ? 1ull : 0ull);
-        const unsigned long long n = wave_sum(counted ? (unsigned long long)nit : 0ull);
-        const unsigned long long cc = wave_sum(counted ? (unsigned long long)cit : 0ull);
-        const unsigned long long f = wave_sum(counted && st != CELL_OK ? 1ull : 0ull);
-        const unsigned long long re = wave_sum(counted ? (unsigned long long)rit : 0ull);
-        const int mx = wave_max(counted ? nit : 0);
-        if ((threadIdx.x & 63) == 0 && c) {
-            atomicAdd(&A.stats[0], c);
-            atomicAdd(&A.stats[1], n);
-            atomicAdd(&A.stats[2], cc);
-            if (f) atomicAdd(&A.stats[3], f);
-            atomicAdd(&A.stats[5], re);
-            atomicMax(&A.stats[4], (unsigned long long)mx);
+        unsigned long long v[6] = {counted ? 1ull : 0ull, counted ? (unsigned long long)nit : 0ull,
+                                   counted ? (unsigned long long)cit : 0ull,
+                                   counted && st != CELL_OK ? 1ull : 0ull, 0ull,
+                                   counted ? (unsigned long long)rit : 0ull};
+#pragma unroll
+        for (int k = 0; k < 6; ++k) v[k] = k == 4 ? (unsigned long long)wave_max(counted ? nit : 0) : wave_sum(v[k]);
+        const int wave = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) red[wave][k] = v[k];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long t[6] = {0, 0, 0, 0, 0, 0};
+            for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv)
+#pragma unroll
+                for (int k = 0; k < 6; ++k) t[k] = k == 4 ? max(t[k], red[wv][k]) : t[k] + red[wv][k];
+            if (t[0]) {
+                unsigned long long *slot = A.stats + (blockIdx.x % STATS_SLOTS) * STATS_STRIDE;
+                atomicAdd(&slot[0], t[0]);
+                atomicAdd(&slot[1], t[1]);
+                atomicAdd(&slot[2], t[2]);
+                if (t[3]) atomicAdd(&slot[3], t[3]);
+                atomicMax(&slot[4], t[4]);
+                atomicAdd(&slot[5], t[5]);
+            }
         }
     }
 }
@@ -256,13 +275,21 @@ struct FluxArgs {
 // candidates b + (b - a)/2 and b + (c - b)/2 with linear weights 1/3, 2/3 and
 // alpha_k = d_k / (1e-6 + beta_k)^2 (Jiang-Shu), written with one division:
 // w0 = t1^2 / (t1^2 + 2 t0^2), t_k = 1e-6 + beta_k.
-__device__ __forceinline__ double weno3(double a, double b, double c)
+// Two reconstructions (f+ on one side, f- on the other, of the same cell) share one
+// reciprocal: 1/n1 = n2 / (n1 n2) and 1/n2 = n1 / (n1 n2); n_k >= 3e-12, so the product
+// neither underflows nor overflows for any representable flux.
+__device__ __forceinline__ void weno3_pair(double ap, double bp, double cp, double am, double bm, double cm,
+                                           double &vp, double &vm)
 {
-    const double d0 = b - a, d1 = c - b;
-    const double t0 = 1e-6 + d0 * d0, t1 = 1e-6 + d1 * d1;
-    const double t0s = t0 * t0, t1s = t1 * t1;
-    const double w0 = t1s / (t1s + 2.0 * t0s);
-    return b + 0.5 * (d1 + w0 * (d0 - d1));
+    const double d0p = bp - ap, d1p = cp - bp, d0m = bm - am, d1m = cm - bm;
+    const double t0p = 1e-6 + d0p * d0p, t1p = 1e-6 + d1p * d1p;
+    const double t0m = 1e-6 + d0m * d0m, t1m = 1e-6 + d1m * d1m;
+    const double t1ps = t1p * t1p, t1ms = t1m * t1m;
+    const double np = t1ps + 2.0 * (t0p * t0p), nm = t1ms + 2.0 * (t0m * t0m);
+    const double r = frcp(np * nm);
+    const double w0p = t1ps * nm * r, w0m = t1ms * np * r;
+    vp = bp + 0.5 * (d1p + w0p * (d0p - d1p));
+    vm = bm + 0.5 * (d1m + w0m * (d0m - d1m));
 }
 
 template <int M, int NDIM, int BX, int BY>
@@ -327,13 +354,19 @@ __global__ __launch_bounds__(BX *BY) void k_flux(FluxArgs A)
         }
         __syncthreads();
         if (do_x) {
-            shp[0][ty][tx] = weno3(sfp[0][ty][tx - 1], sfp[0][ty][tx], sfp[0][ty][tx + 1]);
-            shm[0][ty][tx] = weno3(sfm[0][ty][tx + 1], sfm[0][ty][tx], sfm[0][ty][tx - 1]);
+            double vp, vm;
+            weno3_pair(sfp[0][ty][tx - 1], sfp[0][ty][tx], sfp[0][ty][tx + 1], sfm[0][ty][tx + 1], sfm[0][ty][tx],
+                       sfm[0][ty][tx - 1], vp, vm);
+            shp[0][ty][tx] = vp;
+            shm[0][ty][tx] = vm;
         }
         if constexpr (NDIM == 2) {
             if (do_y) {
-                shp[NDIM - 1][ty][tx] = weno3(sfp[NDIM - 1][ty - 1][tx], sfp[NDIM - 1][ty][tx], sfp[NDIM - 1][ty + 1][tx]);
-                shm[NDIM - 1][ty][tx] = weno3(sfm[NDIM - 1][ty + 1][tx], sfm[NDIM - 1][ty][tx], sfm[NDIM - 1][ty - 1][tx]);
+                double vp, vm;
+                weno3_pair(sfp[NDIM - 1][ty - 1][tx], sfp[NDIM - 1][ty][tx], sfp[NDIM - 1][ty + 1][tx],
+                           sfm[NDIM - 1][ty + 1][tx], sfm[NDIM - 1][ty][tx], sfm[NDIM - 1][ty - 1][tx], vp, vm);
+                shp[NDIM - 1][ty][tx] = vp;
+                shm[NDIM - 1][ty][tx] = vm;
             }
         }
         __syncthreads();
@@ -376,7 +409,7 @@ struct rmhd_ctx {
     double *acc;      // q^n + dt/2 [L(Q1) + Psi(Q1)] (ncons planes)
     int8_t *status;   // one plane
     int32_t *iters;   // one plane
-    unsigned long long *stats;  // 8 counters
+    unsigned long long *stats;  // STATS_SLOTS x STATS_STRIDE counters
     // per-kernel event timing of rmhd_imex_step
     int timing;
     hipEvent_t ev[10];
@@ -501,8 +534,9 @@ extern "C" int rmhd_create(const rmhd_params *p, void *stream, rmhd_ctx **out)
     if (e == hipSuccess) e = hipMalloc((void **)&c->acc, pl * L.ncons);
     if (e == hipSuccess) e = hipMalloc((void **)&c->status, (size_t)L.plane);
     if (e == hipSuccess) e = hipMalloc((void **)&c->iters, (size_t)L.plane * sizeof(int32_t));
-    if (e == hipSuccess) e = hipMalloc((void **)&c->stats, 8 * sizeof(unsigned long long));
-    if (e == hipSuccess) e = hipMemsetAsync(c->stats, 0, 8 * sizeof(unsigned long long), c->stream);
+    const size_t stats_bytes = (size_t)STATS_SLOTS * STATS_STRIDE * sizeof(unsigned long long);
+    if (e == hipSuccess) e = hipMalloc((void **)&c->stats, stats_bytes);
+    if (e == hipSuccess) e = hipMemsetAsync(c->stats, 0, stats_bytes, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         std::string m = std::string("scratch allocation: ") + hipGetErrorString(e);
@@ -768,11 +802,16 @@ extern "C" double rmhd_dt(const rmhd_ctx *c)
 extern "C" int rmhd_get_stats(rmhd_ctx *c, rmhd_stats *out, int reset)
 {
     if (!c || !out) return fail(c, RMHD_EINVAL, "rmhd_get_stats: NULL argument");
-    unsigned long long h[8];
-    int rc = hip_check(c, hipMemcpyAsync(h, c->stats, sizeof(h), hipMemcpyDeviceToHost, c->stream), "stats copy");
-    if (!rc && reset) rc = hip_check(c, hipMemsetAsync(c->stats, 0, sizeof(h), c->stream), "stats reset");
+    unsigned long long raw[STATS_SLOTS * STATS_STRIDE], h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int rc = hip_check(c, hipMemcpyAsync(raw, c->stats, sizeof(raw), hipMemcpyDeviceToHost, c->stream), "stats copy");
+    if (!rc && reset) rc = hip_check(c, hipMemsetAsync(c->stats, 0, sizeof(raw), c->stream), "stats reset");
     if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "stats sync");
     if (rc) return rc;
+    for (int sl = 0; sl < STATS_SLOTS; ++sl)
+        for (int k = 0; k < 6; ++k) {
+            const unsigned long long x = raw[sl * STATS_STRIDE + k];
+            h[k] = k == 4 ? (x > h[k] ? x : h[k]) : h[k] + x;
+        }
     out->stage_cells = (int64_t)h[0];
     out->newton_iters = (int64_t)h[1];
     out->c2p_iters = (int64_t)h[2];

@@ -5,12 +5,12 @@
 // runs the nested primitive recovery:
 //   single fluid  x = E                              (3 unknowns)
 //   two fluid     x = (Sbar/|mu1|, taubar/|mu1|, E)   (7 unknowns, barred parts scaled to O(1))
-// Newton with the exact Jacobian: each column is one forward-mode (dual-number) pass
-// through the residual, in which the recovery root z = rho h W^2 is differentiated by the
-// implicit-function theorem at the converged root instead of iterating in dual arithmetic.
-// Steps are halved (up to 30 times) until the primitives stay physical and ||G||_inf drops;
-// at ||G||_inf <= tol max(1, ||R_x||_inf) one further Newton step is taken, so the answer sits
-// at round-off whatever the starting point.
+// Newton with the exact Jacobian: forward-mode (dual-number) passes through the residual, in
+// which the recovery root z = rho h W^2 is differentiated by the implicit-function theorem at
+// the converged root instead of iterating in dual arithmetic.  Steps are halved (up to 30
+// times) until the primitives stay physical and ||G||_inf drops; at ||G||_inf <= tol max(1,
+// ||R_x||_inf) one further Newton step is taken with the last Jacobian (it changed by the
+// order of the last step only), so the answer sits at round-off whatever the starting point.
 #pragma once
 
 #include "physics.hpp"
@@ -26,35 +26,55 @@ __device__ __forceinline__ double maxabs(const double (&g)[N])
     return m;
 }
 
-// A x = b for a small dense A held in registers: Gaussian elimination with partial pivoting
-// (pivot rows are bubbled into place with compile-time indices, so nothing spills to scratch).
+// LU factorisation of a small dense A held in registers, partial pivoting.  Pivot rows are
+// bubbled into place with compile-time indices (conditional swaps, recorded bit k*N+r of
+// *swaps*), so nothing is indexed dynamically and nothing spills to scratch memory.  The
+// multipliers are kept below the diagonal so the factors can be reused for a new right-hand
+// side.
 template <int N>
-__device__ __forceinline__ bool dense_solve(double (&A)[N][N], double (&b)[N])
+__device__ __forceinline__ bool lu_factor(double (&A)[N][N], unsigned long long &swaps)
 {
+    swaps = 0ull;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
 #pragma unroll
         for (int r = k + 1; r < N; ++r) {
             const bool sw = fabs(A[r][k]) > fabs(A[k][k]);
+            swaps |= (unsigned long long)sw << (k * N + r);
 #pragma unroll
-            for (int c = k; c < N; ++c) {
+            for (int c = 0; c < N; ++c) {
                 const double t = A[k][c];
                 A[k][c] = sw ? A[r][c] : t;
                 A[r][c] = sw ? t : A[r][c];
             }
-            const double t = b[k];
-            b[k] = sw ? b[r] : t;
-            b[r] = sw ? t : b[r];
         }
         if (!(A[k][k] != 0.0) || !isfinite(A[k][k])) return false;
         const double inv = 1.0 / A[k][k];
 #pragma unroll
         for (int r = k + 1; r < N; ++r) {
             const double m = A[r][k] * inv;
+            A[r][k] = m;
 #pragma unroll
             for (int c = k + 1; c < N; ++c) A[r][c] -= m * A[k][c];
-            b[r] -= m * b[k];
         }
+    }
+    return true;
+}
+
+template <int N>
+__device__ __forceinline__ void lu_solve(const double (&A)[N][N], unsigned long long swaps, double (&b)[N])
+{
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+#pragma unroll
+        for (int r = k + 1; r < N; ++r) {
+            const bool sw = (swaps >> (k * N + r)) & 1ull;
+            const double t = b[k];
+            b[k] = sw ? b[r] : t;
+            b[r] = sw ? t : b[r];
+        }
+#pragma unroll
+        for (int r = k + 1; r < N; ++r) b[r] -= A[r][k] * b[k];
     }
 #pragma unroll
     for (int r = N - 1; r >= 0; --r) {
@@ -63,7 +83,6 @@ __device__ __forceinline__ bool dense_solve(double (&A)[N][N], double (&b)[N])
         for (int c = r + 1; c < N; ++c) acc -= A[r][c] * b[c];
         b[r] = acc / A[r][r];
     }
-    return true;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -89,7 +108,7 @@ __device__ __forceinline__ void sf_finish(const SFCell &c, const vec3<T> &E, con
 {
     const T iz = recip(z);
     const vec3<T> v = v3<T>(St.x * iz, St.y * iz, St.z * iz);
-    const T W = recip(dsqrt(1.0 - dot(v, v)));
+    const T W = rsqrt_t(1.0 - dot(v, v));
     const vec3<T> J = sf_current(v, W, E, c.B, c.rhoe, c.sig);
     G[0] = E.x - c.RE.x + c.a * J.x;
     G[1] = E.y - c.RE.y + c.a * J.y;
@@ -112,26 +131,50 @@ __device__ __forceinline__ int sf_residual(const SFCell &c, const double (&x)[3]
     return CELL_OK;
 }
 
+// Exact 3x3 Jacobian dG/dE in one forward pass with three tangents.
 __device__ __forceinline__ void sf_jacobian(const SFCell &c, const double (&x)[3], const Root &r, const Phys &P,
                                             double (&A)[3][3])
 {
+    const vec3<dual3> E = v3(dual3{x[0], 1.0, 0.0, 0.0}, dual3{x[1], 0.0, 1.0, 0.0}, dual3{x[2], 0.0, 0.0, 1.0});
+    vec3<dual3> St;
+    dual3 s2, Eh;
+    sf_split(c, E, St, s2, Eh);
+    const dual3 z = root_tangent(r, c.D, s2, Eh, P);
+    dual3 G[3];
+    sf_finish(c, E, St, z, G);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const vec3<dual> E = v3(mk(x[0], k == 0), mk(x[1], k == 1), mk(x[2], k == 2));
-        vec3<dual> St;
-        dual s2, Eh;
-        sf_split(c, E, St, s2, Eh);
-        const dual z = root_tangent(r, c.D, s2, Eh, P);
-        dual G[3];
-        sf_finish(c, E, St, z, G);
-        A[0][k] = G[0].d;
-        A[1][k] = G[1].d;
-        A[2][k] = G[2].d;
+    for (int i = 0; i < 3; ++i) {
+        A[i][0] = G[i].d0;
+        A[i][1] = G[i].d1;
+        A[i][2] = G[i].d2;
     }
+}
+
+// Inverse of a 3x3 matrix by its adjugate; false if singular or not finite.
+__device__ __forceinline__ bool inverse3(const double (&A)[3][3], double (&Ai)[3][3])
+{
+    const double c00 = A[1][1] * A[2][2] - A[1][2] * A[2][1];
+    const double c01 = A[1][2] * A[2][0] - A[1][0] * A[2][2];
+    const double c02 = A[1][0] * A[2][1] - A[1][1] * A[2][0];
+    const double det = A[0][0] * c00 + A[0][1] * c01 + A[0][2] * c02;
+    if (!(det != 0.0) || !isfinite(det)) return false;
+    const double id = 1.0 / det;
+    Ai[0][0] = c00 * id;
+    Ai[1][0] = c01 * id;
+    Ai[2][0] = c02 * id;
+    Ai[0][1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) * id;
+    Ai[1][1] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) * id;
+    Ai[2][1] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) * id;
+    Ai[0][2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) * id;
+    Ai[1][2] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) * id;
+    Ai[2][2] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) * id;
+    return true;
 }
 
 // Solve one single-fluid cell.  R: the 14 conserved right-hand-side values; x: start of E on
 // entry, solution on exit; w: pressure guess in w[4] on entry, primitives on exit.
+// The polishing step after convergence reuses the last Jacobian (its change over the last
+// step is of the order of that step, so the polished iterate still sits at round-off).
 __device__ inline int sf_stage(const double *R, double a, double sig, const Phys &P, double (&x)[3], double *w,
                                int &newton_it, int &c2p_it, int &res_it)
 {
@@ -154,12 +197,20 @@ __device__ inline int sf_stage(const double *R, double a, double sig, const Phys
     if (st == CELL_OK) {
         const double target = P.newton_tol * fmax(1.0, fmax(fabs(c.RE.x), fmax(fabs(c.RE.y), fabs(c.RE.z))));
         st = CELL_NEWTON_NOCONV;
+        double Ji[3][3];
+        bool have_J = false;
         for (int it = 0; it < P.max_newton; ++it) {
             const double nrm = maxabs(G);
             const bool conv = nrm <= target;
-            double A[3][3], dx[3] = {-G[0], -G[1], -G[2]};
-            sf_jacobian(c, x, r, P, A);
-            if (!dense_solve<3>(A, dx)) { st = CELL_LINESEARCH; break; }
+            if (!conv || !have_J) {
+                double A[3][3];
+                sf_jacobian(c, x, r, P, A);
+                if (!inverse3(A, Ji)) { st = CELL_LINESEARCH; break; }
+                have_J = true;
+            }
+            double dx[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) dx[i] = -(Ji[i][0] * G[0] + Ji[i][1] * G[1] + Ji[i][2] * G[2]);
             double lam = 1.0, xt[3], Gt[3], Eht;
             Root rt;
             bool ok = false;
@@ -330,14 +381,21 @@ __device__ inline int tf_stage(const double *R, double a, double sig, const Phys
         rx = fmax(rx, fabs(c.RE.x)); rx = fmax(rx, fabs(c.RE.y)); rx = fmax(rx, fabs(c.RE.z));
         const double target = P.newton_tol * fmax(1.0, rx);
         st = CELL_NEWTON_NOCONV;
+        double A[7][7];
+        unsigned long long swaps = 0ull;
+        bool have_J = false;
         for (int it = 0; it < P.max_newton; ++it) {
             const double nrm = maxabs(G);
             const bool conv = nrm <= target;
-            double A[7][7], dx[7];
+            if (!conv || !have_J) {
+                tf_jacobian(c, x, r, P, A);
+                if (!lu_factor<7>(A, swaps)) { st = CELL_LINESEARCH; break; }
+                have_J = true;
+            }
+            double dx[7];
 #pragma unroll
             for (int i = 0; i < 7; ++i) dx[i] = -G[i];
-            tf_jacobian(c, x, r, P, A);
-            if (!dense_solve<7>(A, dx)) { st = CELL_LINESEARCH; break; }
+            lu_solve<7>(A, swaps, dx);
             double lam = 1.0, xt[7], Gt[7], Eht[2];
             Root rt[2];
             bool ok = false;
