@@ -44,6 +44,30 @@ def cpu_baseline(budget_s: float = 12.0) -> dict:
                       f"OpenMP over cells ({cores} threads), {el:.1f} s"}
 
 
+def source_hash() -> str:
+    """Hash of the HIP sources; counter-derived traffic is reported only while it matches."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1808_09721_amd", "csrc", "*"))):
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(tag: str, kernel_prefix: str):
+    """HBM bytes per launch (copy-calibrated FETCH_SIZE + WRITE_SIZE) recorded under profiles/."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{tag}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_hash") != source_hash():
+        return None
+    for k, v in rec["kernels"].items():
+        if k.startswith(kernel_prefix):
+            return v["fetch_bytes"] + v["write_bytes"]
+    return None
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,7 +149,9 @@ def main() -> int:
     dominant = "implicit_stage" if 2 * stage_ms >= 2 * flux_ms else "flux"
     roof = {k: kernels[dominant][k] for k in ("bound", "achieved", "peak", "unit", "frac")}
     roof["kernel"] = dominant
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic("khi_256x512", "rmhd::k_flux" if dominant == "flux" else "rmhd::k_stage")
+    if roof["traffic"] is not None and dominant == "flux":
+        roof["traffic_over_algorithmic"] = roof["traffic"] / (flux_bytes * cells)
 
     out = {
         "metric": "FP64 cell-updates/s per IMEX step + Newton iters/cell, plain vs batched+learned",
