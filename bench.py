@@ -68,6 +68,58 @@ def measured_traffic(tag: str, kernel_prefix: str):
     return None
 
 
+def batched_measure(steps: int, warmup: int) -> dict:
+    """The 64-domain batched workload (32 1-D shock tubes, N ~ U[128, 4096]; 32 2-D KH set-ups,
+    sides ~ U[64, 512]; sigma ~ 10^U[1, 6]; seed 4): one batched step (autotuned, graph-
+    captured) against the same domains stepped one after another on the single-grid path."""
+    import torch
+
+    from paper_1808_09721_amd import rmhd as R
+    from paper_1808_09721_amd import workloads as WL
+    doms = WL.batched_domains(seed=4)
+    cells = sum(w.cells for w in doms)
+    B = R.Batch(doms)
+    tuning = B.autotune()
+    for _ in range(warmup):
+        B.step()
+    B.stats(reset=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        B.step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_b = e0.elapsed_time(e1) / steps
+    st = B.stats(reset=True)
+    B.close()
+    # the same domains, one single-grid context each, stepped in turn
+    solvers = []
+    for wl in doms:
+        s = R.Solver(R.params_from(wl))
+        c, w = s.initial_state(wl.prims, wl.EB)
+        solvers.append((s, c, w, s.dt()))
+    for _ in range(warmup):
+        for s, c, w, h in solvers:
+            s.step(h, c, w)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        for s, c, w, h in solvers:
+            s.step(h, c, w)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_p = e0.elapsed_time(e1) / steps
+    for s, *_ in solvers:
+        s.close()
+    return {"workload": "64 domains (32 x 1-D Brio-Wu N~U[128,4096], 32 x 2-D KHI sides~U[64,512], "
+                        "sigma~10^U[1,6], seed 4)", "cells": cells,
+            "value": cells / (ms_b / 1e3), "unit": "cell-updates/s", "ms_per_step": ms_b,
+            "plain_value": cells / (ms_p / 1e3), "plain_ms_per_step": ms_p, "speedup_vs_plain": ms_p / ms_b,
+            "newton_iters_per_cell_stage": st["newton_iters"] / max(1, st["stage_cells"]),
+            "newton_iters_max": st["newton_max"], "failures": st["failures"], "tuning": tuning}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +127,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--timing-steps", type=int, default=20)
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (traffic calibration)")
     args = ap.parse_args()
@@ -169,6 +222,8 @@ def main() -> int:
         "roofline": roof,
         "kernels": kernels,
     }
+    if not args.no_batched:
+        out["batched"] = batched_measure(max(5, args.steps // 5), args.warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
         out["cpu_baseline"]["gpu_speedup"] = value / out["cpu_baseline"]["value"]

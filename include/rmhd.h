@@ -166,6 +166,49 @@ int rmhd_get_timing(rmhd_ctx *ctx, rmhd_timing *out, int reset);
  * when ctx is NULL).  Owned by the library; valid until the next call on the same ctx. */
 const char *rmhd_last_error(const rmhd_ctx *ctx);
 
+/* ------------------------------------------------------------------------------------
+ * Batched form: many independent single-fluid domains of uneven size and stiffness advanced
+ * by one launch per kernel of the SSP2(222) step for all of them (each domain with its own
+ * grid, boundary, sigma and dt), with a convergence-compacted queue for the implicit stage
+ * (cells still unconverged after newton_cap Newton iterations continue in full wavefronts),
+ * the step captured once in a HIP graph, and launch shapes chosen by rmhd_batch_autotune().
+ * The method per cell is exactly the one of rmhd_imex_step (Sec. 2.2.1, Eqs. 10-11).
+ * ------------------------------------------------------------------------------------ */
+typedef struct rmhd_batch rmhd_batch;
+
+typedef struct rmhd_batch_tuning {
+    int32_t persistent;         /* stage launch: 1 = persistent grid pulling work items from an
+                                   atomic counter, 0 = one block per 256-cell chunk */
+    int32_t chunks_per_item;    /* persistent mode: 256-cell chunks per counter grab */
+    int32_t persistent_blocks;  /* persistent mode: blocks in the grid */
+    int32_t newton_cap;         /* Newton iterations before a cell moves to the compacted queue
+                                   (>= max_newton_iter: no queue) */
+    int32_t flux_rows;          /* rows of a 2-D flux tile block: 8 or 16 */
+    int32_t use_graph;          /* 1: capture the step in a HIP graph and replay it */
+    double step_ms;             /* set by rmhd_batch_autotune: time of the chosen shape */
+} rmhd_batch_tuning;
+
+/* Create a batch of n domains (each validated as for rmhd_create; single fluid, scalar
+ * sigma).  Allocates pooled stage scratch for all domains.  *out is set even on failure so
+ * that rmhd_batch_last_error() can explain it; always release with rmhd_batch_destroy(). */
+int rmhd_batch_create(const rmhd_params *domains, int n, void *hip_stream, rmhd_batch **out);
+void rmhd_batch_destroy(rmhd_batch *batch);
+
+/* One SSP2(222) step of every domain.  dt: host array of n time steps, or NULL for each
+ * domain's CFL time step.  cons, prims: host arrays of n device pointers, laid out per domain
+ * as in rmhd_layout_of(); advanced in place exactly as rmhd_imex_step() does. */
+int rmhd_batch_step(rmhd_batch *batch, const double *dt, double *const *cons, double *const *prims);
+
+/* Time the candidate launch shapes on the given state (only library scratch is written) and
+ * keep the fastest; the choice is returned in *out (may be NULL). */
+int rmhd_batch_autotune(rmhd_batch *batch, double *const *cons, double *const *prims, rmhd_batch_tuning *out);
+int rmhd_batch_set_tuning(rmhd_batch *batch, const rmhd_batch_tuning *tuning);
+int rmhd_batch_get_tuning(const rmhd_batch *batch, rmhd_batch_tuning *tuning);
+
+/* Statistics of the stage solves of all domains (synchronises the stream). */
+int rmhd_batch_get_stats(rmhd_batch *batch, rmhd_stats *out, int reset);
+const char *rmhd_batch_last_error(const rmhd_batch *batch);
+
 #ifdef __cplusplus
 }
 #endif

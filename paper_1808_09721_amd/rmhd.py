@@ -52,9 +52,17 @@ class rmhd_timing(ctypes.Structure):
                 ("c2p_launches", ctypes.c_int64), ("steps", ctypes.c_int64)]
 
 
+class rmhd_batch_tuning(ctypes.Structure):
+    _fields_ = [("persistent", ctypes.c_int32), ("chunks_per_item", ctypes.c_int32),
+                ("persistent_blocks", ctypes.c_int32), ("newton_cap", ctypes.c_int32),
+                ("flux_rows", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("step_ms", ctypes.c_double)]
+
+
 EXPORTS = ["rmhd_layout_of", "rmhd_create", "rmhd_destroy", "rmhd_init_state", "rmhd_cons2prim", "rmhd_F",
            "rmhd_implicit_stage", "rmhd_imex_step", "rmhd_dt", "rmhd_get_stats", "rmhd_set_timing",
-           "rmhd_get_timing", "rmhd_last_error"]
+           "rmhd_get_timing", "rmhd_last_error",
+           "rmhd_batch_create", "rmhd_batch_destroy", "rmhd_batch_step", "rmhd_batch_autotune",
+           "rmhd_batch_set_tuning", "rmhd_batch_get_tuning", "rmhd_batch_get_stats", "rmhd_batch_last_error"]
 
 _lib = None
 
@@ -82,6 +90,14 @@ def lib() -> ctypes.CDLL:
             "rmhd_set_timing": (ctypes.c_int, [vp, ctypes.c_int]),
             "rmhd_get_timing": (ctypes.c_int, [vp, ctypes.POINTER(rmhd_timing), ctypes.c_int]),
             "rmhd_last_error": (ctypes.c_char_p, [vp]),
+            "rmhd_batch_create": (ctypes.c_int, [P, ctypes.c_int, vp, ctypes.POINTER(vp)]),
+            "rmhd_batch_destroy": (None, [vp]),
+            "rmhd_batch_step": (ctypes.c_int, [vp, vp, vp, vp]),
+            "rmhd_batch_autotune": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(rmhd_batch_tuning)]),
+            "rmhd_batch_set_tuning": (ctypes.c_int, [vp, ctypes.POINTER(rmhd_batch_tuning)]),
+            "rmhd_batch_get_tuning": (ctypes.c_int, [vp, ctypes.POINTER(rmhd_batch_tuning)]),
+            "rmhd_batch_get_stats": (ctypes.c_int, [vp, ctypes.POINTER(rmhd_stats), ctypes.c_int]),
+            "rmhd_batch_last_error": (ctypes.c_char_p, [vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -264,3 +280,110 @@ class Solver:
 
     def stats(self, reset: bool = False) -> dict:
         return rmhd_get_stats(self.ctx, reset)
+
+
+# ---------------------------------------------------------------------------------------------
+# batched form
+# ---------------------------------------------------------------------------------------------
+def _bcheck(rc: int, batch):
+    if rc != 0:
+        msg = lib().rmhd_batch_last_error(batch)
+        raise RmhdError(f"librmhd batch error {rc}: {msg.decode() if msg else ''}")
+
+
+def _ptr_array(tensors):
+    arr = (ctypes.c_void_p * len(tensors))(*[_ptr(t) for t in tensors])
+    return arr
+
+
+def rmhd_batch_create(params_list, stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    arr = (rmhd_params * len(params_list))(*params_list)
+    b = ctypes.c_void_p()
+    rc = lib().rmhd_batch_create(arr, len(params_list), ctypes.c_void_p(s.cuda_stream), ctypes.byref(b))
+    if rc != 0:
+        msg = lib().rmhd_batch_last_error(b)
+        lib().rmhd_batch_destroy(b)
+        raise RmhdError(f"librmhd batch error {rc}: {msg.decode() if msg else ''}")
+    return b
+
+
+def rmhd_batch_destroy(b):
+    lib().rmhd_batch_destroy(b)
+
+
+def rmhd_batch_step(b, dt, cons_list, prims_list):
+    dts = None if dt is None else (ctypes.c_double * len(dt))(*[float(x) for x in dt])
+    c, p = _ptr_array(cons_list), _ptr_array(prims_list)
+    _bcheck(lib().rmhd_batch_step(b, dts, c, p), b)
+
+
+def rmhd_batch_autotune(b, cons_list, prims_list) -> dict:
+    t = rmhd_batch_tuning()
+    c, p = _ptr_array(cons_list), _ptr_array(prims_list)
+    _bcheck(lib().rmhd_batch_autotune(b, c, p, ctypes.byref(t)), b)
+    return {k: getattr(t, k) for k, _ in rmhd_batch_tuning._fields_}
+
+
+def rmhd_batch_set_tuning(b, **kw):
+    t = rmhd_batch_tuning()
+    _bcheck(lib().rmhd_batch_get_tuning(b, ctypes.byref(t)), b)
+    for k, v in kw.items():
+        setattr(t, k, v)
+    _bcheck(lib().rmhd_batch_set_tuning(b, ctypes.byref(t)), b)
+
+
+def rmhd_batch_get_tuning(b) -> dict:
+    t = rmhd_batch_tuning()
+    _bcheck(lib().rmhd_batch_get_tuning(b, ctypes.byref(t)), b)
+    return {k: getattr(t, k) for k, _ in rmhd_batch_tuning._fields_}
+
+
+def rmhd_batch_get_stats(b, reset: bool = False) -> dict:
+    s = rmhd_stats()
+    _bcheck(lib().rmhd_batch_get_stats(b, ctypes.byref(s), int(reset)), b)
+    return {k: getattr(s, k) for k, _ in rmhd_stats._fields_}
+
+
+class Batch:
+    """Owner of a batch and of its domains' device state (initialised per domain through the
+    single-grid entry points)."""
+
+    def __init__(self, workloads, stream=None, **param_kw):
+        self.params = [params_from(wl, **param_kw) for wl in workloads]
+        self.grids = [Grid(p) for p in self.params]
+        self.cons, self.prims = [], []
+        for wl, p in zip(workloads, self.params):
+            s = Solver(p, stream)
+            c, w = s.initial_state(wl.prims, wl.EB)
+            s.close()
+            self.cons.append(c)
+            self.prims.append(w)
+        self.b = rmhd_batch_create(self.params, stream)
+
+    def step(self, dt=None):
+        rmhd_batch_step(self.b, dt, self.cons, self.prims)
+
+    def autotune(self) -> dict:
+        return rmhd_batch_autotune(self.b, self.cons, self.prims)
+
+    def tune(self, **kw):
+        rmhd_batch_set_tuning(self.b, **kw)
+
+    def tuning(self) -> dict:
+        return rmhd_batch_get_tuning(self.b)
+
+    def stats(self, reset: bool = False) -> dict:
+        return rmhd_batch_get_stats(self.b, reset)
+
+    def close(self):
+        if self.b is not None:
+            rmhd_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -224,3 +224,25 @@ def random_states(n: int, model: int, seed: int, w_max: float = 10.0, field_max:
         prims[:, 6:9] = np.where(speed < 0.999, v2, v2 * 0.999 / speed)
     EB = rng.uniform(-field_max, field_max, (n, 6))
     return prims, EB
+
+
+def batched_domains(seed: int = 4, n1: int = 32, n2: int = 32, n1_range=(128, 4096), side_range=(64, 512),
+                    log_sigma=(1.0, 6.0)) -> list[Workload]:
+    """Many independent single-fluid domains of uneven size and stiffness: ``n1`` 1-D Brio-Wu
+    shock tubes with N ~ U[128, 4096] and ``n2`` 2-D Kelvin-Helmholtz set-ups with
+    nx, ny ~ U[64, 512] independently, each with sigma ~ 10^U[1, 6].  Drawn in a fixed order
+    from ``seed``: all 1-D sizes, all 2-D sizes, all sigmas, then one initial-data seed per
+    domain."""
+    rng = np.random.default_rng(seed)
+    n1s = rng.integers(n1_range[0], n1_range[1] + 1, n1)
+    sides = rng.integers(side_range[0], side_range[1] + 1, (n2, 2))
+    sigmas = 10.0 ** rng.uniform(log_sigma[0], log_sigma[1], n1 + n2)
+    seeds = rng.integers(0, 2 ** 31 - 1, n1 + n2)
+    out = []
+    for k in range(n1):
+        out.append(brio_wu_1d(int(n1s[k]), sigma=float(sigmas[k]), seed=int(seeds[k])))
+    for k in range(n2):
+        wl = kelvin_helmholtz_2d(int(sides[k, 0]), int(sides[k, 1]), sigma=float(sigmas[n1 + k]),
+                                 seed=int(seeds[n1 + k]))
+        out.append(wl)
+    return out

@@ -65,3 +65,40 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(R, "_lib", None)
     with pytest.raises(R.RmhdError, match="missing"):
         R.lib()
+
+
+def _batch_create_error(params):
+    lib = R.lib()
+    arr = (R.rmhd_params * len(params))(*params)
+    b = ctypes.c_void_p()
+    rc = lib.rmhd_batch_create(arr, len(params), None, ctypes.byref(b))
+    msg = lib.rmhd_batch_last_error(b).decode()
+    lib.rmhd_batch_destroy(b)
+    return rc, msg
+
+
+def test_batch_create_validates_before_touching_the_gpu():
+    if not os.path.exists(R.LIB_PATH):
+        pytest.skip("librmhd.so not built")
+    ok = R.params_from(WL.brio_wu_1d(128))
+    tf = R.params_from(WL.two_fluid_sheet_2d(16, 16, steps=1))
+    rc, msg = _batch_create_error([ok, tf])
+    assert rc == -1 and "single-fluid" in msg
+    bad = R.params_from(WL.brio_wu_1d(128))
+    bad.nx = 2
+    rc, msg = _batch_create_error([ok, bad])
+    assert rc == -1 and "domain 1" in msg
+    lib = R.lib()
+    b = ctypes.c_void_p()
+    assert lib.rmhd_batch_create(None, 0, None, ctypes.byref(b)) == -1
+    lib.rmhd_batch_destroy(b)
+
+
+def test_batched_domains_recipe_is_seeded():
+    a = WL.batched_domains(seed=4)
+    b = WL.batched_domains(seed=4)
+    assert len(a) == 64 and sum(w.ndim == 1 for w in a) == 32
+    assert [(w.nx, w.ny, w.sigma) for w in a] == [(w.nx, w.ny, w.sigma) for w in b]
+    assert all(128 <= w.nx <= 4096 for w in a if w.ndim == 1)
+    assert all(64 <= w.nx <= 512 and 64 <= w.ny <= 512 for w in a if w.ndim == 2)
+    assert all(10.0 <= w.sigma <= 1e6 for w in a)
