@@ -58,7 +58,7 @@ __device__ __forceinline__ int batch_cell(const DomainDev &D, int phase, long id
 {
     const Geo &g = D.g;
     (void)g;
-    const double gm = 1.0 - 0.70710678118654752440;
+    const double gm = SSP2_GAMMA;
     const double a = gm * D.dt;
     const double *Rb = phase == 1 ? D.cons : D.r2;
     double R[sf::NC];
@@ -85,7 +85,7 @@ __device__ __forceinline__ void batch_write(const DomainDev &D, int phase, long 
                                             const double *w)
 {
     const Geo &g = D.g;
-    const double gm = 1.0 - 0.70710678118654752440;
+    const double gm = SSP2_GAMMA;
     const double a = gm * D.dt;
     const double aK = 1.0 / (1.0 + a * D.P.kappa);
     const double *Rb = phase == 1 ? D.cons : D.r2;
@@ -219,7 +219,7 @@ __global__ __launch_bounds__(BX *BY) void kb_flux(BatchFluxArgs B)
     const int4 t = B.tiles[blockIdx.x];
     const DomainDev &D = B.dom[t.x];
     const Geo &g = D.g;
-    const double gm = 1.0 - 0.70710678118654752440;
+    const double gm = SSP2_GAMMA;
     FluxArgs A{};
     A.g = g;
     A.P = D.P;

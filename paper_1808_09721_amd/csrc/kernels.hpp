@@ -144,6 +144,10 @@ __global__ __launch_bounds__(256) void k_c2p(CPlanes cons, Planes prims, int8_t 
 // ---------------------------------------------------------------------------------------
 // implicit stage
 // ---------------------------------------------------------------------------------------
+// SSP2(222) coefficient gamma = 1 - 1/sqrt(2) (Table 2), correctly rounded; every path that
+// advances a grid uses this one value so that they agree bit for bit
+constexpr double SSP2_GAMMA = 0.29289321881345247559915563789515;
+
 // statistics counters: STATS_SLOTS slots of STATS_STRIDE (128 bytes) each, summed on read
 constexpr int STATS_SLOTS = 64;
 constexpr int STATS_STRIDE = 16;

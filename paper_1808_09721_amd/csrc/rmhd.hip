@@ -273,7 +273,7 @@ extern "C" int rmhd_imex_step(rmhd_ctx *c, double dt, double *cons, double *prim
     if (!c || !cons || !prims) return fail(c, RMHD_EINVAL, "rmhd_imex_step: NULL argument");
     if (!(dt > 0.0)) return fail(c, RMHD_EINVAL, "rmhd_imex_step: dt must be > 0");
     const rmhd_layout &L = c->lay;
-    const double gm = 1.0 - 1.0 / sqrt(2.0);
+    const double gm = SSP2_GAMMA;
     const int M = c->prm.model;
     // Q1: the source-free components are those of q^n; the others live in scratch
     Planes Q1 = planes_of(cons, L, L.ncons);

@@ -246,3 +246,30 @@ def batched_domains(seed: int = 4, n1: int = 32, n2: int = 32, n1_range=(128, 40
                                  seed=int(seeds[n1 + k]))
         out.append(wl)
     return out
+
+
+# ----------------------------------------------------------------------------------------
+# learned Newton guess: seeded inputs
+# ----------------------------------------------------------------------------------------
+MLP_SHAPES = [(64, 19), (64,), (64, 64), (64,), (7, 64), (7,)]   # W1, b1, W2, b2, W3, b3
+
+
+def mlp_initial_params(seed: int) -> np.ndarray:
+    """Initial FP32 master weights of the 19-64-64-7 guess network, flattened in the order
+    W1, b1, W2, b2, W3, b3 (row-major): weights uniform in +-1/sqrt(fan_in), biases zero."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for shape in MLP_SHAPES:
+        if len(shape) == 2:
+            lim = 1.0 / np.sqrt(shape[1])
+            parts.append(rng.uniform(-lim, lim, shape).astype(np.float32).ravel())
+        else:
+            parts.append(np.zeros(shape, dtype=np.float32))
+    return np.concatenate(parts)
+
+
+def learned_guess_sheet(n: int = 1024, seed: int = 5, steps: int = 10) -> Workload:
+    """Two-fluid current sheet with a per-cell conductivity sigma ~ 10^U[2, 6] (eta from 1e-6
+    to 1e-2), the workload of the learned starting guess.  Training data come from the same
+    set-up at other seeds (the evaluation seed 5 is held out)."""
+    return two_fluid_sheet_2d(n, n, seed=seed, steps=steps, sigma_range=(1e2, 1e6))
