@@ -120,6 +120,80 @@ def batched_measure(steps: int, warmup: int) -> dict:
             "newton_iters_max": st["newton_max"], "failures": st["failures"], "tuning": tuning}
 
 
+def learned_measure(steps: int, warmup: int, n: int = 1024, train_n: int = 512, train_seeds=(1, 2, 3, 4),
+                    harvest_steps: int = 6, dt_factors=(1.0, 0.5, 0.25), epochs: int = 8) -> dict:
+    """Learned starting guess on the two-fluid current sheet with sigma ~ 10^U[2, 6] per cell:
+    harvest (features, target) rows from train_n^2 runs at seeds 1-4 whose steps cycle through
+    dt_factors times the CFL step (so the network sees the stage coefficient of finer grids),
+    fit the normalisation, train on the device, then time ``steps`` steps of the n^2 set-up at
+    the held-out seed 5 with the plain and with the learned guess (same initial state, same
+    dt).  Harvest and training are outside the timed regions and reported separately."""
+    import torch
+
+    from paper_1808_09721_amd import rmhd as R
+    from paper_1808_09721_amd import workloads as WL
+    t0 = time.perf_counter()
+    X, T = R.harvest_stages([WL.learned_guess_sheet(train_n, seed=sd, steps=harvest_steps) for sd in train_seeds],
+                            harvest_steps, dt_factors)
+    torch.cuda.synchronize()
+    t_harvest = time.perf_counter() - t0
+    off = X.shape[0]
+    net = R.Mlp(WL.mlp_initial_params(7))
+    net.fit_norm(X, T)
+    t1 = time.perf_counter()
+    hist = net.train(X, T, batch=16384, epochs=epochs, lr0=3e-3, lr1=1e-4, seed=11)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    del X, T
+
+    wl = WL.learned_guess_sheet(n, seed=5, steps=steps)
+    res = {}
+    for mode in ("plain_single_pass", "plain", "learned"):
+        s = R.Solver.for_workload(wl)
+        c, w = s.initial_state(wl.prims, wl.EB)
+        dt = s.dt()
+        if mode == "plain_single_pass":
+            s.set_newton_cap(1000)     # no queue: every wavefront runs to its slowest cell
+        if mode == "learned":
+            s.set_guess_model(net)
+        for _ in range(warmup):
+            s.step(dt, c, w)
+        s.stats(reset=True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            s.step(dt, c, w)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        st = s.stats(reset=True)
+        R.rmhd_set_timing(s.ctx, True)
+        R.rmhd_get_timing(s.ctx, reset=True)
+        for _ in range(2):
+            s.step(dt, c, w)
+        tm = R.rmhd_get_timing(s.ctx, reset=True)
+        R.rmhd_set_timing(s.ctx, False)
+        res[mode] = {"ms_per_step": ms, "value": wl.cells / (ms / 1e3),
+                     "newton_iters_per_cell_stage": st["newton_iters"] / max(1, st["stage_cells"]),
+                     "residual_evals_per_cell_stage": st["residual_evals"] / max(1, st["stage_cells"]),
+                     "c2p_iters_per_cell_stage": st["c2p_iters"] / max(1, st["stage_cells"]),
+                     "newton_iters_max": st["newton_max"], "failures": st["failures"],
+                     "stage_ms_per_launch": tm["stage_ms"] / tm["stage_launches"]}
+        s.close()
+    net.close()
+    return {"workload": f"two-fluid current sheet {n}x{n}, sigma~10^U[2,6] per cell, seed 5 (held out)",
+            "cells": wl.cells, "unit": "cell-updates/s", "steps": steps,
+            "value": res["learned"]["value"], "plain_value": res["plain"]["value"],
+            "speedup_vs_plain": res["plain"]["ms_per_step"] / res["learned"]["ms_per_step"],
+            "plain": res["plain"], "learned": res["learned"], "plain_single_pass": res["plain_single_pass"],
+            "training": {"rows": off, "harvest": f"{len(train_seeds)} seeds x {harvest_steps} steps x 2 stages of "
+                                                 f"{train_n}x{train_n}, dt factors {list(dt_factors)}",
+                         "epochs": epochs, "batch": 16384,
+                         "loss_first_epoch": float(hist[0]), "loss_last_epoch": float(hist[-1]),
+                         "harvest_s": t_harvest, "train_s": t_train}}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +202,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--timing-steps", type=int, default=20)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (traffic calibration)")
     args = ap.parse_args()
@@ -224,6 +299,8 @@ def main() -> int:
     }
     if not args.no_batched:
         out["batched"] = batched_measure(max(5, args.steps // 5), args.warmup)
+    if not args.no_learned:
+        out["learned"] = learned_measure(10, args.warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
         out["cpu_baseline"]["gpu_speedup"] = value / out["cpu_baseline"]["value"]

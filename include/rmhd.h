@@ -100,7 +100,7 @@ typedef struct rmhd_stats {
 /* Per-kernel GPU time of rmhd_imex_step, from HIP events recorded on the context's stream
  * around every launch while timing is enabled (rmhd_set_timing). */
 typedef struct rmhd_timing {
-    double stage_ms;          /* implicit-stage kernel, summed */
+    double stage_ms;          /* implicit-stage kernels (learned guess, solve, queue), summed */
     double flux_ms;           /* flux-divergence + combiner kernel, summed */
     double c2p_ms;            /* primitive-recovery kernel, summed */
     int64_t stage_launches, flux_launches, c2p_launches;
@@ -136,7 +136,9 @@ int rmhd_F(rmhd_ctx *ctx, double *cons, double *prims, double *L);
 
 /* Implicit stage (Sec. 2.2.1, Eq. 10): solve Q = R + a Psi(Q) per cell, a = a_ii dt, on every
  * cell including ghosts (so Q's ghosts follow R's).  guess: optional array of conserved
- * variables whose source-carrying components start Newton (NULL = the plain guess R).
+ * variables whose source-carrying components start Newton (NULL = the plain guess R; two
+ * fluid: Newton starts from whichever of guess and R has the smaller residual); a cell whose
+ * Newton fails from guess is solved again from R.
  * prims: pressure guesses on entry, primitives of Q on exit.  Q may alias R.  status and
  * iters (Newton iterations) may be NULL. */
 int rmhd_implicit_stage(rmhd_ctx *ctx, double a, const double *R, const double *guess, double *Q,
@@ -153,6 +155,15 @@ double rmhd_dt(const rmhd_ctx *ctx);
 
 /* Copy the accumulated statistics (synchronises the stream); reset != 0 zeroes them. */
 int rmhd_get_stats(rmhd_ctx *ctx, rmhd_stats *out, int reset);
+
+/* Newton steps a cell may take from unconverged iterates in the first pass of an implicit
+ * stage (rmhd_implicit_stage, rmhd_imex_step) before it moves to a compacted queue that a
+ * second kernel finishes in full wavefronts: the first pass then costs what its fastest
+ * cells need instead of what the slowest cell of each wavefront needs.  cap >=
+ * max_newton_iter disables the queue and gives the uninterrupted solve bit for bit; a queued
+ * cell resumes from its saved unknowns and pressures with a fresh Jacobian, which agrees with
+ * the uninterrupted solve to the Newton tolerance.  Default 1.  cap must be >= 1. */
+int rmhd_set_newton_cap(rmhd_ctx *ctx, int cap);
 
 /* Enable (1) or disable (0) per-kernel event timing of rmhd_imex_step.  While enabled each
  * step waits for its own kernels to finish (to read the events), so it is meant for a
@@ -172,7 +183,10 @@ const char *rmhd_last_error(const rmhd_ctx *ctx);
  * grid, boundary, sigma and dt), with a convergence-compacted queue for the implicit stage
  * (cells still unconverged after newton_cap Newton iterations continue in full wavefronts),
  * the step captured once in a HIP graph, and launch shapes chosen by rmhd_batch_autotune().
- * The method per cell is exactly the one of rmhd_imex_step (Sec. 2.2.1, Eqs. 10-11).
+ * The method per cell is exactly the one of rmhd_imex_step (Sec. 2.2.1, Eqs. 10-11): with
+ * newton_cap >= max_newton_iter the results equal rmhd_imex_step's bit for bit; a queued cell
+ * resumes from its saved unknowns and pressure with a fresh Jacobian, which agrees with the
+ * uninterrupted solve to the Newton tolerance.
  * ------------------------------------------------------------------------------------ */
 typedef struct rmhd_batch rmhd_batch;
 

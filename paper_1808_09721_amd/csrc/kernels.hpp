@@ -162,7 +162,19 @@ struct StageArgs {
     Geo g;
     Phys P;
     int write_all;
-    int use_guess;
+    int use_guess;    // start Newton from guess (plain guess R_x again for a cell that fails)
+    // optional harvest of (features, target) rows of the learned guess, two fluid only:
+    // interior cell (i, j) writes row hbase + (j - 2) nx + (i - 2)
+    float *hx, *ht;
+    long hbase;
+    // convergence-compacted queue: a cell still unconverged after cap Newton steps is
+    // appended (cell index, unknowns, pressure guesses, steps taken) and finished by k_drain
+    int cap;          // >= P.max_newton: no queue
+    int qcap;
+    int *qidx, *qit;
+    double *qx;       // [NX][qcap]
+    double *qp;       // [2][qcap]
+    unsigned *qcount;
 };
 
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v)
@@ -214,6 +226,94 @@ __device__ __forceinline__ void stats_block_add(unsigned long long *stats, unsig
     __syncthreads();  // red[] may be reused by a following call in the same block
 }
 
+// Starting unknowns of a cell: the caller's guess planes, or the plain guess R_x.
+template <int M>
+__device__ __forceinline__ void stage_start(const StageArgs &A, long idx, bool guess, double (&x)[Model<M>::NX])
+{
+    const CPlanes &X0 = guess ? A.guess : A.R;
+    if constexpr (M == 0) {
+        x[0] = X0.p[sf::EX][idx]; x[1] = X0.p[sf::EY][idx]; x[2] = X0.p[sf::EZ][idx];
+    } else {
+        const double isc = 1.0 / fabs(A.P.mu1);
+        x[0] = X0.p[tf::SBX][idx] * isc; x[1] = X0.p[tf::SBY][idx] * isc; x[2] = X0.p[tf::SBZ][idx] * isc;
+        x[3] = X0.p[tf::TAUB][idx] * isc;
+        x[4] = X0.p[tf::EX][idx]; x[5] = X0.p[tf::EY][idx]; x[6] = X0.p[tf::EZ][idx];
+    }
+}
+
+// One solve attempt of a cell from x (TF: with R_x as the alternative start when alt).
+template <int M>
+__device__ __forceinline__ int stage_solve(const double *R, const StageArgs &A, double sig, const Phys &P,
+                                          double (&x)[Model<M>::NX], double *w, int &nit, int &cit, int &rit,
+                                          bool alt, int cap)
+{
+    int n = 0, c = 0, r = 0, st;
+    if constexpr (M == 0) {
+        (void)alt;
+        st = sf_stage(R, A.a, sig, P, x, w, n, c, r, cap);
+    } else {
+        const double isc = 1.0 / fabs(P.mu1);
+        const double rx[7] = {R[tf::SBX] * isc, R[tf::SBY] * isc, R[tf::SBZ] * isc, R[tf::TAUB] * isc,
+                              R[tf::EX], R[tf::EY], R[tf::EZ]};
+        st = tf_stage(R, A.a, sig, P, x, w, n, c, r, alt ? rx : nullptr, cap);
+    }
+    nit += n;
+    cit += c;
+    rit += r;
+    return st;
+}
+
+// Outputs of a finished cell: the source-carrying components of Q (psi and phi in closed
+// form), the other components when Q != R, primitives, status, iterations, harvest row.
+template <int M>
+__device__ __forceinline__ void stage_write(const StageArgs &A, long idx, int i, int j, const double *R,
+                                           const double (&x)[Model<M>::NX], const double *w, int st, int nit,
+                                           double sig)
+{
+    constexpr int NC = Model<M>::NC, NP = Model<M>::NP;
+    const Geo &g = A.g;
+    const double aK = 1.0 / (1.0 + A.a * A.P.kappa);
+    if constexpr (M == 0) {
+        A.Q.p[sf::EX][idx] = x[0]; A.Q.p[sf::EY][idx] = x[1]; A.Q.p[sf::EZ][idx] = x[2];
+        A.Q.p[sf::PHI][idx] = R[sf::PHI] * aK;
+        A.Q.p[sf::PSI][idx] = (R[sf::PSI] + A.a * R[sf::RHOE]) * aK;
+    } else {
+        const double sc = fabs(A.P.mu1), isc = 1.0 / sc;
+        A.Q.p[tf::SBX][idx] = x[0] * sc; A.Q.p[tf::SBY][idx] = x[1] * sc; A.Q.p[tf::SBZ][idx] = x[2] * sc;
+        A.Q.p[tf::TAUB][idx] = x[3] * sc;
+        A.Q.p[tf::EX][idx] = x[4]; A.Q.p[tf::EY][idx] = x[5]; A.Q.p[tf::EZ][idx] = x[6];
+        A.Q.p[tf::PHI][idx] = R[tf::PHI] * aK;
+        A.Q.p[tf::PSI][idx] = (R[tf::PSI] + A.a * R[tf::DB]) * aK;
+        if (A.hx && is_interior(g, i, j)) {
+            // features of R and target (x* - R_x) / D of the learned guess
+            const long row = A.hbase + (g.ndim == 2 ? (long)(j - 2) * g.nx : 0) + (i - 2);
+            const double iD = 1.0 / R[tf::D];
+            float *f = A.hx + row * 19;
+            f[0] = (float)log10(A.a * A.P.mu1 * A.P.mu1 * R[tf::D]);
+#pragma unroll
+            for (int v = 1; v < 18; ++v) f[v] = (float)(R[v] * iD);
+            f[18] = (float)log10(A.a * sig);
+            const double rx[7] = {R[tf::SBX] * isc, R[tf::SBY] * isc, R[tf::SBZ] * isc, R[tf::TAUB] * isc,
+                                  R[tf::EX], R[tf::EY], R[tf::EZ]};
+            float *tg = A.ht + row * 7;
+#pragma unroll
+            for (int k = 0; k < 7; ++k) tg[k] = st == CELL_OK ? (float)((x[k] - rx[k]) * iD) : 0.0f;
+        }
+    }
+    if (A.write_all) {
+#pragma unroll
+        for (int v = 0; v < NC; ++v)
+            if (!has_source(M, v)) A.Q.p[v][idx] = R[v];
+    }
+#pragma unroll
+    for (int v = 0; v < NP; ++v) A.wout.p[v][idx] = w[v];
+    if (A.status) A.status[idx] = (int8_t)st;
+    if (A.iters) A.iters[idx] = nit;
+}
+
+// Implicit stage over every cell, ghosts included.  With a guess the cell starts there (TF:
+// at the better of guess and R_x); a failed cell is solved again from R_x.  A cell still
+// unconverged after A.cap steps is appended to the queue (one atomic per block).
 template <int M>
 __global__ __launch_bounds__(256) void k_stage(StageArgs A)
 {
@@ -222,51 +322,114 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs A)
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const int i = (int)(t % g.pitch), j = (int)(t / g.pitch);
     const bool live = i < g.nxg && j < g.nyg;
+    const long idx = (long)j * g.pitch + i;
     int nit = 0, cit = 0, rit = 0, st = CELL_OK;
+    bool push = false;
+    double x[NX], w[NP];
     if (live) {
-        const long idx = (long)j * g.pitch + i;
         const double sig = cell_sigma(A.P, idx);
-        double R[NC], w[NP], x[NX];
+        double R[NC];
 #pragma unroll
         for (int v = 0; v < NC; ++v) R[v] = A.R.p[v][idx];
 #pragma unroll
         for (int v = 0; v < NP; ++v) w[v] = A.win.p[v][idx];
-        const double aK = 1.0 / (1.0 + A.a * A.P.kappa);
-        if constexpr (M == 0) {
-            const CPlanes &X0 = A.use_guess ? A.guess : A.R;
-            x[0] = X0.p[sf::EX][idx]; x[1] = X0.p[sf::EY][idx]; x[2] = X0.p[sf::EZ][idx];
-            st = sf_stage(R, A.a, sig, A.P, x, w, nit, cit, rit);
-            A.Q.p[sf::EX][idx] = x[0]; A.Q.p[sf::EY][idx] = x[1]; A.Q.p[sf::EZ][idx] = x[2];
-            A.Q.p[sf::PHI][idx] = R[sf::PHI] * aK;
-            A.Q.p[sf::PSI][idx] = (R[sf::PSI] + A.a * R[sf::RHOE]) * aK;
-        } else {
-            const CPlanes &X0 = A.use_guess ? A.guess : A.R;
-            const double isc = 1.0 / fabs(A.P.mu1);
-            x[0] = X0.p[tf::SBX][idx] * isc; x[1] = X0.p[tf::SBY][idx] * isc; x[2] = X0.p[tf::SBZ][idx] * isc;
-            x[3] = X0.p[tf::TAUB][idx] * isc;
-            x[4] = X0.p[tf::EX][idx]; x[5] = X0.p[tf::EY][idx]; x[6] = X0.p[tf::EZ][idx];
-            st = tf_stage(R, A.a, sig, A.P, x, w, nit, cit, rit);
-            const double sc = fabs(A.P.mu1);
-            A.Q.p[tf::SBX][idx] = x[0] * sc; A.Q.p[tf::SBY][idx] = x[1] * sc; A.Q.p[tf::SBZ][idx] = x[2] * sc;
-            A.Q.p[tf::TAUB][idx] = x[3] * sc;
-            A.Q.p[tf::EX][idx] = x[4]; A.Q.p[tf::EY][idx] = x[5]; A.Q.p[tf::EZ][idx] = x[6];
-            A.Q.p[tf::PHI][idx] = R[tf::PHI] * aK;
-            A.Q.p[tf::PSI][idx] = (R[tf::PSI] + A.a * R[tf::DB]) * aK;
-        }
-        if (A.write_all) {
+        for (int attempt = A.use_guess ? 0 : 1;; ++attempt) {
+            stage_start<M>(A, idx, attempt == 0, x);
+            if (attempt == 1 && A.use_guess)
 #pragma unroll
-            for (int v = 0; v < NC; ++v)
-                if (!has_source(M, v)) A.Q.p[v][idx] = R[v];
+                for (int v = 0; v < NP; ++v) w[v] = A.win.p[v][idx];
+            st = stage_solve<M>(R, A, sig, A.P, x, w, nit, cit, rit, attempt == 0, A.cap);
+            if (st == CELL_OK || st == CELL_QUEUED || attempt == 1) break;
         }
+        push = st == CELL_QUEUED;
+        if (!push) stage_write<M>(A, idx, i, j, R, x, w, st, nit, sig);
+    }
+    if (A.cap < A.P.max_newton) {
+        // block-aggregated append: wave ballots, per-wave counts in LDS, one atomic
+        __shared__ int s_wc[4];
+        __shared__ int s_base;
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        const unsigned long long mask = __ballot(push);
+        if (lane == 0) s_wc[wave] = __popcll(mask);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const int tot = s_wc[0] + s_wc[1] + s_wc[2] + s_wc[3];
+            s_base = tot ? (int)atomicAdd(A.qcount, (unsigned)tot) : 0;
+        }
+        __syncthreads();
+        if (push) {
+            int e = s_base;
+            for (int wv = 0; wv < wave; ++wv) e += s_wc[wv];
+            e += __popcll(mask & ((1ull << lane) - 1ull));
+            // the queue holds every cell of the grid, so e < qcap
+            A.qidx[e] = (int)idx;
+            A.qit[e] = nit;
 #pragma unroll
-        for (int v = 0; v < NP; ++v) A.wout.p[v][idx] = w[v];
-        if (A.status) A.status[idx] = (int8_t)st;
-        if (A.iters) A.iters[idx] = nit;
+            for (int k = 0; k < NX; ++k) A.qx[(long)k * A.qcap + e] = x[k];
+            A.qp[e] = w[4];
+            if constexpr (M == 1) A.qp[(long)A.qcap + e] = w[9];
+        }
     }
     if (A.stats) {
         const bool c = live && is_interior(g, i, j);
-        stats_block_add(A.stats, c, c ? nit : 0, c ? nit : 0, c ? cit : 0, c && st != CELL_OK, c ? rit : 0);
+        stats_block_add(A.stats, c, c ? nit : 0, c && !push ? nit : 0, c ? cit : 0, c && !push && st != CELL_OK,
+                        c ? rit : 0);
     }
+}
+
+// Finish the queued cells in full wavefronts: each thread resumes one entry from its saved
+// unknowns and pressures with the Newton steps it has left.  Sized for the largest queue;
+// blocks past the tail exit at once.
+template <int M>
+__global__ __launch_bounds__(256) void k_drain(StageArgs A)
+{
+    constexpr int NC = Model<M>::NC, NP = Model<M>::NP, NX = Model<M>::NX;
+    const int tail = (int)min(*A.qcount, (unsigned)A.qcap);
+    if ((int)(blockIdx.x * blockDim.x) >= tail) return;   // whole block past the tail
+    const int e = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const Geo &g = A.g;
+    int nit = 0, cit = 0, rit = 0, st = CELL_OK, done = 0;
+    bool interior = false;
+    if (e < tail) {
+        const long idx = A.qidx[e];
+        const int i = (int)(idx % g.pitch), j = (int)(idx / g.pitch);
+        interior = is_interior(g, i, j);
+        done = A.qit[e];
+        const double sig = cell_sigma(A.P, idx);
+        double R[NC], x[NX], w[NP];
+#pragma unroll
+        for (int v = 0; v < NC; ++v) R[v] = A.R.p[v][idx];
+#pragma unroll
+        for (int v = 0; v < NP; ++v) w[v] = A.win.p[v][idx];
+#pragma unroll
+        for (int k = 0; k < NX; ++k) x[k] = A.qx[(long)k * A.qcap + e];
+        w[4] = A.qp[e];
+        if constexpr (M == 1) w[9] = A.qp[(long)A.qcap + e];
+        Phys P = A.P;
+        P.max_newton = max(1, A.P.max_newton - done);
+        for (int attempt = 0;; ++attempt) {
+            if (attempt == 1) {
+                // a guessed start led nowhere: the plain guess with the full step budget
+                stage_start<M>(A, idx, false, x);
+#pragma unroll
+                for (int v = 0; v < NP; ++v) w[v] = A.win.p[v][idx];
+                P.max_newton = A.P.max_newton;
+            }
+            st = stage_solve<M>(R, A, sig, P, x, w, nit, cit, rit, false, 1 << 30);
+            if (st == CELL_OK || !A.use_guess || attempt == 1) break;
+        }
+        stage_write<M>(A, idx, i, j, R, x, w, st, done + nit, sig);
+    }
+    // the cell was counted by k_stage; iterations, the maximum and failures are added here
+    if (A.stats) {
+        const bool c = e < tail && interior;
+        stats_block_add(A.stats, 0u, c ? nit : 0, c ? done + nit : 0, c ? cit : 0, c && st != CELL_OK, c ? rit : 0);
+    }
+}
+
+static __global__ void k_qreset(unsigned *count)
+{
+    if (threadIdx.x == 0) *count = 0u;
 }
 
 // ---------------------------------------------------------------------------------------

@@ -23,7 +23,8 @@ constexpr int NP = 10;
 }  // namespace tf
 
 enum CellStatus { CELL_OK = 0, CELL_C2P_NOCONV = 1, CELL_C2P_UNPHYS = 2, CELL_NEWTON_NOCONV = 3,
-                  CELL_LINESEARCH = 4 };
+                  CELL_LINESEARCH = 4,
+                  CELL_QUEUED = 5 };  // internal: stopped unconverged at the step cap, to be resumed
 
 // Per-launch physics constants (by value in every kernel).
 struct Phys {

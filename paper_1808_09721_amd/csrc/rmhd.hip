@@ -8,6 +8,7 @@
 #include <string>
 
 #include "kernels.hpp"
+#include "mlp.hpp"
 
 // =======================================================================================
 // host side
@@ -29,6 +30,17 @@ struct rmhd_ctx {
     int8_t *status;   // one plane
     int32_t *iters;   // one plane
     unsigned long long *stats;  // STATS_SLOTS x STATS_STRIDE counters
+    // learned starting guess (two fluid): network, and the seven planes it writes
+    const rmhd_mlp *mlp;
+    double *guess;
+    // harvest of (features, target) rows
+    float *hx, *ht;
+    long hcap, hcount;
+    // convergence-compacted queue of the implicit stage (one entry per cell at most)
+    int cap;
+    int *qidx, *qit;
+    double *qx, *qp;
+    unsigned *qcount;
     // per-kernel event timing of rmhd_imex_step
     int timing;
     hipEvent_t ev[10];
@@ -134,6 +146,15 @@ extern "C" int rmhd_create(const rmhd_params *p, void *stream, rmhd_ctx **out)
     if (e == hipSuccess) e = hipMalloc((void **)&c->acc, pl * L.ncons);
     if (e == hipSuccess) e = hipMalloc((void **)&c->status, (size_t)L.plane);
     if (e == hipSuccess) e = hipMalloc((void **)&c->iters, (size_t)L.plane * sizeof(int32_t));
+    const int nx_unk = p->model == RMHD_SINGLE_FLUID ? 3 : 7;
+    c->cap = 1;
+    if (e == hipSuccess) e = hipMalloc((void **)&c->qidx, (size_t)L.plane * 2 * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc((void **)&c->qx, pl * (nx_unk + 2));
+    if (e == hipSuccess) e = hipMalloc((void **)&c->qcount, 256);
+    if (e == hipSuccess) {
+        c->qit = c->qidx + L.plane;
+        c->qp = c->qx + (size_t)nx_unk * L.plane;
+    }
     const size_t stats_bytes = (size_t)STATS_SLOTS * STATS_STRIDE * sizeof(unsigned long long);
     if (e == hipSuccess) e = hipMalloc((void **)&c->stats, stats_bytes);
     if (e == hipSuccess) e = hipMemsetAsync(c->stats, 0, stats_bytes, c->stream);
@@ -159,6 +180,10 @@ extern "C" void rmhd_destroy(rmhd_ctx *c)
     hipFree(c->status);
     hipFree(c->iters);
     hipFree(c->stats);
+    hipFree(c->guess);
+    hipFree(c->qidx);
+    hipFree(c->qx);
+    hipFree(c->qcount);
     delete c;
 }
 
@@ -170,13 +195,45 @@ static int launch_bc(rmhd_ctx *c, double *arr, int nvar)
     return hip_check(c, hipGetLastError(), "k_bc launch");
 }
 
+template <int M>
+static int launch_stage_m(rmhd_ctx *c, StageArgs B)
+{
+    B.cap = c->cap;
+    B.qcap = (int)c->lay.plane;
+    B.qidx = c->qidx;
+    B.qit = c->qit;
+    B.qx = c->qx;
+    B.qp = c->qp;
+    B.qcount = c->qcount;
+    const bool queue = B.cap < c->prm.max_newton_iter;
+    if (queue) hipLaunchKernelGGL(k_qreset, dim3(1), dim3(64), 0, c->stream, c->qcount);
+    hipLaunchKernelGGL(k_stage<M>, cells_grid(c), dim3(256), 0, c->stream, B);
+    if (queue) hipLaunchKernelGGL(k_drain<M>, cells_grid(c), dim3(256), 0, c->stream, B);
+    return hip_check(c, hipGetLastError(), "k_stage launch");
+}
+
 static int launch_stage(rmhd_ctx *c, const StageArgs &A)
 {
-    if (c->prm.model == RMHD_SINGLE_FLUID)
-        hipLaunchKernelGGL(k_stage<0>, cells_grid(c), dim3(256), 0, c->stream, A);
-    else
-        hipLaunchKernelGGL(k_stage<1>, cells_grid(c), dim3(256), 0, c->stream, A);
-    return hip_check(c, hipGetLastError(), "k_stage launch");
+    if (c->prm.model == RMHD_SINGLE_FLUID) return launch_stage_m<0>(c, A);
+    StageArgs B = A;
+    // learned starting point, unless the caller gave one
+    if (c->mlp && !A.use_guess) {
+        Planes G{};
+        int k = 0;
+        for (int v : {tf::SBX, tf::SBY, tf::SBZ, tf::TAUB, tf::EX, tf::EY, tf::EZ}) G.p[v] = c->guess + (k++) * c->lay.plane;
+        if (mlp_launch_guess(c->mlp, c->stream, A.R, G, c->geo, c->phys, A.a))
+            return hip_check(c, hipGetLastError(), "k_infer launch");
+        B.guess = as_const(G);
+        B.use_guess = 1;
+    }
+    const long cells = (long)c->prm.nx * c->prm.ny;
+    if (c->hx && c->hcount + cells <= c->hcap) {
+        B.hx = c->hx;
+        B.ht = c->ht;
+        B.hbase = c->hcount;
+        c->hcount += cells;
+    }
+    return launch_stage_m<1>(c, B);
 }
 
 template <int M>
@@ -415,3 +472,42 @@ extern "C" int rmhd_get_stats(rmhd_ctx *c, rmhd_stats *out, int reset)
 }
 
 extern "C" const char *rmhd_last_error(const rmhd_ctx *c) { return c ? c->err.c_str() : g_err.c_str(); }
+
+// ---- learned starting guess and harvest (include/rmhd_mlp.h) ---------------------------
+extern "C" int rmhd_set_harvest(rmhd_ctx *c, float *X, float *T, long capacity)
+{
+    if (!c) return fail(c, RMHD_EINVAL, "rmhd_set_harvest: NULL context");
+    if (c->prm.model != RMHD_TWO_FLUID) return fail(c, RMHD_EINVAL, "rmhd_set_harvest: two-fluid contexts only");
+    if ((X == nullptr) != (T == nullptr)) return fail(c, RMHD_EINVAL, "rmhd_set_harvest: give both arrays or neither");
+    if (X && capacity < 0) return fail(c, RMHD_EINVAL, "rmhd_set_harvest: capacity must be >= 0");
+    c->hx = X;
+    c->ht = T;
+    c->hcap = X ? capacity : 0;
+    c->hcount = 0;
+    return RMHD_OK;
+}
+
+extern "C" long rmhd_harvest_count(const rmhd_ctx *c) { return c ? c->hcount : 0; }
+
+extern "C" int rmhd_set_guess_model(rmhd_ctx *c, const rmhd_mlp *m)
+{
+    if (!c) return fail(c, RMHD_EINVAL, "rmhd_set_guess_model: NULL context");
+    if (c->prm.model != RMHD_TWO_FLUID) return fail(c, RMHD_EINVAL, "rmhd_set_guess_model: two-fluid contexts only");
+    if (m && !c->guess) {
+        const hipError_t e = hipMalloc(&c->guess, sizeof(double) * 7 * c->lay.plane);
+        if (e != hipSuccess) {
+            c->guess = nullptr;
+            return fail(c, e == hipErrorOutOfMemory ? RMHD_ENOMEM : RMHD_EHIP, "rmhd_set_guess_model: guess planes");
+        }
+    }
+    c->mlp = m;
+    return RMHD_OK;
+}
+
+extern "C" int rmhd_set_newton_cap(rmhd_ctx *c, int cap)
+{
+    if (!c) return fail(c, RMHD_EINVAL, "rmhd_set_newton_cap: NULL context");
+    if (cap < 1) return fail(c, RMHD_EINVAL, "rmhd_set_newton_cap: cap must be >= 1");
+    c->cap = cap;
+    return RMHD_OK;
+}

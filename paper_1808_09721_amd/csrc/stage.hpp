@@ -175,8 +175,10 @@ __device__ __forceinline__ bool inverse3(const double (&A)[3][3], double (&Ai)[3
 // entry, solution on exit; w: pressure guess in w[4] on entry, primitives on exit.
 // The polishing step after convergence reuses the last Jacobian (its change over the last
 // step is of the order of that step, so the polished iterate still sits at round-off).
+// cap: Newton steps allowed from unconverged iterates in this call; a cell still unconverged
+// after them returns CELL_QUEUED with x and w (pressure) ready for a later call to resume.
 __device__ inline int sf_stage(const double *R, double a, double sig, const Phys &P, double (&x)[3], double *w,
-                               int &newton_it, int &c2p_it, int &res_it)
+                               int &newton_it, int &c2p_it, int &res_it, int cap = 1 << 30)
 {
     SFCell c;
     c.D = R[sf::D];
@@ -202,6 +204,7 @@ __device__ inline int sf_stage(const double *R, double a, double sig, const Phys
         for (int it = 0; it < P.max_newton; ++it) {
             const double nrm = maxabs(G);
             const bool conv = nrm <= target;
+            if (!conv && it >= cap) { st = CELL_QUEUED; break; }
             if (!conv || !have_J) {
                 double A[3][3];
                 sf_jacobian(c, x, r, P, A);
@@ -348,9 +351,11 @@ __device__ __forceinline__ void tf_jacobian(const TFCell &c, const double (&x)[7
 }
 
 // Solve one two-fluid cell.  x: start (scaled unknowns) on entry, solution on exit;
-// w: pressure guesses w[4], w[9] on entry, primitives on exit.
+// w: pressure guesses w[4], w[9] on entry, primitives on exit.  alt: optional second start;
+// Newton begins at whichever of x and alt has the smaller residual.  cap: as for sf_stage.
 __device__ inline int tf_stage(const double *R, double a, double sig, const Phys &P, double (&x)[7], double *w,
-                               int &newton_it, int &c2p_it, int &res_it)
+                               int &newton_it, int &c2p_it, int &res_it, const double *alt = nullptr,
+                               int cap = 1 << 30)
 {
     TFCell c;
     c.D = R[tf::D];
@@ -374,6 +379,22 @@ __device__ inline int tf_stage(const double *R, double a, double sig, const Phys
     double pg[2] = {w[4], w[9]};
     res_it = 1;
     int st = tf_residual(c, x, pg, P, G, r, Eh, c2p_it);
+    if (alt) {
+        double xa[7], Ga[7], Eha[2];
+        Root ra[2];
+#pragma unroll
+        for (int i = 0; i < 7; ++i) xa[i] = alt[i];
+        ++res_it;
+        if (tf_residual(c, xa, pg, P, Ga, ra, Eha, c2p_it) == CELL_OK && (st != CELL_OK || maxabs(Ga) < maxabs(G))) {
+#pragma unroll
+            for (int i = 0; i < 7; ++i) { x[i] = xa[i]; G[i] = Ga[i]; }
+            r[0] = ra[0];
+            r[1] = ra[1];
+            Eh[0] = Eha[0];
+            Eh[1] = Eha[1];
+            st = CELL_OK;
+        }
+    }
     if (st == CELL_OK) {
         double rx = 0.0;
         rx = fmax(rx, fabs(c.RSb.x / c.sc)); rx = fmax(rx, fabs(c.RSb.y / c.sc)); rx = fmax(rx, fabs(c.RSb.z / c.sc));
@@ -387,6 +408,7 @@ __device__ inline int tf_stage(const double *R, double a, double sig, const Phys
         for (int it = 0; it < P.max_newton; ++it) {
             const double nrm = maxabs(G);
             const bool conv = nrm <= target;
+            if (!conv && it >= cap) { st = CELL_QUEUED; break; }
             if (!conv || !have_J) {
                 tf_jacobian(c, x, r, P, A);
                 if (!lu_factor<7>(A, swaps)) { st = CELL_LINESEARCH; break; }

@@ -59,10 +59,15 @@ class rmhd_batch_tuning(ctypes.Structure):
 
 
 EXPORTS = ["rmhd_layout_of", "rmhd_create", "rmhd_destroy", "rmhd_init_state", "rmhd_cons2prim", "rmhd_F",
-           "rmhd_implicit_stage", "rmhd_imex_step", "rmhd_dt", "rmhd_get_stats", "rmhd_set_timing",
+           "rmhd_implicit_stage", "rmhd_imex_step", "rmhd_dt", "rmhd_get_stats", "rmhd_set_newton_cap", "rmhd_set_timing",
            "rmhd_get_timing", "rmhd_last_error",
            "rmhd_batch_create", "rmhd_batch_destroy", "rmhd_batch_step", "rmhd_batch_autotune",
-           "rmhd_batch_set_tuning", "rmhd_batch_get_tuning", "rmhd_batch_get_stats", "rmhd_batch_last_error"]
+           "rmhd_batch_set_tuning", "rmhd_batch_get_tuning", "rmhd_batch_get_stats", "rmhd_batch_last_error",
+           "rmhd_mlp_create", "rmhd_mlp_destroy", "rmhd_mlp_get_params", "rmhd_mlp_get_norm", "rmhd_mlp_set_norm",
+           "rmhd_mlp_fit_norm", "rmhd_mlp_forward", "rmhd_mlp_loss_grad", "rmhd_mlp_train_step", "rmhd_mlp_train",
+           "rmhd_mlp_steps", "rmhd_mlp_last_error", "rmhd_set_harvest", "rmhd_harvest_count", "rmhd_set_guess_model"]
+
+MLP_NIN, MLP_NHID, MLP_NOUT, MLP_NPARAMS, MLP_NNORM, MLP_MAX_BATCH = 19, 64, 7, 5895, 52, 65536
 
 _lib = None
 
@@ -87,6 +92,7 @@ def lib() -> ctypes.CDLL:
             "rmhd_imex_step": (ctypes.c_int, [vp, ctypes.c_double, dp, dp]),
             "rmhd_dt": (ctypes.c_double, [vp]),
             "rmhd_get_stats": (ctypes.c_int, [vp, ctypes.POINTER(rmhd_stats), ctypes.c_int]),
+            "rmhd_set_newton_cap": (ctypes.c_int, [vp, ctypes.c_int]),
             "rmhd_set_timing": (ctypes.c_int, [vp, ctypes.c_int]),
             "rmhd_get_timing": (ctypes.c_int, [vp, ctypes.POINTER(rmhd_timing), ctypes.c_int]),
             "rmhd_last_error": (ctypes.c_char_p, [vp]),
@@ -98,6 +104,23 @@ def lib() -> ctypes.CDLL:
             "rmhd_batch_get_tuning": (ctypes.c_int, [vp, ctypes.POINTER(rmhd_batch_tuning)]),
             "rmhd_batch_get_stats": (ctypes.c_int, [vp, ctypes.POINTER(rmhd_stats), ctypes.c_int]),
             "rmhd_batch_last_error": (ctypes.c_char_p, [vp]),
+            "rmhd_mlp_create": (ctypes.c_int, [vp, vp, ctypes.POINTER(vp)]),
+            "rmhd_mlp_destroy": (None, [vp]),
+            "rmhd_mlp_get_params": (ctypes.c_int, [vp, vp]),
+            "rmhd_mlp_get_norm": (ctypes.c_int, [vp, vp]),
+            "rmhd_mlp_set_norm": (ctypes.c_int, [vp, vp]),
+            "rmhd_mlp_fit_norm": (ctypes.c_int, [vp, vp, vp, ctypes.c_long]),
+            "rmhd_mlp_forward": (ctypes.c_int, [vp, vp, ctypes.c_long, vp, ctypes.c_int]),
+            "rmhd_mlp_loss_grad": (ctypes.c_int, [vp, vp, vp, ctypes.c_long, vp, vp]),
+            "rmhd_mlp_train_step": (ctypes.c_int, [vp, vp, vp, ctypes.c_long, ctypes.c_long, ctypes.c_long,
+                                                   ctypes.c_int, ctypes.c_float, vp]),
+            "rmhd_mlp_train": (ctypes.c_int, [vp, vp, vp, ctypes.c_long, ctypes.c_int, ctypes.c_int, ctypes.c_float,
+                                              ctypes.c_float, ctypes.c_ulonglong, vp]),
+            "rmhd_mlp_steps": (ctypes.c_long, [vp]),
+            "rmhd_mlp_last_error": (ctypes.c_char_p, [vp]),
+            "rmhd_set_harvest": (ctypes.c_int, [vp, vp, vp, ctypes.c_long]),
+            "rmhd_harvest_count": (ctypes.c_long, [vp]),
+            "rmhd_set_guess_model": (ctypes.c_int, [vp, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -186,6 +209,10 @@ def rmhd_get_stats(ctx, reset: bool = False) -> dict:
     return {k: getattr(s, k) for k, _ in rmhd_stats._fields_}
 
 
+def rmhd_set_newton_cap(ctx, cap: int):
+    _check(lib().rmhd_set_newton_cap(ctx, int(cap)), ctx)
+
+
 def rmhd_set_timing(ctx, enable: bool):
     _check(lib().rmhd_set_timing(ctx, int(enable)), ctx)
 
@@ -241,6 +268,17 @@ class Grid:
     def download_all(self, t) -> np.ndarray:
         return self.all_view(t).cpu().numpy().copy()
 
+    def sigma_plane(self, sigma_interior: np.ndarray):
+        """Per-cell conductivity as one padded device plane, ghosts copied as the boundary
+        condition copies state (periodic wrap or outflow edge)."""
+        import torch
+        a = np.asarray(sigma_interior, dtype=np.float64).reshape(self.ny if self.ndim == 2 else 1, self.nx)
+        mode = "wrap" if self.params.bc == BC_PERIODIC else "edge"
+        full = np.pad(a, ((2, 2) if self.ndim == 2 else (0, 0), (2, 2)), mode=mode)
+        t = self.alloc(1)
+        self.all_view(t)[...] = torch.from_numpy(full[None]).cuda()
+        return t
+
 
 class Solver:
     """Convenience owner of one context and its geometry."""
@@ -248,6 +286,16 @@ class Solver:
     def __init__(self, params: rmhd_params, stream=None):
         self.grid = Grid(params)
         self.ctx = rmhd_create(params, stream)
+
+    @classmethod
+    def for_workload(cls, wl, stream=None, **param_kw):
+        """A solver for a workload, with its per-cell conductivity plane (if any) on the device."""
+        sigma = None
+        if wl.sigma_cell is not None:
+            sigma = Grid(params_from(wl, **param_kw)).sigma_plane(wl.sigma_cell)
+        s = cls(params_from(wl, sigma_cell=sigma, **param_kw), stream)
+        s._sigma_plane = sigma    # kept alive with the context
+        return s
 
     def close(self):
         if self.ctx is not None:
@@ -280,6 +328,202 @@ class Solver:
 
     def stats(self, reset: bool = False) -> dict:
         return rmhd_get_stats(self.ctx, reset)
+
+    def set_newton_cap(self, cap: int):
+        """Newton steps from unconverged iterates before a cell is queued (>= max: no queue)."""
+        rmhd_set_newton_cap(self.ctx, cap)
+
+    def set_harvest(self, X, T):
+        """Harvest (features, target) rows of every following implicit stage into the float32
+        CUDA tensors X[cap, 19] and T[cap, 7] (None stops)."""
+        rmhd_set_harvest(self.ctx, X, T)
+
+    def harvest_count(self) -> int:
+        return rmhd_harvest_count(self.ctx)
+
+    def set_guess_model(self, mlp):
+        """Start every following implicit stage from the learned guess of ``mlp`` (None: plain)."""
+        rmhd_set_guess_model(self.ctx, mlp)
+
+
+# ---------------------------------------------------------------------------------------------
+# learned starting guess (include/rmhd_mlp.h)
+# ---------------------------------------------------------------------------------------------
+def _mcheck(rc: int, m):
+    if rc != 0:
+        msg = lib().rmhd_mlp_last_error(m)
+        raise RmhdError(f"librmhd mlp error {rc}: {msg.decode() if msg else ''}")
+
+
+def _hostf(arr, n):
+    a = np.ascontiguousarray(arr, dtype=np.float32)
+    if a.size != n:
+        raise RmhdError(f"expected {n} floats, got {a.size}")
+    return a
+
+
+def _f32(t, cols=None):
+    if t is None:
+        return None
+    import torch
+    if t.dtype != torch.float32:
+        raise RmhdError("sample arrays must be float32")
+    if cols is not None and (t.dim() != 2 or t.shape[1] != cols):
+        raise RmhdError(f"sample arrays must have shape [n, {cols}]")
+    return _ptr(t)
+
+
+def rmhd_mlp_create(params, stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    a = _hostf(params, MLP_NPARAMS)
+    m = ctypes.c_void_p()
+    rc = lib().rmhd_mlp_create(a.ctypes.data, ctypes.c_void_p(s.cuda_stream), ctypes.byref(m))
+    _mcheck(rc, None)
+    return m
+
+
+def rmhd_mlp_destroy(m):
+    lib().rmhd_mlp_destroy(m)
+
+
+def rmhd_mlp_get_params(m) -> np.ndarray:
+    out = np.zeros(MLP_NPARAMS, dtype=np.float32)
+    _mcheck(lib().rmhd_mlp_get_params(m, out.ctypes.data), m)
+    return out
+
+
+def rmhd_mlp_get_norm(m) -> np.ndarray:
+    out = np.zeros(MLP_NNORM, dtype=np.float32)
+    _mcheck(lib().rmhd_mlp_get_norm(m, out.ctypes.data), m)
+    return out
+
+
+def rmhd_mlp_set_norm(m, norm):
+    a = _hostf(norm, MLP_NNORM)
+    _mcheck(lib().rmhd_mlp_set_norm(m, a.ctypes.data), m)
+
+
+def rmhd_mlp_fit_norm(m, X, T):
+    _mcheck(lib().rmhd_mlp_fit_norm(m, _f32(X, MLP_NIN), _f32(T, MLP_NOUT), X.shape[0]), m)
+
+
+def rmhd_mlp_forward(m, X, Y, precision: int):
+    _mcheck(lib().rmhd_mlp_forward(m, _f32(X, MLP_NIN), X.shape[0], _f32(Y, MLP_NOUT), int(precision)), m)
+
+
+def rmhd_mlp_loss_grad(m, X, T, grad=None, loss=None):
+    _mcheck(lib().rmhd_mlp_loss_grad(m, _f32(X, MLP_NIN), _f32(T, MLP_NOUT), X.shape[0], _f32(grad), _f32(loss)), m)
+
+
+def rmhd_mlp_train_step(m, X, T, first: int, stride: int, batch: int, lr: float, loss=None):
+    _mcheck(lib().rmhd_mlp_train_step(m, _f32(X, MLP_NIN), _f32(T, MLP_NOUT), X.shape[0], int(first), int(stride),
+                                      int(batch), float(lr), _f32(loss)), m)
+
+
+def rmhd_mlp_train(m, X, T, batch: int, epochs: int, lr0: float, lr1: float, seed: int) -> np.ndarray:
+    hist = np.zeros(epochs, dtype=np.float32)
+    _mcheck(lib().rmhd_mlp_train(m, _f32(X, MLP_NIN), _f32(T, MLP_NOUT), X.shape[0], int(batch), int(epochs),
+                                 float(lr0), float(lr1), int(seed), hist.ctypes.data), m)
+    return hist
+
+
+def rmhd_mlp_steps(m) -> int:
+    return lib().rmhd_mlp_steps(m)
+
+
+def rmhd_set_harvest(ctx, X, T):
+    cap = 0 if X is None else X.shape[0]
+    if X is not None and (T is None or T.shape[0] != cap):
+        raise RmhdError("harvest arrays must have the same number of rows")
+    _check(lib().rmhd_set_harvest(ctx, _f32(X, MLP_NIN), _f32(T, MLP_NOUT), cap), ctx)
+
+
+def rmhd_harvest_count(ctx) -> int:
+    return lib().rmhd_harvest_count(ctx)
+
+
+def rmhd_set_guess_model(ctx, mlp):
+    _check(lib().rmhd_set_guess_model(ctx, None if mlp is None else mlp.m), ctx)
+
+
+def harvest_stages(workloads, steps: int, dt_factors=(1.0,)):
+    """Training rows of the learned guess: every workload is run for ``steps`` steps from its
+    initial state, step k with dt = dt_CFL * dt_factors[k mod len] (so the stage coefficient a
+    varies), harvesting both implicit stages of every step.  Returns float32 CUDA tensors
+    X[rows, 19], T[rows, 7]."""
+    import torch
+    rows = sum(2 * steps * wl.cells for wl in workloads)
+    X = torch.empty((rows, MLP_NIN), dtype=torch.float32, device="cuda")
+    T = torch.empty((rows, MLP_NOUT), dtype=torch.float32, device="cuda")
+    off = 0
+    for wl in workloads:
+        s = Solver.for_workload(wl)
+        c, w = s.initial_state(wl.prims, wl.EB)
+        s.set_harvest(X[off:], T[off:])
+        dt = s.dt()
+        for k in range(steps):
+            s.step(dt * dt_factors[k % len(dt_factors)], c, w)
+        off += s.harvest_count()
+        s.close()
+    if off != rows:
+        raise RmhdError(f"harvested {off} rows, expected {rows}")
+    return X, T
+
+
+class Mlp:
+    """Owner of one guess network on the device."""
+
+    def __init__(self, params, stream=None):
+        self.m = rmhd_mlp_create(params, stream)
+
+    def params(self) -> np.ndarray:
+        return rmhd_mlp_get_params(self.m)
+
+    def norm(self) -> np.ndarray:
+        return rmhd_mlp_get_norm(self.m)
+
+    def set_norm(self, norm):
+        rmhd_mlp_set_norm(self.m, norm)
+
+    def fit_norm(self, X, T):
+        rmhd_mlp_fit_norm(self.m, X, T)
+
+    def forward(self, X, precision: int = 1):
+        import torch
+        Y = torch.empty((X.shape[0], MLP_NOUT), dtype=torch.float32, device=X.device)
+        rmhd_mlp_forward(self.m, X, Y, precision)
+        return Y
+
+    def loss_grad(self, X, T):
+        import torch
+        g = torch.empty(MLP_NPARAMS, dtype=torch.float32, device=X.device)
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+        rmhd_mlp_loss_grad(self.m, X, T, g, loss)
+        return float(loss.item()), g
+
+    def train_step(self, X, T, first=0, stride=1, batch=None, lr=1e-3):
+        import torch
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+        rmhd_mlp_train_step(self.m, X, T, first, stride, batch or X.shape[0], lr, loss)
+        return loss
+
+    def train(self, X, T, batch=4096, epochs=10, lr0=3e-3, lr1=3e-4, seed=0) -> np.ndarray:
+        return rmhd_mlp_train(self.m, X, T, batch, epochs, lr0, lr1, seed)
+
+    def steps(self) -> int:
+        return rmhd_mlp_steps(self.m)
+
+    def close(self):
+        if self.m is not None:
+            rmhd_mlp_destroy(self.m)
+            self.m = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---------------------------------------------------------------------------------------------

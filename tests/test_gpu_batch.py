@@ -40,6 +40,7 @@ def rel(a, b):
 
 def plain_run(R, wl, steps):
     s = R.Solver(R.params_from(wl))
+    s.set_newton_cap(1000)    # the uninterrupted solve, no queue
     c, p = s.initial_state(wl.prims, wl.EB)
     for _ in range(steps):
         s.step(s.dt(), c, p)
@@ -67,10 +68,18 @@ def test_batch_matches_single_grid(R, plain_results, shape):
     st = B.stats()
     assert st["failures"] == 0
     assert st["stage_cells"] == 2 * 12 * sum(w.cells for w in doms)
+    # Without a Newton cap every cell runs the single-grid arithmetic: bit for bit.  A cell
+    # moved to the queue resumes from its saved unknowns and pressure with a fresh Jacobian,
+    # which agrees with the uninterrupted solve to the Newton tolerance, not bit for bit.
+    capped = shape["newton_cap"] < 50
     for d, (c_ref, p_ref) in enumerate(plain_results):
         g = B.grids[d]
-        assert rel(g.download_all(B.cons[d]), c_ref) < 1e-12, d
-        assert rel(g.download_all(B.prims[d]), p_ref) < 1e-12, d
+        if capped:
+            assert rel(g.download_all(B.cons[d]), c_ref) < 1e-9, d
+            assert rel(g.download_all(B.prims[d]), p_ref) < 1e-9, d
+        else:
+            np.testing.assert_array_equal(g.download_all(B.cons[d]), c_ref)
+            np.testing.assert_array_equal(g.download_all(B.prims[d]), p_ref)
     B.close()
 
 

@@ -251,6 +251,36 @@ def test_khi_small_ragged_tiles_100_steps(R, O):
     assert np.all(rel_linf(gp, op) < 1e-9)
 
 
+@pytest.mark.parametrize("model", [0, 1])
+def test_newton_cap_queue_agrees_with_uninterrupted_solve(R, O, model):
+    """The stage's first pass with a cap of 1 or 2 unconverged Newton steps plus the queue
+    drain, against the uncapped single pass and the oracle: same cells, same iteration
+    maximum, no failures, results within the step-parity bar."""
+    banner(f"newton cap queue model={model}")
+    wl = (WL.kelvin_helmholtz_2d(70, 37, steps=6, seed=13, sigma=1e5) if model == 0 else
+          WL.two_fluid_sheet_2d(40, 28, steps=6, seed=14, sigma_range=(1e2, 1e6)))
+    out = {}
+    for cap in (1, 2, 1000):
+        s = gpu_solver(R, wl)
+        s.set_newton_cap(cap)
+        cons, prims = s.initial_state(wl.prims, wl.EB)
+        dt = s.dt()
+        for _ in range(wl.steps):
+            s.step(dt, cons, prims)
+        out[cap] = (s.grid.download_all(cons), s.grid.download_all(prims), s.stats())
+        s.close()
+    g, oc, op = initial_state(wl)
+    advance(g, oc, op, O.dt(g, wl.cfl), steps=wl.steps)
+    ref = out[1000]
+    for cap in (1, 2):
+        c, p, st = out[cap]
+        assert st["failures"] == 0
+        assert st["stage_cells"] == ref[2]["stage_cells"] == 2 * wl.steps * wl.cells
+        assert abs(st["newton_max"] - ref[2]["newton_max"]) <= 1
+        assert np.all(rel_linf(c, ref[0]) < 1e-9) and np.all(rel_linf(p, ref[1]) < 1e-9)
+        assert np.all(rel_linf(c, oc) < 1e-9)
+
+
 def family_scale(g, c):
     """Sum of |value| per variable, shared by the components of each 3-vector (a component
     that stays at round-off level is measured against its vector's size)."""
