@@ -162,8 +162,14 @@ int rmhd_get_stats(rmhd_ctx *ctx, rmhd_stats *out, int reset);
  * cells need instead of what the slowest cell of each wavefront needs.  cap >=
  * max_newton_iter disables the queue and gives the uninterrupted solve bit for bit; a queued
  * cell resumes from its saved unknowns and pressures with a fresh Jacobian, which agrees with
- * the uninterrupted solve to the Newton tolerance.  Default 1.  cap must be >= 1. */
+ * the uninterrupted solve to the Newton tolerance.  Default: 1 for the two-fluid model, no
+ * queue for the single-fluid model.  cap must be >= 1. */
 int rmhd_set_newton_cap(rmhd_ctx *ctx, int cap);
+
+/* Rows of the 2-D flux-pass thread block: 16 (12 interior rows per 64 x 16 block) or 8
+ * (4 interior rows, more blocks and more halo work); 0 (default) = 16.  Results do not
+ * depend on it. */
+int rmhd_set_flux_rows(rmhd_ctx *ctx, int rows);
 
 /* Enable (1) or disable (0) per-kernel event timing of rmhd_imex_step.  While enabled each
  * step waits for its own kernels to finish (to read the events), so it is meant for a

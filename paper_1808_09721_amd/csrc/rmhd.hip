@@ -36,6 +36,8 @@ struct rmhd_ctx {
     // harvest of (features, target) rows
     float *hx, *ht;
     long hcap, hcount;
+    // flux tile rows (0 = default)
+    int flux_rows;
     // convergence-compacted queue of the implicit stage (one entry per cell at most)
     int cap;
     int *qidx, *qit;
@@ -147,7 +149,9 @@ extern "C" int rmhd_create(const rmhd_params *p, void *stream, rmhd_ctx **out)
     if (e == hipSuccess) e = hipMalloc((void **)&c->status, (size_t)L.plane);
     if (e == hipSuccess) e = hipMalloc((void **)&c->iters, (size_t)L.plane * sizeof(int32_t));
     const int nx_unk = p->model == RMHD_SINGLE_FLUID ? 3 : 7;
-    c->cap = 1;
+    // stage queue by default for the two-fluid stage only: its 7-unknown Newton step is
+    // costly enough to repay the second launch; the single-fluid one is not
+    c->cap = p->model == RMHD_TWO_FLUID ? 1 : 1 << 30;
     if (e == hipSuccess) e = hipMalloc((void **)&c->qidx, (size_t)L.plane * 2 * sizeof(int));
     if (e == hipSuccess) e = hipMalloc((void **)&c->qx, pl * (nx_unk + 2));
     if (e == hipSuccess) e = hipMalloc((void **)&c->qcount, 256);
@@ -244,9 +248,16 @@ static void launch_flux_m(rmhd_ctx *c, const FluxArgs &A)
         dim3 grid((c->prm.nx + (BX - 4) - 1) / (BX - 4));
         hipLaunchKernelGGL((k_flux<M, 1, BX, 1>), grid, dim3(BX, 1), 0, c->stream, A);
     } else {
-        constexpr int BX = 64, BY = 16;
-        dim3 grid((c->prm.nx + (BX - 4) - 1) / (BX - 4), (c->prm.ny + (BY - 4) - 1) / (BY - 4));
-        hipLaunchKernelGGL((k_flux<M, 2, BX, BY>), grid, dim3(BX, BY), 0, c->stream, A);
+        // 64 x 16 tiles (12 interior rows); 64 x 8 (4 rows) on request.  Measured on the
+        // 256 x 512 grid, whose 16-row tiles leave some CUs idle, 16 rows are still faster
+        // (30 us against 41 us): the 8-row tile's halo work costs more than the idle CUs.
+        constexpr int BX = 64;
+        const unsigned gx = (unsigned)((c->prm.nx + (BX - 4) - 1) / (BX - 4));
+        const int rows = c->flux_rows ? c->flux_rows : 16;
+        if (rows == 8)
+            hipLaunchKernelGGL((k_flux<M, 2, BX, 8>), dim3(gx, (c->prm.ny + 3) / 4), dim3(BX, 8), 0, c->stream, A);
+        else
+            hipLaunchKernelGGL((k_flux<M, 2, BX, 16>), dim3(gx, (c->prm.ny + 11) / 12), dim3(BX, 16), 0, c->stream, A);
     }
 }
 
@@ -509,5 +520,13 @@ extern "C" int rmhd_set_newton_cap(rmhd_ctx *c, int cap)
     if (!c) return fail(c, RMHD_EINVAL, "rmhd_set_newton_cap: NULL context");
     if (cap < 1) return fail(c, RMHD_EINVAL, "rmhd_set_newton_cap: cap must be >= 1");
     c->cap = cap;
+    return RMHD_OK;
+}
+
+extern "C" int rmhd_set_flux_rows(rmhd_ctx *c, int rows)
+{
+    if (!c) return fail(c, RMHD_EINVAL, "rmhd_set_flux_rows: NULL context");
+    if (rows != 0 && rows != 8 && rows != 16) return fail(c, RMHD_EINVAL, "rmhd_set_flux_rows: rows must be 0, 8 or 16");
+    c->flux_rows = rows;
     return RMHD_OK;
 }

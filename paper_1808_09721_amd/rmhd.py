@@ -59,7 +59,8 @@ class rmhd_batch_tuning(ctypes.Structure):
 
 
 EXPORTS = ["rmhd_layout_of", "rmhd_create", "rmhd_destroy", "rmhd_init_state", "rmhd_cons2prim", "rmhd_F",
-           "rmhd_implicit_stage", "rmhd_imex_step", "rmhd_dt", "rmhd_get_stats", "rmhd_set_newton_cap", "rmhd_set_timing",
+           "rmhd_implicit_stage", "rmhd_imex_step", "rmhd_dt", "rmhd_get_stats", "rmhd_set_newton_cap", "rmhd_set_flux_rows",
+           "rmhd_set_timing",
            "rmhd_get_timing", "rmhd_last_error",
            "rmhd_batch_create", "rmhd_batch_destroy", "rmhd_batch_step", "rmhd_batch_autotune",
            "rmhd_batch_set_tuning", "rmhd_batch_get_tuning", "rmhd_batch_get_stats", "rmhd_batch_last_error",
@@ -93,6 +94,7 @@ def lib() -> ctypes.CDLL:
             "rmhd_dt": (ctypes.c_double, [vp]),
             "rmhd_get_stats": (ctypes.c_int, [vp, ctypes.POINTER(rmhd_stats), ctypes.c_int]),
             "rmhd_set_newton_cap": (ctypes.c_int, [vp, ctypes.c_int]),
+            "rmhd_set_flux_rows": (ctypes.c_int, [vp, ctypes.c_int]),
             "rmhd_set_timing": (ctypes.c_int, [vp, ctypes.c_int]),
             "rmhd_get_timing": (ctypes.c_int, [vp, ctypes.POINTER(rmhd_timing), ctypes.c_int]),
             "rmhd_last_error": (ctypes.c_char_p, [vp]),
@@ -211,6 +213,10 @@ def rmhd_get_stats(ctx, reset: bool = False) -> dict:
 
 def rmhd_set_newton_cap(ctx, cap: int):
     _check(lib().rmhd_set_newton_cap(ctx, int(cap)), ctx)
+
+
+def rmhd_set_flux_rows(ctx, rows: int):
+    _check(lib().rmhd_set_flux_rows(ctx, int(rows)), ctx)
 
 
 def rmhd_set_timing(ctx, enable: bool):
