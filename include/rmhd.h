@@ -95,6 +95,8 @@ typedef struct rmhd_stats {
     int64_t c2p_iters;        /* primitive-recovery iterations inside them, summed */
     int32_t newton_max;       /* largest Newton iteration count of one cell */
     int32_t failures;         /* cell solves that ended with a nonzero status */
+    int64_t newton_hist[16];  /* cell solves by Newton iteration count (last bin: 15 or more) */
+    double residual_max;      /* largest final |G|_inf / max(1, |R_x|_inf) of a converged cell */
 } rmhd_stats;
 
 /* Per-kernel GPU time of rmhd_imex_step, from HIP events recorded on the context's stream
@@ -102,7 +104,8 @@ typedef struct rmhd_stats {
 typedef struct rmhd_timing {
     double stage_ms;          /* implicit-stage kernels (learned guess, solve, queue), summed */
     double flux_ms;           /* flux-divergence + combiner kernel, summed */
-    double c2p_ms;            /* primitive-recovery kernel, summed */
+    double c2p_ms;            /* separate primitive-recovery kernel, summed (0: the step
+                                 recovers the primitives inside its second flux pass) */
     int64_t stage_launches, flux_launches, c2p_launches;
     int64_t steps;
 } rmhd_timing;
@@ -187,7 +190,7 @@ const char *rmhd_last_error(const rmhd_ctx *ctx);
  * Batched form: many independent single-fluid domains of uneven size and stiffness advanced
  * by one launch per kernel of the SSP2(222) step for all of them (each domain with its own
  * grid, boundary, sigma and dt), with a convergence-compacted queue for the implicit stage
- * (cells still unconverged after newton_cap Newton iterations continue in full wavefronts),
+ * (cells still unconverged after newton_cap Newton steps continue in full wavefronts),
  * the step captured once in a HIP graph, and launch shapes chosen by rmhd_batch_autotune().
  * The method per cell is exactly the one of rmhd_imex_step (Sec. 2.2.1, Eqs. 10-11): with
  * newton_cap >= max_newton_iter the results equal rmhd_imex_step's bit for bit; a queued cell
@@ -201,7 +204,9 @@ typedef struct rmhd_batch_tuning {
                                    atomic counter, 0 = one block per 256-cell chunk */
     int32_t chunks_per_item;    /* persistent mode: 256-cell chunks per counter grab */
     int32_t persistent_blocks;  /* persistent mode: blocks in the grid */
-    int32_t newton_cap;         /* Newton iterations before a cell moves to the compacted queue
+    int32_t newton_cap;         /* Newton steps from unconverged iterates before a cell moves to
+                                   the compacted queue (a cell converged by then still takes its
+                                   polishing step)
                                    (>= max_newton_iter: no queue) */
     int32_t flux_rows;          /* rows of a 2-D flux tile block: 8 or 16 */
     int32_t use_graph;          /* 1: capture the step in a HIP graph and replay it */

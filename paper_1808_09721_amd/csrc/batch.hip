@@ -38,7 +38,7 @@ struct BatchArgs {
     int persistent;             // 1: loop over grabbed items; 0: one chunk per block
     unsigned *counters;         // [0] item head  [1] queue tail
     int phase;                  // 1 or 2 (selects the stage buffers)
-    int K;                      // Newton iterations before a cell is moved to the queue
+    int K;                      // Newton steps from unconverged iterates before a cell is queued
     int *qdom, *qidx, *qit;     // compacted queue of unconverged cells
     double *qx, *qp;            // their current unknowns (3 per entry) and pressure
     int qcap;
@@ -51,10 +51,12 @@ __device__ __forceinline__ int sf_src_slot(int v)
     return v == sf::EX ? 0 : v == sf::EY ? 1 : v == sf::EZ ? 2 : v == sf::PSI ? 3 : 4;
 }
 
-// Solve (or continue) the stage of one cell of domain D.  Returns the status; on
-// CELL_NEWTON_NOCONV with iterations left the caller queues the cell instead of writing it.
+// Solve (or continue) the stage of one cell of domain D.  First pass (resume false): at
+// most cap Newton steps from unconverged iterates; CELL_QUEUED tells the caller to queue
+// the cell.  Resumed pass: up to budget more steps, no cap.
 __device__ __forceinline__ int batch_cell(const DomainDev &D, int phase, long idx, double (&x)[3], double *w,
-                                          int cap, bool resume, int &nit, int &cit, int &rit)
+                                          int cap, int budget, bool resume, int &nit, int &cit, int &rit,
+                                          double &gres)
 {
     const Geo &g = D.g;
     (void)g;
@@ -72,9 +74,9 @@ __device__ __forceinline__ int batch_cell(const DomainDev &D, int phase, long id
         x[2] = R[sf::EZ];
     }
     Phys P = D.P;
-    P.max_newton = cap;
+    if (resume) P.max_newton = budget;
     int n = 0, c = 0, r = 0;
-    const int st = sf_stage(R, a, cell_sigma(D.P, idx), P, x, w, n, c, r);
+    const int st = sf_stage(R, a, cell_sigma(D.P, idx), P, x, w, n, c, r, resume ? 1 << 30 : cap, &gres);
     nit += n;
     cit += c;
     rit += r;
@@ -138,9 +140,9 @@ __global__ __launch_bounds__(256) void kb_stage(BatchArgs A)
         const int i = (int)(idx % g.pitch), j = (int)(idx / g.pitch);
         const bool live = idx < g.plane && i < g.nxg && j < g.nyg;
         int nit = 0, cit = 0, rit = 0, st = CELL_OK;
-        double x[3] = {0, 0, 0}, w[sf::NP] = {0, 0, 0, 0, 0};
-        if (live) st = batch_cell(D, A.phase, idx, x, w, A.K, false, nit, cit, rit);
-        const bool push = live && st == CELL_NEWTON_NOCONV && A.K < D.P.max_newton;
+        double x[3] = {0, 0, 0}, w[sf::NP] = {0, 0, 0, 0, 0}, gres = 0.0;
+        if (live) st = batch_cell(D, A.phase, idx, x, w, A.K, 0, false, nit, cit, rit, gres);
+        const bool push = live && st == CELL_QUEUED;
         if (live && !push) batch_write(D, A.phase, idx, x, w);
         // block-aggregated queue append
         const unsigned long long mask = __ballot(push);
@@ -168,7 +170,7 @@ __global__ __launch_bounds__(256) void kb_stage(BatchArgs A)
         if (A.stats) {
             const bool c = live && is_interior(g, i, j);
             stats_block_add(A.stats, c, c ? nit : 0, c ? nit : 0, c ? cit : 0, c && !push && st != CELL_OK,
-                            c ? rit : 0);
+                            c ? rit : 0, c && !push ? nit : -1, gres);
         }
         if (!A.persistent) break;
         __syncthreads();  // s_wcount / s_base are rewritten by the next chunk
@@ -184,6 +186,7 @@ __global__ __launch_bounds__(256) void kb_drain(BatchArgs A)
     if ((int)(blockIdx.x * blockDim.x) >= tail) return;   // whole block past the tail
     const bool live = e < tail;
     int nit = 0, cit = 0, rit = 0, st = CELL_OK, done_it = 0;
+    double gres = 0.0;
     bool interior = false;
     if (live) {
         const DomainDev &D = A.dom[A.qdom[e]];
@@ -191,13 +194,14 @@ __global__ __launch_bounds__(256) void kb_drain(BatchArgs A)
         interior = is_interior(D.g, (int)(idx % D.g.pitch), (int)(idx / D.g.pitch));
         double x[3] = {A.qx[3 * e], A.qx[3 * e + 1], A.qx[3 * e + 2]}, w[sf::NP] = {0, 0, 0, 0, A.qp[e]};
         done_it = A.qit[e];
-        st = batch_cell(D, A.phase, idx, x, w, max(1, D.P.max_newton - done_it), true, nit, cit, rit);
+        st = batch_cell(D, A.phase, idx, x, w, 0, max(1, D.P.max_newton - done_it), true, nit, cit, rit, gres);
         batch_write(D, A.phase, idx, x, w);
     }
     // the cell was counted by kb_stage; only iterations and failures are added here
     if (A.stats) {
         const bool c = live && interior;
-        stats_block_add(A.stats, 0u, c ? nit : 0, c ? nit + done_it : 0, c ? cit : 0, c && st != CELL_OK, c ? rit : 0);
+        stats_block_add(A.stats, 0u, c ? nit : 0, c ? nit + done_it : 0, c ? cit : 0, c && st != CELL_OK, c ? rit : 0,
+                        c ? nit + done_it : -1, gres);
     }
 }
 
@@ -443,7 +447,7 @@ extern "C" int rmhd_batch_create(const rmhd_params *domains, int n, void *stream
     b->tune.persistent = 0;
     b->tune.chunks_per_item = 16;
     b->tune.persistent_blocks = std::max(1, cus) * 4;
-    b->tune.newton_cap = 6;
+    b->tune.newton_cap = 2;
     b->tune.flux_rows = 16;
     b->tune.use_graph = 1;
     b->tune.step_ms = 0.0;
@@ -633,7 +637,7 @@ extern "C" int rmhd_batch_autotune(rmhd_batch *b, double *const *cons, double *c
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     rmhd_batch_tuning best = b->tune;
     float best_ms = 1e30f;
-    const int caps[] = {3, 6, 1 << 20};
+    const int caps[] = {1, 2, 1 << 20};
     for (int persistent = 0; persistent <= 1; ++persistent)
         for (int rows : {8, 16})
             for (int cap : caps)
@@ -665,22 +669,12 @@ extern "C" int rmhd_batch_autotune(rmhd_batch *b, double *const *cons, double *c
 extern "C" int rmhd_batch_get_stats(rmhd_batch *b, rmhd_stats *out, int reset)
 {
     if (!b || !out) return bfail(b, RMHD_EINVAL, "rmhd_batch_get_stats: NULL argument");
-    unsigned long long raw[STATS_SLOTS * STATS_STRIDE], h[6] = {0, 0, 0, 0, 0, 0};
+    unsigned long long raw[STATS_SLOTS * STATS_STRIDE];
     int rc = bcheck(b, hipMemcpyAsync(raw, b->stats, sizeof(raw), hipMemcpyDeviceToHost, b->stream), "stats copy");
     if (!rc && reset) rc = bcheck(b, hipMemsetAsync(b->stats, 0, sizeof(raw), b->stream), "stats reset");
     if (!rc) rc = bcheck(b, hipStreamSynchronize(b->stream), "stats sync");
     if (rc) return rc;
-    for (int sl = 0; sl < STATS_SLOTS; ++sl)
-        for (int k = 0; k < 6; ++k) {
-            const unsigned long long x = raw[sl * STATS_STRIDE + k];
-            h[k] = k == 4 ? std::max(h[k], x) : h[k] + x;
-        }
-    out->stage_cells = (int64_t)h[0];
-    out->newton_iters = (int64_t)h[1];
-    out->c2p_iters = (int64_t)h[2];
-    out->failures = (int32_t)h[3];
-    out->newton_max = (int32_t)h[4];
-    out->residual_evals = (int64_t)h[5];
+    stats_fold(raw, out);
     return RMHD_OK;
 }
 

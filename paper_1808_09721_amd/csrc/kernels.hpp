@@ -13,6 +13,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstring>
+
 #include "../../include/rmhd.h"
 #include "physics.hpp"
 #include "stage.hpp"
@@ -148,9 +150,12 @@ __global__ __launch_bounds__(256) void k_c2p(CPlanes cons, Planes prims, int8_t 
 // advances a grid uses this one value so that they agree bit for bit
 constexpr double SSP2_GAMMA = 0.29289321881345247559915563789515;
 
-// statistics counters: STATS_SLOTS slots of STATS_STRIDE (128 bytes) each, summed on read
+// statistics counters: STATS_SLOTS slots of STATS_STRIDE (256 bytes) each, summed on read;
+// per slot [0] cells [1] Newton steps [2] recovery iterations [3] failures [4] Newton maximum
+// [5] residual evaluations [6..21] histogram of per-cell Newton steps (last bucket: >= 15)
 constexpr int STATS_SLOTS = 64;
-constexpr int STATS_STRIDE = 16;
+constexpr int STATS_STRIDE = 32;
+constexpr int STATS_HIST = 6, STATS_NHIST = 16, STATS_RES = 22;   // [22]: largest final relative residual (bits)
 
 struct StageArgs {
     CPlanes R, guess, win;
@@ -189,24 +194,58 @@ __device__ __forceinline__ int wave_max(int v)
     for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
     return v;
 }
+__device__ __forceinline__ double wave_maxd(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
 
 // Add per-thread contributions to the statistics: wave shuffles, then LDS, then one atomic
 // per counter per block, spread over STATS_SLOTS padded slots so blocks rarely share an
 // address.  Every thread of the block must call it.
 //   cells: cells counted (0/1); nit: Newton iterations added to the sum; nmax: value for the
-//   maximum; cit: recovery iterations; fail: failed cells (0/1); rit: residual evaluations.
+//   maximum; cit: recovery iterations; fail: failed cells (0/1); rit: residual evaluations;
+//   hbin: final Newton step count of a finished counted cell, for the histogram (-1: none);
+//   gres: its final relative residual (>= 0), for the maximum.
 __device__ __forceinline__ void stats_block_add(unsigned long long *stats, unsigned cells, unsigned nit, unsigned nmax,
-                                                unsigned cit, unsigned fail, unsigned rit)
+                                                unsigned cit, unsigned fail, unsigned rit, int hbin, double gres)
 {
     __shared__ unsigned long long red[16][6];
+    __shared__ unsigned hist[16][STATS_NHIST];
+    __shared__ double gmax[16];
     unsigned long long v[6] = {cells, nit, cit, fail, nmax, rit};
 #pragma unroll
     for (int k = 0; k < 6; ++k) v[k] = k == 4 ? (unsigned long long)wave_max((int)nmax) : wave_sum(v[k]);
     const int tid = threadIdx.x + blockDim.x * threadIdx.y, wave = tid >> 6;
-    if ((tid & 63) == 0)
+    const int bin = hbin < 0 ? -1 : min(hbin, STATS_NHIST - 1);
+    unsigned hc[STATS_NHIST];
+#pragma unroll
+    for (int b = 0; b < STATS_NHIST; ++b) hc[b] = (unsigned)__popcll(__ballot(bin == b));
+    const double gw = wave_maxd(hbin < 0 || !(gres >= 0.0) ? 0.0 : gres);
+    if ((tid & 63) == 0) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) red[wave][k] = v[k];
+#pragma unroll
+        for (int b = 0; b < STATS_NHIST; ++b) hist[wave][b] = hc[b];
+        gmax[wave] = gw;
+    }
     __syncthreads();
+    if (tid == STATS_NHIST) {
+        // non-negative doubles order like their bit patterns
+        double g = 0.0;
+        const int nw = (int)((blockDim.x * blockDim.y + 63) >> 6);
+        for (int wv = 0; wv < nw; ++wv) g = fmax(g, gmax[wv]);
+        if (g > 0.0)
+            atomicMax(&stats[((blockIdx.x + gridDim.x * blockIdx.y) % STATS_SLOTS) * STATS_STRIDE + STATS_RES],
+                      (unsigned long long)__double_as_longlong(g));
+    }
+    if (tid < STATS_NHIST) {
+        unsigned long long t = 0;
+        const int nw = (int)((blockDim.x * blockDim.y + 63) >> 6);
+        for (int wv = 0; wv < nw; ++wv) t += hist[wv][tid];
+        if (t) atomicAdd(&stats[((blockIdx.x + gridDim.x * blockIdx.y) % STATS_SLOTS) * STATS_STRIDE + STATS_HIST + tid], t);
+    }
     if (tid == 0) {
         unsigned long long t[6] = {0, 0, 0, 0, 0, 0};
         const int nw = (int)((blockDim.x * blockDim.y + 63) >> 6);
@@ -245,17 +284,17 @@ __device__ __forceinline__ void stage_start(const StageArgs &A, long idx, bool g
 template <int M>
 __device__ __forceinline__ int stage_solve(const double *R, const StageArgs &A, double sig, const Phys &P,
                                           double (&x)[Model<M>::NX], double *w, int &nit, int &cit, int &rit,
-                                          bool alt, int cap)
+                                          bool alt, int cap, double &gres)
 {
     int n = 0, c = 0, r = 0, st;
     if constexpr (M == 0) {
         (void)alt;
-        st = sf_stage(R, A.a, sig, P, x, w, n, c, r, cap);
+        st = sf_stage(R, A.a, sig, P, x, w, n, c, r, cap, &gres);
     } else {
         const double isc = 1.0 / fabs(P.mu1);
         const double rx[7] = {R[tf::SBX] * isc, R[tf::SBY] * isc, R[tf::SBZ] * isc, R[tf::TAUB] * isc,
                               R[tf::EX], R[tf::EY], R[tf::EZ]};
-        st = tf_stage(R, A.a, sig, P, x, w, n, c, r, alt ? rx : nullptr, cap);
+        st = tf_stage(R, A.a, sig, P, x, w, n, c, r, alt ? rx : nullptr, cap, &gres);
     }
     nit += n;
     cit += c;
@@ -325,7 +364,7 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs A)
     const long idx = (long)j * g.pitch + i;
     int nit = 0, cit = 0, rit = 0, st = CELL_OK;
     bool push = false;
-    double x[NX], w[NP];
+    double x[NX], w[NP], gres = 0.0;
     if (live) {
         const double sig = cell_sigma(A.P, idx);
         double R[NC];
@@ -338,7 +377,7 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs A)
             if (attempt == 1 && A.use_guess)
 #pragma unroll
                 for (int v = 0; v < NP; ++v) w[v] = A.win.p[v][idx];
-            st = stage_solve<M>(R, A, sig, A.P, x, w, nit, cit, rit, attempt == 0, A.cap);
+            st = stage_solve<M>(R, A, sig, A.P, x, w, nit, cit, rit, attempt == 0, A.cap, gres);
             if (st == CELL_OK || st == CELL_QUEUED || attempt == 1) break;
         }
         push = st == CELL_QUEUED;
@@ -373,7 +412,7 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs A)
     if (A.stats) {
         const bool c = live && is_interior(g, i, j);
         stats_block_add(A.stats, c, c ? nit : 0, c && !push ? nit : 0, c ? cit : 0, c && !push && st != CELL_OK,
-                        c ? rit : 0);
+                        c ? rit : 0, c && !push ? nit : -1, gres);
     }
 }
 
@@ -390,6 +429,7 @@ __global__ __launch_bounds__(256) void k_drain(StageArgs A)
     const Geo &g = A.g;
     int nit = 0, cit = 0, rit = 0, st = CELL_OK, done = 0;
     bool interior = false;
+    double gres = 0.0;
     if (e < tail) {
         const long idx = A.qidx[e];
         const int i = (int)(idx % g.pitch), j = (int)(idx / g.pitch);
@@ -415,7 +455,7 @@ __global__ __launch_bounds__(256) void k_drain(StageArgs A)
                 for (int v = 0; v < NP; ++v) w[v] = A.win.p[v][idx];
                 P.max_newton = A.P.max_newton;
             }
-            st = stage_solve<M>(R, A, sig, P, x, w, nit, cit, rit, false, 1 << 30);
+            st = stage_solve<M>(R, A, sig, P, x, w, nit, cit, rit, false, 1 << 30, gres);
             if (st == CELL_OK || !A.use_guess || attempt == 1) break;
         }
         stage_write<M>(A, idx, i, j, R, x, w, st, done + nit, sig);
@@ -423,7 +463,8 @@ __global__ __launch_bounds__(256) void k_drain(StageArgs A)
     // the cell was counted by k_stage; iterations, the maximum and failures are added here
     if (A.stats) {
         const bool c = e < tail && interior;
-        stats_block_add(A.stats, 0u, c ? nit : 0, c ? done + nit : 0, c ? cit : 0, c && st != CELL_OK, c ? rit : 0);
+        stats_block_add(A.stats, 0u, c ? nit : 0, c ? done + nit : 0, c ? cit : 0, c && st != CELL_OK, c ? rit : 0,
+                        c ? done + nit : -1, gres);
     }
 }
 
@@ -442,7 +483,32 @@ struct FluxArgs {
     Geo g;
     Phys P;
     int fuse_bc;          // also write the ghost images of out0
+    // wnew.p[0] != nullptr: also recover the primitives of out0 (guess: w) and write them,
+    // with their ghost images, to wnew, which must not alias w (halo cells of other tiles
+    // still read w)
+    Planes wnew;
 };
+
+// Primitives of a cell's new state q (guess w), written with the ghost images of the cell.
+template <int M>
+__device__ __forceinline__ void flux_recover(const FluxArgs &A, const double *q, const double *w,
+                                            const int (&xi)[3], const int (&yj)[3], int ny_img)
+{
+    constexpr int NP = Model<M>::NP;
+    double wn[NP];
+#pragma unroll
+    for (int v = 0; v < NP; ++v) wn[v] = w[v];
+    int it = 0;
+    if constexpr (M == 0) sf_cons2prim(q, wn, A.P, it);
+    else tf_cons2prim(q, wn, A.P, it);
+#pragma unroll
+    for (int v = 0; v < NP; ++v)
+#pragma unroll
+        for (int aa = 0; aa < 3; ++aa)
+#pragma unroll
+            for (int bb = 0; bb < 3; ++bb)
+                if (bb < ny_img && xi[aa] >= 0 && yj[bb] >= 0) A.wnew.p[v][(long)yj[bb] * A.g.pitch + xi[aa]] = wn[v];
+}
 
 // WENO3 value at the downwind face of b from the upwind-ordered stencil (a, b, c):
 // candidates b + (b - a)/2 and b + (c - b)/2 with linear weights 1/3, 2/3 and
@@ -465,10 +531,11 @@ __device__ __forceinline__ void weno3_pair(double ap, double bp, double cp, doub
     vm = bm + 0.5 * (d1m + w0m * (d0m - d1m));
 }
 
-// One tile of the flux pass; every thread of a BX x BY block must call it (it holds
+// One tile of the flux pass, both directions staged through LDS (used for 1-D blocks, whose
+// rows span several wavefronts); every thread of the block must call it (it holds
 // barriers).  (bx, by) is the tile position in units of interior tiles.
 template <int M, int NDIM, int BX, int BY>
-__device__ __forceinline__ void flux_tile(const FluxArgs &A, int bx, int by)
+__device__ __forceinline__ void flux_tile_lds(const FluxArgs &A, int bx, int by)
 {
     constexpr int NC = Model<M>::NC, NP = Model<M>::NP;
     constexpr int TX = BX - 4, TY = NDIM == 2 ? BY - 4 : 1;
@@ -559,8 +626,130 @@ __device__ __forceinline__ void flux_tile(const FluxArgs &A, int bx, int by)
                 for (int bb = 0; bb < (NDIM == 2 ? 3 : 1); ++bb)
                     if (xi[aa] >= 0 && yj[bb] >= 0) A.out0.p[v][(long)yj[bb] * g.pitch + xi[aa]] = o0;
             if (two_out) A.out1.p[v][idx] = b + A.c1L * L + A.c1S * S;
+            q[v] = o0;   // this thread's own q[v] is not read again
         }
     }
+    if (A.wnew.p[0] && interior) flux_recover<M>(A, q, w, xi, yj, NDIM == 2 ? 3 : 1);
+}
+
+// Values of the lanes to the left and right in the same wavefront (a lane at the edge gets
+// its own value back; edge lanes are halo cells whose results are not used).
+__device__ __forceinline__ double from_left(double v) { return __shfl_up(v, 1); }
+__device__ __forceinline__ double from_right(double v) { return __shfl_down(v, 1); }
+
+// One tile of a 2-D flux pass with 64-wide rows: each row of the block is one wavefront, so
+// the x stencil is read from neighbouring lanes (no LDS, no barrier) and only the y stencil
+// goes through LDS, G variables per pair of barriers.  The arithmetic per face and cell is
+// that of flux_tile_lds.  Every thread of the block must call it.
+template <int M, int BY>
+__device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by)
+{
+    constexpr int NC = Model<M>::NC, NP = Model<M>::NP;
+    constexpr int BX = 64, TX = BX - 4, TY = BY - 4;
+#ifdef RMHD_FLUX_G
+    constexpr int G = RMHD_FLUX_G;
+#else
+    constexpr int G = 2;   // variables per LDS round: G x 4 x BY x 64 doubles
+#endif
+    __shared__ double sfp[G][BY][BX], sfm[G][BY][BX], shp[G][BY][BX], shm[G][BY][BX];
+    const Geo &g = A.g;
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int ii = bx * TX + tx - 2;
+    const int jj = by * TY + ty - 2;
+    const int i = min(max(ii + 2, 0), g.nxg - 1);
+    const int j = min(max(jj + 2, 0), g.nyg - 1);
+    const long idx = (long)j * g.pitch + i;
+
+    double q[NC], w[NP], fx[NC], fy[NC], src[NC];
+#pragma unroll
+    for (int v = 0; v < NC; ++v) q[v] = A.q.p[v][idx];
+#pragma unroll
+    for (int v = 0; v < NP; ++v) w[v] = A.w.p[v][idx];
+    const double sig = cell_sigma(A.P, idx);
+    if constexpr (M == 0) sf_flux_source(q, w, sig, A.P, fx, fy, src);
+    else tf_flux_source(q, w, sig, A.P, fx, fy, src);
+
+    const bool interior = tx >= 2 && tx < BX - 2 && ii < g.nx && ty >= 2 && ty < BY - 2 && jj < g.ny;
+    const bool do_y = ty >= 1 && ty <= BY - 2 && tx >= 2 && tx <= BX - 3;
+
+    // ghost images of this interior cell (fused boundary fill of out0)
+    int xi[3] = {i, -1, -1}, yj[3] = {j, -1, -1};
+    if (A.fuse_bc && interior) {
+        if (g.bc == RMHD_BC_PERIODIC) {
+            if (ii < 2) xi[1] = i + g.nx;
+            if (ii >= g.nx - 2) xi[2] = i - g.nx;
+            if (jj < 2) yj[1] = j + g.ny;
+            if (jj >= g.ny - 2) yj[2] = j - g.ny;
+        } else {
+            if (ii == 0) { xi[1] = 0; xi[2] = 1; }
+            if (ii == g.nx - 1) { xi[1] = g.nx + 2; xi[2] = g.nx + 3; }
+            if (jj == 0) { yj[1] = 0; yj[2] = 1; }
+            if (jj == g.ny - 1) { yj[1] = g.ny + 2; yj[2] = g.ny + 3; }
+        }
+    }
+    const bool has_base = A.base.p[0] != nullptr, two_out = A.out1.p[0] != nullptr;
+
+#pragma unroll
+    for (int v0 = 0; v0 < NC; v0 += G) {
+        double Lx[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            const int v = v0 + k;
+            if (v >= NC) break;
+            // x: split fluxes and both half reconstructions from the neighbouring lanes
+            const double fp = 0.5 * (fx[v] + q[v]), fm = 0.5 * (fx[v] - q[v]);
+            double vp, vm;
+            weno3_pair(from_left(fp), fp, from_right(fp), from_right(fm), fm, from_left(fm), vp, vm);
+            Lx[k] = -((vp + from_right(vm)) - (from_left(vp) + vm)) * g.idx;
+            // y: split fluxes to LDS
+            sfp[k][ty][tx] = 0.5 * (fy[v] + q[v]);
+            sfm[k][ty][tx] = 0.5 * (fy[v] - q[v]);
+        }
+        __syncthreads();
+        if (do_y) {
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                if (v0 + k >= NC) break;
+                double vp, vm;
+                weno3_pair(sfp[k][ty - 1][tx], sfp[k][ty][tx], sfp[k][ty + 1][tx], sfm[k][ty + 1][tx], sfm[k][ty][tx],
+                           sfm[k][ty - 1][tx], vp, vm);
+                shp[k][ty][tx] = vp;
+                shm[k][ty][tx] = vm;
+            }
+        }
+        __syncthreads();
+        if (interior) {
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                const int v = v0 + k;
+                if (v >= NC) break;
+                double L = Lx[k];
+                L -= ((shp[k][ty][tx] + shm[k][ty + 1][tx]) - (shp[k][ty - 1][tx] + shm[k][ty][tx])) * g.idy;
+                const double S = has_source(M, v) ? src[v] : 0.0;
+                const double b = has_base ? A.base.p[v][idx] : 0.0;
+                const double o0 = b + A.c0L * L + A.c0S * S;
+#pragma unroll
+                for (int aa = 0; aa < 3; ++aa)
+#pragma unroll
+                    for (int bb = 0; bb < 3; ++bb)
+                        if (xi[aa] >= 0 && yj[bb] >= 0) A.out0.p[v][(long)yj[bb] * g.pitch + xi[aa]] = o0;
+                if (two_out) A.out1.p[v][idx] = b + A.c1L * L + A.c1S * S;
+                q[v] = o0;   // this thread's own q[v] is not read again
+            }
+        }
+        // the next round rewrites sfp/sfm only after every thread has passed the barrier
+        // above, and shp/shm only after the next round's first barrier
+    }
+    if (A.wnew.p[0] && interior) flux_recover<M>(A, q, w, xi, yj, 3);
+}
+
+// One tile of the flux pass: 2-D tiles with 64-wide rows use the wavefront-row form,
+// everything else the LDS form.
+template <int M, int NDIM, int BX, int BY>
+__device__ __forceinline__ void flux_tile(const FluxArgs &A, int bx, int by)
+{
+    if constexpr (NDIM == 2 && BX == 64) flux_tile_rows<M, BY>(A, bx, by);
+    else flux_tile_lds<M, NDIM, BX, BY>(A, bx, by);
 }
 
 template <int M, int NDIM, int BX, int BY>
@@ -572,6 +761,26 @@ __global__ __launch_bounds__(BX *BY) void k_flux(FluxArgs A)
 // ---------------------------------------------------------------------------------------
 // host-side set-up shared by the single-grid and batched paths
 // ---------------------------------------------------------------------------------------
+// Sum the statistics slots into the public record.
+static inline void stats_fold(const unsigned long long *raw, rmhd_stats *out)
+{
+    unsigned long long h[STATS_HIST + STATS_NHIST] = {};
+    for (int sl = 0; sl < STATS_SLOTS; ++sl)
+        for (int k = 0; k < STATS_HIST + STATS_NHIST; ++k) {
+            const unsigned long long x = raw[sl * STATS_STRIDE + k];
+            h[k] = k == 4 ? (x > h[k] ? x : h[k]) : h[k] + x;
+        }
+    out->stage_cells = (int64_t)h[0];
+    out->newton_iters = (int64_t)h[1];
+    out->c2p_iters = (int64_t)h[2];
+    out->failures = (int32_t)h[3];
+    out->newton_max = (int32_t)h[4];
+    out->residual_evals = (int64_t)h[5];
+    for (int b = 0; b < STATS_NHIST; ++b) out->newton_hist[b] = (int64_t)h[STATS_HIST + b];
+    unsigned long long g = 0;
+    for (int sl = 0; sl < STATS_SLOTS; ++sl) g = raw[sl * STATS_STRIDE + STATS_RES] > g ? raw[sl * STATS_STRIDE + STATS_RES] : g;
+    memcpy(&out->residual_max, &g, sizeof(double));
+}
 static inline void layout_from(const rmhd_params *p, rmhd_layout *out)
 {
     out->nxg = p->nx + 4;

@@ -388,42 +388,37 @@ extern "C" int rmhd_imex_step(rmhd_ctx *c, double dt, double *cons, double *prim
     rc = launch_flux(c, F);
     mark(3);
     if (rc) return rc;
-    // stage 2: Q2 = R2 + gamma dt Psi(Q2), in place; primitives into the caller's array
+    // stage 2: Q2 = R2 + gamma dt Psi(Q2), in place; its primitives replace those of Q1
     S.R = cplanes_of(c->r2, L, L.ncons);
     S.win = cplanes_of(c->w1, L, L.nprim);
-    S.wout = planes_of(prims, L, L.nprim);
+    S.wout = planes_of(c->w1, L, L.nprim);
     S.Q = planes_of(c->r2, L, L.ncons);
     mark(4);
     rc = launch_stage(c, S);
     mark(5);
     if (rc) return rc;
-    // q^{n+1} = ACC + dt/2 L(Q2) + dt/2 Psi(Q2), ghosts included
+    // q^{n+1} = ACC + dt/2 L(Q2) + dt/2 Psi(Q2), ghosts included, and its primitives
+    // (recovered by the thread that forms each cell, from those of Q2)
     F.q = cplanes_of(c->r2, L, L.ncons);
-    F.w = cplanes_of(prims, L, L.nprim);
+    F.w = cplanes_of(c->w1, L, L.nprim);
     F.base = cplanes_of(c->acc, L, L.ncons);
     F.out0 = planes_of(cons, L, L.ncons);
     F.out1 = Planes{};
+    F.wnew = planes_of(prims, L, L.nprim);
     F.c0L = 0.5 * dt;
     F.c0S = 0.5 * dt;
     mark(6);
     rc = launch_flux(c, F);
     mark(7);
-    if (rc) return rc;
-    // primitives of q^{n+1} (starting from those of Q2)
-    mark(8);
-    rc = rmhd_cons2prim(c, cons, prims, nullptr, nullptr);
-    mark(9);
     if (rc || !c->timing) return rc;
-    rc = hip_check(c, hipEventSynchronize(c->ev[9]), "timing sync");
+    rc = hip_check(c, hipEventSynchronize(c->ev[7]), "timing sync");
     if (rc) return rc;
-    float ms[5];
-    for (int k = 0; k < 5; ++k) hipEventElapsedTime(&ms[k], c->ev[2 * k], c->ev[2 * k + 1]);
+    float ms[4];
+    for (int k = 0; k < 4; ++k) hipEventElapsedTime(&ms[k], c->ev[2 * k], c->ev[2 * k + 1]);
     c->times.stage_ms += ms[0] + ms[2];
     c->times.flux_ms += ms[1] + ms[3];
-    c->times.c2p_ms += ms[4];
     c->times.stage_launches += 2;
     c->times.flux_launches += 2;
-    c->times.c2p_launches += 1;
     c->times.steps += 1;
     return RMHD_OK;
 }
@@ -463,22 +458,12 @@ extern "C" double rmhd_dt(const rmhd_ctx *c) { return c ? cfl_dt(&c->prm) : 0.0;
 extern "C" int rmhd_get_stats(rmhd_ctx *c, rmhd_stats *out, int reset)
 {
     if (!c || !out) return fail(c, RMHD_EINVAL, "rmhd_get_stats: NULL argument");
-    unsigned long long raw[STATS_SLOTS * STATS_STRIDE], h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    unsigned long long raw[STATS_SLOTS * STATS_STRIDE];
     int rc = hip_check(c, hipMemcpyAsync(raw, c->stats, sizeof(raw), hipMemcpyDeviceToHost, c->stream), "stats copy");
     if (!rc && reset) rc = hip_check(c, hipMemsetAsync(c->stats, 0, sizeof(raw), c->stream), "stats reset");
     if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "stats sync");
     if (rc) return rc;
-    for (int sl = 0; sl < STATS_SLOTS; ++sl)
-        for (int k = 0; k < 6; ++k) {
-            const unsigned long long x = raw[sl * STATS_STRIDE + k];
-            h[k] = k == 4 ? (x > h[k] ? x : h[k]) : h[k] + x;
-        }
-    out->stage_cells = (int64_t)h[0];
-    out->newton_iters = (int64_t)h[1];
-    out->c2p_iters = (int64_t)h[2];
-    out->failures = (int32_t)h[3];
-    out->newton_max = (int32_t)h[4];
-    out->residual_evals = (int64_t)h[5];
+    stats_fold(raw, out);
     return RMHD_OK;
 }
 

@@ -178,7 +178,7 @@ __device__ __forceinline__ bool inverse3(const double (&A)[3][3], double (&Ai)[3
 // cap: Newton steps allowed from unconverged iterates in this call; a cell still unconverged
 // after them returns CELL_QUEUED with x and w (pressure) ready for a later call to resume.
 __device__ inline int sf_stage(const double *R, double a, double sig, const Phys &P, double (&x)[3], double *w,
-                               int &newton_it, int &c2p_it, int &res_it, int cap = 1 << 30)
+                               int &newton_it, int &c2p_it, int &res_it, int cap = 1 << 30, double *gres = nullptr)
 {
     SFCell c;
     c.D = R[sf::D];
@@ -196,8 +196,9 @@ __device__ inline int sf_stage(const double *R, double a, double sig, const Phys
     double pg = w[4];
     res_it = 1;
     int st = sf_residual(c, x, pg, P, G, r, Eh, c2p_it);
+    const double gscale = fmax(1.0, fmax(fabs(c.RE.x), fmax(fabs(c.RE.y), fabs(c.RE.z))));
     if (st == CELL_OK) {
-        const double target = P.newton_tol * fmax(1.0, fmax(fabs(c.RE.x), fmax(fabs(c.RE.y), fabs(c.RE.z))));
+        const double target = P.newton_tol * gscale;
         st = CELL_NEWTON_NOCONV;
         double Ji[3][3];
         bool have_J = false;
@@ -237,6 +238,7 @@ __device__ inline int sf_stage(const double *R, double a, double sig, const Phys
             if (conv) { st = CELL_OK; break; }
         }
     }
+    if (gres) *gres = st == CELL_OK ? maxabs(G) / gscale : 0.0;
     // primitives at the final point
     const vec3<double> E = v3(x[0], x[1], x[2]);
     vec3<double> St;
@@ -355,7 +357,7 @@ __device__ __forceinline__ void tf_jacobian(const TFCell &c, const double (&x)[7
 // Newton begins at whichever of x and alt has the smaller residual.  cap: as for sf_stage.
 __device__ inline int tf_stage(const double *R, double a, double sig, const Phys &P, double (&x)[7], double *w,
                                int &newton_it, int &c2p_it, int &res_it, const double *alt = nullptr,
-                               int cap = 1 << 30)
+                               int cap = 1 << 30, double *gres = nullptr)
 {
     TFCell c;
     c.D = R[tf::D];
@@ -395,12 +397,13 @@ __device__ inline int tf_stage(const double *R, double a, double sig, const Phys
             st = CELL_OK;
         }
     }
+    double rx = 0.0;
+    rx = fmax(rx, fabs(c.RSb.x / c.sc)); rx = fmax(rx, fabs(c.RSb.y / c.sc)); rx = fmax(rx, fabs(c.RSb.z / c.sc));
+    rx = fmax(rx, fabs(c.Rtb / c.sc));
+    rx = fmax(rx, fabs(c.RE.x)); rx = fmax(rx, fabs(c.RE.y)); rx = fmax(rx, fabs(c.RE.z));
+    const double gscale = fmax(1.0, rx);
     if (st == CELL_OK) {
-        double rx = 0.0;
-        rx = fmax(rx, fabs(c.RSb.x / c.sc)); rx = fmax(rx, fabs(c.RSb.y / c.sc)); rx = fmax(rx, fabs(c.RSb.z / c.sc));
-        rx = fmax(rx, fabs(c.Rtb / c.sc));
-        rx = fmax(rx, fabs(c.RE.x)); rx = fmax(rx, fabs(c.RE.y)); rx = fmax(rx, fabs(c.RE.z));
-        const double target = P.newton_tol * fmax(1.0, rx);
+        const double target = P.newton_tol * gscale;
         st = CELL_NEWTON_NOCONV;
         double A[7][7];
         unsigned long long swaps = 0ull;
@@ -441,6 +444,7 @@ __device__ inline int tf_stage(const double *R, double a, double sig, const Phys
             if (conv) { st = CELL_OK; break; }
         }
     }
+    if (gres) *gres = st == CELL_OK ? maxabs(G) / gscale : 0.0;
     vec3<double> Ss[2];
     double s2[2];
     tf_split(c, x, P, Ss, s2, Eh);

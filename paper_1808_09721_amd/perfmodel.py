@@ -26,7 +26,8 @@ Two-fluid implicit stage, per cell:
 
 Flux kernel, algorithmic HBM bytes per interior cell (each value read or written once):
   first pass  q^n (ncons) + Q1 source parts (nsrc) + w1 (nprim) in, R2 + ACC (2 ncons) out
-  second pass ACC (ncons) + Q2 (ncons) + w2 (nprim) in, q^{n+1} (ncons) out
+  second pass ACC (ncons) + Q2 (ncons) + w2 (nprim) in, q^{n+1} (ncons) + its primitives
+              (nprim, recovered in the same kernel) out
   F(U) alone  q (ncons) + w (nprim) in, L (ncons) out
 """
 from __future__ import annotations
@@ -56,5 +57,5 @@ def flux_bytes_per_cell(model: int, which: str) -> int:
     if which == "first":
         return 8 * (nc + ns + npr + 2 * nc)
     if which == "second":
-        return 8 * (nc + nc + npr + nc)
+        return 8 * (nc + nc + npr + nc + npr)
     return 8 * (nc + npr + nc)

@@ -43,7 +43,8 @@ class rmhd_layout(ctypes.Structure):
 class rmhd_stats(ctypes.Structure):
     _fields_ = [("stage_cells", ctypes.c_int64), ("newton_iters", ctypes.c_int64),
                 ("residual_evals", ctypes.c_int64), ("c2p_iters", ctypes.c_int64),
-                ("newton_max", ctypes.c_int32), ("failures", ctypes.c_int32)]
+                ("newton_max", ctypes.c_int32), ("failures", ctypes.c_int32),
+                ("newton_hist", ctypes.c_int64 * 16), ("residual_max", ctypes.c_double)]
 
 
 class rmhd_timing(ctypes.Structure):
@@ -205,10 +206,28 @@ def rmhd_dt(ctx) -> float:
     return lib().rmhd_dt(ctx)
 
 
+def _stats_dict(s) -> dict:
+    d = {k: getattr(s, k) for k, _ in rmhd_stats._fields_}
+    d["newton_hist"] = list(s.newton_hist)
+    return d
+
+
+def newton_percentile(stats: dict, q: float) -> int:
+    """Smallest Newton iteration count covering fraction q of the counted cell solves."""
+    h = stats["newton_hist"]
+    tot = sum(h)
+    acc = 0
+    for k, n in enumerate(h):
+        acc += n
+        if tot and acc >= q * tot:
+            return k
+    return len(h) - 1
+
+
 def rmhd_get_stats(ctx, reset: bool = False) -> dict:
     s = rmhd_stats()
     _check(lib().rmhd_get_stats(ctx, ctypes.byref(s), int(reset)), ctx)
-    return {k: getattr(s, k) for k, _ in rmhd_stats._fields_}
+    return _stats_dict(s)
 
 
 def rmhd_set_newton_cap(ctx, cap: int):
@@ -593,7 +612,7 @@ def rmhd_batch_get_tuning(b) -> dict:
 def rmhd_batch_get_stats(b, reset: bool = False) -> dict:
     s = rmhd_stats()
     _bcheck(lib().rmhd_batch_get_stats(b, ctypes.byref(s), int(reset)), b)
-    return {k: getattr(s, k) for k, _ in rmhd_stats._fields_}
+    return _stats_dict(s)
 
 
 class Batch:

@@ -280,5 +280,7 @@ def test_learned_guess_gain(R, trained):
     il = sl["newton_iters"] / sl["stage_cells"]
     print(f"newton iterations per cell and stage: plain {ip:.3f}, learned {il:.3f}", flush=True)
     assert sp["failures"] == 0 and sl["failures"] == 0
+    # equal final residual: both end every cell below the same stopping tolerance
+    assert 0.0 < sp["residual_max"] <= 1e-12 and 0.0 < sl["residual_max"] <= 1e-12
     assert rel_linf(learned, plain).max() < 1e-9
     assert il <= ip + 0.05

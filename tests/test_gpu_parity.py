@@ -272,6 +272,14 @@ def test_newton_cap_queue_agrees_with_uninterrupted_solve(R, O, model):
     g, oc, op = initial_state(wl)
     advance(g, oc, op, O.dt(g, wl.cfl), steps=wl.steps)
     ref = out[1000]
+    for cap in (1, 2, 1000):
+        # the histogram of per-cell Newton steps accounts for every counted solve
+        h = out[cap][2]["newton_hist"]
+        assert sum(h) == out[cap][2]["stage_cells"]
+        assert sum(k * n for k, n in enumerate(h)) == out[cap][2]["newton_iters"]
+        assert h[out[cap][2]["newton_max"]] > 0 and not any(h[out[cap][2]["newton_max"] + 1:])
+        # every accepted cell ends below the stopping tolerance (after its polishing step)
+        assert 0.0 < out[cap][2]["residual_max"] <= 1e-12
     for cap in (1, 2):
         c, p, st = out[cap]
         assert st["failures"] == 0
