@@ -95,6 +95,7 @@ typedef struct rmhd_stats {
     int64_t c2p_iters;        /* primitive-recovery iterations inside them, summed */
     int32_t newton_max;       /* largest Newton iteration count of one cell */
     int32_t failures;         /* cell solves that ended with a nonzero status */
+    /* collected only while detailed statistics are on (rmhd_set_stats_detail): */
     int64_t newton_hist[16];  /* cell solves by Newton iteration count (last bin: 15 or more) */
     double residual_max;      /* largest final |G|_inf / max(1, |R_x|_inf) of a converged cell */
 } rmhd_stats;
@@ -158,6 +159,10 @@ double rmhd_dt(const rmhd_ctx *ctx);
 
 /* Copy the accumulated statistics (synchronises the stream); reset != 0 zeroes them. */
 int rmhd_get_stats(rmhd_ctx *ctx, rmhd_stats *out, int reset);
+
+/* Detailed statistics (1) or the six basic counters only (0, default): the histogram and the
+ * residual maximum cost a few microseconds per stage launch. */
+int rmhd_set_stats_detail(rmhd_ctx *ctx, int detail);
 
 /* Newton steps a cell may take from unconverged iterates in the first pass of an implicit
  * stage (rmhd_implicit_stage, rmhd_imex_step) before it moves to a compacted queue that a
@@ -232,6 +237,7 @@ int rmhd_batch_get_tuning(const rmhd_batch *batch, rmhd_batch_tuning *tuning);
 
 /* Statistics of the stage solves of all domains (synchronises the stream). */
 int rmhd_batch_get_stats(rmhd_batch *batch, rmhd_stats *out, int reset);
+int rmhd_batch_set_stats_detail(rmhd_batch *batch, int detail);   /* as rmhd_set_stats_detail */
 const char *rmhd_batch_last_error(const rmhd_batch *batch);
 
 #ifdef __cplusplus

@@ -39,6 +39,7 @@ struct BatchArgs {
     unsigned *counters;         // [0] item head  [1] queue tail
     int phase;                  // 1 or 2 (selects the stage buffers)
     int K;                      // Newton steps from unconverged iterates before a cell is queued
+    int stats_detail;           // also the Newton-step histogram and the largest final residual
     int *qdom, *qidx, *qit;     // compacted queue of unconverged cells
     double *qx, *qp;            // their current unknowns (3 per entry) and pressure
     int qcap;
@@ -170,7 +171,7 @@ __global__ __launch_bounds__(256) void kb_stage(BatchArgs A)
         if (A.stats) {
             const bool c = live && is_interior(g, i, j);
             stats_block_add(A.stats, c, c ? nit : 0, c ? nit : 0, c ? cit : 0, c && !push && st != CELL_OK,
-                            c ? rit : 0, c && !push ? nit : -1, gres);
+                            c ? rit : 0, c && !push ? nit : -1, gres, A.stats_detail != 0);
         }
         if (!A.persistent) break;
         __syncthreads();  // s_wcount / s_base are rewritten by the next chunk
@@ -201,7 +202,7 @@ __global__ __launch_bounds__(256) void kb_drain(BatchArgs A)
     if (A.stats) {
         const bool c = live && interior;
         stats_block_add(A.stats, 0u, c ? nit : 0, c ? nit + done_it : 0, c ? cit : 0, c && st != CELL_OK, c ? rit : 0,
-                        c ? nit + done_it : -1, gres);
+                        c ? nit + done_it : -1, gres, A.stats_detail != 0);
     }
 }
 
@@ -304,6 +305,7 @@ struct rmhd_batch {
     int max_newton = 50;
     unsigned long long *stats = nullptr;
     rmhd_batch_tuning tune{};
+    int stats_detail = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool table_dirty = true;
@@ -465,6 +467,7 @@ static int enqueue_step(rmhd_batch *b, hipStream_t s)
     A.chunks_per_item = std::max(1, T.chunks_per_item);
     A.persistent = T.persistent;
     A.K = std::max(1, std::min(T.newton_cap, b->max_newton));
+    A.stats_detail = b->stats_detail;
     A.qdom = b->qdom;
     A.qidx = b->qidx;
     A.qit = b->qit;
@@ -561,6 +564,14 @@ extern "C" int rmhd_batch_set_tuning(rmhd_batch *b, const rmhd_batch_tuning *t)
         return bfail(b, RMHD_EINVAL, "newton_cap, chunks_per_item and persistent_blocks must be >= 1");
     b->tune = *t;
     free_graph(b);   // launch shapes changed: capture again on the next step
+    return RMHD_OK;
+}
+
+extern "C" int rmhd_batch_set_stats_detail(rmhd_batch *b, int detail)
+{
+    if (!b) return RMHD_EINVAL;
+    b->stats_detail = detail != 0;
+    free_graph(b);   // the kernels' arguments changed: capture again on the next step
     return RMHD_OK;
 }
 

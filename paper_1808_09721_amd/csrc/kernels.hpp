@@ -167,6 +167,7 @@ struct StageArgs {
     Geo g;
     Phys P;
     int write_all;
+    int stats_detail; // also the Newton-step histogram and the largest final residual
     int use_guess;    // start Newton from guess (plain guess R_x again for a cell that fails)
     // optional harvest of (features, target) rows of the learned guess, two fluid only:
     // interior cell (i, j) writes row hbase + (j - 2) nx + (i - 2)
@@ -209,7 +210,8 @@ __device__ __forceinline__ double wave_maxd(double v)
 //   hbin: final Newton step count of a finished counted cell, for the histogram (-1: none);
 //   gres: its final relative residual (>= 0), for the maximum.
 __device__ __forceinline__ void stats_block_add(unsigned long long *stats, unsigned cells, unsigned nit, unsigned nmax,
-                                                unsigned cit, unsigned fail, unsigned rit, int hbin, double gres)
+                                                unsigned cit, unsigned fail, unsigned rit, int hbin, double gres,
+                                                bool detail)
 {
     __shared__ unsigned long long red[16][6];
     __shared__ unsigned hist[16][STATS_NHIST];
@@ -218,20 +220,23 @@ __device__ __forceinline__ void stats_block_add(unsigned long long *stats, unsig
 #pragma unroll
     for (int k = 0; k < 6; ++k) v[k] = k == 4 ? (unsigned long long)wave_max((int)nmax) : wave_sum(v[k]);
     const int tid = threadIdx.x + blockDim.x * threadIdx.y, wave = tid >> 6;
-    const int bin = hbin < 0 ? -1 : min(hbin, STATS_NHIST - 1);
-    unsigned hc[STATS_NHIST];
-#pragma unroll
-    for (int b = 0; b < STATS_NHIST; ++b) hc[b] = (unsigned)__popcll(__ballot(bin == b));
-    const double gw = wave_maxd(hbin < 0 || !(gres >= 0.0) ? 0.0 : gres);
-    if ((tid & 63) == 0) {
+    if ((tid & 63) == 0)
 #pragma unroll
         for (int k = 0; k < 6; ++k) red[wave][k] = v[k];
+    if (detail) {   // block-uniform
+        const int bin = hbin < 0 ? -1 : min(hbin, STATS_NHIST - 1);
+        unsigned hc[STATS_NHIST];
 #pragma unroll
-        for (int b = 0; b < STATS_NHIST; ++b) hist[wave][b] = hc[b];
-        gmax[wave] = gw;
+        for (int b = 0; b < STATS_NHIST; ++b) hc[b] = (unsigned)__popcll(__ballot(bin == b));
+        const double gw = wave_maxd(hbin < 0 || !(gres >= 0.0) ? 0.0 : gres);
+        if ((tid & 63) == 0) {
+#pragma unroll
+            for (int b = 0; b < STATS_NHIST; ++b) hist[wave][b] = hc[b];
+            gmax[wave] = gw;
+        }
     }
     __syncthreads();
-    if (tid == STATS_NHIST) {
+    if (detail && tid == STATS_NHIST) {
         // non-negative doubles order like their bit patterns
         double g = 0.0;
         const int nw = (int)((blockDim.x * blockDim.y + 63) >> 6);
@@ -240,7 +245,7 @@ __device__ __forceinline__ void stats_block_add(unsigned long long *stats, unsig
             atomicMax(&stats[((blockIdx.x + gridDim.x * blockIdx.y) % STATS_SLOTS) * STATS_STRIDE + STATS_RES],
                       (unsigned long long)__double_as_longlong(g));
     }
-    if (tid < STATS_NHIST) {
+    if (detail && tid < STATS_NHIST) {
         unsigned long long t = 0;
         const int nw = (int)((blockDim.x * blockDim.y + 63) >> 6);
         for (int wv = 0; wv < nw; ++wv) t += hist[wv][tid];
@@ -412,7 +417,7 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs A)
     if (A.stats) {
         const bool c = live && is_interior(g, i, j);
         stats_block_add(A.stats, c, c ? nit : 0, c && !push ? nit : 0, c ? cit : 0, c && !push && st != CELL_OK,
-                        c ? rit : 0, c && !push ? nit : -1, gres);
+                        c ? rit : 0, c && !push ? nit : -1, gres, A.stats_detail != 0);
     }
 }
 
@@ -464,7 +469,7 @@ __global__ __launch_bounds__(256) void k_drain(StageArgs A)
     if (A.stats) {
         const bool c = e < tail && interior;
         stats_block_add(A.stats, 0u, c ? nit : 0, c ? done + nit : 0, c ? cit : 0, c && st != CELL_OK, c ? rit : 0,
-                        c ? done + nit : -1, gres);
+                        c ? done + nit : -1, gres, A.stats_detail != 0);
     }
 }
 
@@ -646,11 +651,7 @@ __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by
 {
     constexpr int NC = Model<M>::NC, NP = Model<M>::NP;
     constexpr int BX = 64, TX = BX - 4, TY = BY - 4;
-#ifdef RMHD_FLUX_G
-    constexpr int G = RMHD_FLUX_G;
-#else
-    constexpr int G = 2;   // variables per LDS round: G x 4 x BY x 64 doubles
-#endif
+    constexpr int G = 2;   // variables per LDS round: G x 4 x BY x 64 doubles (measured best)
     __shared__ double sfp[G][BY][BX], sfm[G][BY][BX], shp[G][BY][BX], shm[G][BY][BX];
     const Geo &g = A.g;
     const int tx = threadIdx.x, ty = threadIdx.y;
@@ -743,12 +744,13 @@ __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by
     if (A.wnew.p[0] && interior) flux_recover<M>(A, q, w, xi, yj, 3);
 }
 
-// One tile of the flux pass: 2-D tiles with 64-wide rows use the wavefront-row form,
-// everything else the LDS form.
+// One tile of the flux pass: single-fluid 2-D tiles with 64-wide rows use the wavefront-row
+// form, everything else the LDS form (measured: for the two-fluid model the row form's
+// extra live registers cost more than its saved LDS traffic).
 template <int M, int NDIM, int BX, int BY>
 __device__ __forceinline__ void flux_tile(const FluxArgs &A, int bx, int by)
 {
-    if constexpr (NDIM == 2 && BX == 64) flux_tile_rows<M, BY>(A, bx, by);
+    if constexpr (M == 0 && NDIM == 2 && BX == 64) flux_tile_rows<M, BY>(A, bx, by);
     else flux_tile_lds<M, NDIM, BX, BY>(A, bx, by);
 }
 

@@ -36,8 +36,8 @@ struct rmhd_ctx {
     // harvest of (features, target) rows
     float *hx, *ht;
     long hcap, hcount;
-    // flux tile rows (0 = default)
-    int flux_rows;
+    // flux tile rows (0 = default); detailed statistics (histogram, largest residual)
+    int flux_rows, stats_detail;
     // convergence-compacted queue of the implicit stage (one entry per cell at most)
     int cap;
     int *qidx, *qit;
@@ -203,6 +203,7 @@ template <int M>
 static int launch_stage_m(rmhd_ctx *c, StageArgs B)
 {
     B.cap = c->cap;
+    B.stats_detail = c->stats_detail;
     B.qcap = (int)c->lay.plane;
     B.qidx = c->qidx;
     B.qit = c->qit;
@@ -388,10 +389,13 @@ extern "C" int rmhd_imex_step(rmhd_ctx *c, double dt, double *cons, double *prim
     rc = launch_flux(c, F);
     mark(3);
     if (rc) return rc;
-    // stage 2: Q2 = R2 + gamma dt Psi(Q2), in place; its primitives replace those of Q1
+    // stage 2: Q2 = R2 + gamma dt Psi(Q2), in place.  Single fluid: its primitives replace
+    // those of Q1 (the second flux pass reads them there and writes the new ones to the
+    // caller's array); two fluid: into the caller's array, recovered over by k_c2p.
+    const bool fused = M == RMHD_SINGLE_FLUID;
     S.R = cplanes_of(c->r2, L, L.ncons);
     S.win = cplanes_of(c->w1, L, L.nprim);
-    S.wout = planes_of(c->w1, L, L.nprim);
+    S.wout = planes_of(fused ? c->w1 : prims, L, L.nprim);
     S.Q = planes_of(c->r2, L, L.ncons);
     mark(4);
     rc = launch_stage(c, S);
@@ -400,25 +404,38 @@ extern "C" int rmhd_imex_step(rmhd_ctx *c, double dt, double *cons, double *prim
     // q^{n+1} = ACC + dt/2 L(Q2) + dt/2 Psi(Q2), ghosts included, and its primitives
     // (recovered by the thread that forms each cell, from those of Q2)
     F.q = cplanes_of(c->r2, L, L.ncons);
-    F.w = cplanes_of(c->w1, L, L.nprim);
+    F.w = cplanes_of(fused ? c->w1 : prims, L, L.nprim);
     F.base = cplanes_of(c->acc, L, L.ncons);
     F.out0 = planes_of(cons, L, L.ncons);
     F.out1 = Planes{};
-    F.wnew = planes_of(prims, L, L.nprim);
+    F.wnew = fused ? planes_of(prims, L, L.nprim) : Planes{};
     F.c0L = 0.5 * dt;
     F.c0S = 0.5 * dt;
     mark(6);
     rc = launch_flux(c, F);
     mark(7);
-    if (rc || !c->timing) return rc;
-    rc = hip_check(c, hipEventSynchronize(c->ev[7]), "timing sync");
     if (rc) return rc;
-    float ms[4];
-    for (int k = 0; k < 4; ++k) hipEventElapsedTime(&ms[k], c->ev[2 * k], c->ev[2 * k + 1]);
+    if (!fused) {
+        // primitives of q^{n+1} (starting from those of Q2)
+        mark(8);
+        rc = rmhd_cons2prim(c, cons, prims, nullptr, nullptr);
+        mark(9);
+        if (rc) return rc;
+    }
+    if (!c->timing) return RMHD_OK;
+    const int last = fused ? 7 : 9;
+    rc = hip_check(c, hipEventSynchronize(c->ev[last]), "timing sync");
+    if (rc) return rc;
+    float ms[5] = {0, 0, 0, 0, 0};
+    for (int k = 0; 2 * k + 1 <= last; ++k) hipEventElapsedTime(&ms[k], c->ev[2 * k], c->ev[2 * k + 1]);
     c->times.stage_ms += ms[0] + ms[2];
     c->times.flux_ms += ms[1] + ms[3];
     c->times.stage_launches += 2;
     c->times.flux_launches += 2;
+    if (!fused) {
+        c->times.c2p_ms += ms[4];
+        c->times.c2p_launches += 1;
+    }
     c->times.steps += 1;
     return RMHD_OK;
 }
@@ -513,5 +530,12 @@ extern "C" int rmhd_set_flux_rows(rmhd_ctx *c, int rows)
     if (!c) return fail(c, RMHD_EINVAL, "rmhd_set_flux_rows: NULL context");
     if (rows != 0 && rows != 8 && rows != 16) return fail(c, RMHD_EINVAL, "rmhd_set_flux_rows: rows must be 0, 8 or 16");
     c->flux_rows = rows;
+    return RMHD_OK;
+}
+
+extern "C" int rmhd_set_stats_detail(rmhd_ctx *c, int detail)
+{
+    if (!c) return fail(c, RMHD_EINVAL, "rmhd_set_stats_detail: NULL context");
+    c->stats_detail = detail != 0;
     return RMHD_OK;
 }

@@ -60,11 +60,12 @@ class rmhd_batch_tuning(ctypes.Structure):
 
 
 EXPORTS = ["rmhd_layout_of", "rmhd_create", "rmhd_destroy", "rmhd_init_state", "rmhd_cons2prim", "rmhd_F",
-           "rmhd_implicit_stage", "rmhd_imex_step", "rmhd_dt", "rmhd_get_stats", "rmhd_set_newton_cap", "rmhd_set_flux_rows",
+           "rmhd_implicit_stage", "rmhd_imex_step", "rmhd_dt", "rmhd_get_stats", "rmhd_set_newton_cap", "rmhd_set_flux_rows", "rmhd_set_stats_detail",
            "rmhd_set_timing",
            "rmhd_get_timing", "rmhd_last_error",
            "rmhd_batch_create", "rmhd_batch_destroy", "rmhd_batch_step", "rmhd_batch_autotune",
-           "rmhd_batch_set_tuning", "rmhd_batch_get_tuning", "rmhd_batch_get_stats", "rmhd_batch_last_error",
+           "rmhd_batch_set_tuning", "rmhd_batch_get_tuning", "rmhd_batch_get_stats", "rmhd_batch_set_stats_detail",
+           "rmhd_batch_last_error",
            "rmhd_mlp_create", "rmhd_mlp_destroy", "rmhd_mlp_get_params", "rmhd_mlp_get_norm", "rmhd_mlp_set_norm",
            "rmhd_mlp_fit_norm", "rmhd_mlp_forward", "rmhd_mlp_loss_grad", "rmhd_mlp_train_step", "rmhd_mlp_train",
            "rmhd_mlp_steps", "rmhd_mlp_last_error", "rmhd_set_harvest", "rmhd_harvest_count", "rmhd_set_guess_model"]
@@ -96,6 +97,8 @@ def lib() -> ctypes.CDLL:
             "rmhd_get_stats": (ctypes.c_int, [vp, ctypes.POINTER(rmhd_stats), ctypes.c_int]),
             "rmhd_set_newton_cap": (ctypes.c_int, [vp, ctypes.c_int]),
             "rmhd_set_flux_rows": (ctypes.c_int, [vp, ctypes.c_int]),
+            "rmhd_set_stats_detail": (ctypes.c_int, [vp, ctypes.c_int]),
+            "rmhd_batch_set_stats_detail": (ctypes.c_int, [vp, ctypes.c_int]),
             "rmhd_set_timing": (ctypes.c_int, [vp, ctypes.c_int]),
             "rmhd_get_timing": (ctypes.c_int, [vp, ctypes.POINTER(rmhd_timing), ctypes.c_int]),
             "rmhd_last_error": (ctypes.c_char_p, [vp]),
@@ -238,6 +241,10 @@ def rmhd_set_flux_rows(ctx, rows: int):
     _check(lib().rmhd_set_flux_rows(ctx, int(rows)), ctx)
 
 
+def rmhd_set_stats_detail(ctx, detail: bool):
+    _check(lib().rmhd_set_stats_detail(ctx, int(detail)), ctx)
+
+
 def rmhd_set_timing(ctx, enable: bool):
     _check(lib().rmhd_set_timing(ctx, int(enable)), ctx)
 
@@ -353,6 +360,10 @@ class Solver:
 
     def stats(self, reset: bool = False) -> dict:
         return rmhd_get_stats(self.ctx, reset)
+
+    def set_stats_detail(self, detail: bool = True):
+        """Also collect the Newton-step histogram and the largest final residual."""
+        rmhd_set_stats_detail(self.ctx, detail)
 
     def set_newton_cap(self, cap: int):
         """Newton steps from unconverged iterates before a cell is queued (>= max: no queue)."""
@@ -645,6 +656,9 @@ class Batch:
 
     def stats(self, reset: bool = False) -> dict:
         return rmhd_batch_get_stats(self.b, reset)
+
+    def set_stats_detail(self, detail: bool = True):
+        _bcheck(lib().rmhd_batch_set_stats_detail(self.b, int(detail)), self.b)
 
     def close(self):
         if self.b is not None:

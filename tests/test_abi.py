@@ -106,3 +106,20 @@ def test_batched_domains_recipe_is_seeded():
     assert all(128 <= w.nx <= 4096 for w in a if w.ndim == 1)
     assert all(64 <= w.nx <= 512 and 64 <= w.ny <= 512 for w in a if w.ndim == 2)
     assert all(10.0 <= w.sigma <= 1e6 for w in a)
+
+
+def test_newton_percentile_from_histogram():
+    st = {"newton_hist": [0, 0, 70, 29, 1] + [0] * 11}
+    assert R.newton_percentile(st, 0.5) == 2
+    assert R.newton_percentile(st, 0.7) == 2
+    assert R.newton_percentile(st, 0.99) == 3
+    assert R.newton_percentile(st, 1.0) == 4
+    assert R.newton_percentile({"newton_hist": [0] * 16}, 0.5) == 15
+
+
+def test_stats_record_matches_header():
+    """The ctypes mirror of rmhd_stats has the header's fields in the header's order."""
+    src = open(os.path.join(ROOT, "include", "rmhd.h")).read()
+    body = src[src.index("typedef struct rmhd_stats {"):src.index("} rmhd_stats;")]
+    names = re.findall(r"\b(\w+)(?:\[\d+\])?;", re.sub(r"/\*.*?\*/", "", body, flags=re.S))
+    assert names == [n for n, _ in R.rmhd_stats._fields_]

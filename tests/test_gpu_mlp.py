@@ -235,6 +235,7 @@ def trained(R):
 
 def run_sheet(R, wl, net):
     s = gpu_solver(R, wl)
+    s.set_stats_detail(True)
     cons, prims = s.initial_state(wl.prims, wl.EB)
     s.set_guess_model(net)
     for _ in range(wl.steps):

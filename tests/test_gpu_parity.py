@@ -263,6 +263,7 @@ def test_newton_cap_queue_agrees_with_uninterrupted_solve(R, O, model):
     for cap in (1, 2, 1000):
         s = gpu_solver(R, wl)
         s.set_newton_cap(cap)
+        s.set_stats_detail(True)
         cons, prims = s.initial_state(wl.prims, wl.EB)
         dt = s.dt()
         for _ in range(wl.steps):
