@@ -154,6 +154,12 @@ int rmhd_implicit_stage(rmhd_ctx *ctx, double a, const double *R, const double *
  * Counters of the two stage solves are accumulated into the context's statistics. */
 int rmhd_imex_step(rmhd_ctx *ctx, double dt, double *cons, double *prims);
 
+/* With enable = 1, rmhd_imex_step captures its kernels once into a HIP graph (on a private
+ * stream) and replays it on the context's stream while (dt, cons, prims) and the context's
+ * settings stay the same; any change captures again.  Steps with timing or harvesting on
+ * are launched directly.  Results are identical either way.  Default 0. */
+int rmhd_set_graph(rmhd_ctx *ctx, int enable);
+
 /* Time step CFL / sum_d (1/dx_d) (maximum signal speed c = 1). */
 double rmhd_dt(const rmhd_ctx *ctx);
 

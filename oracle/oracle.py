@@ -58,6 +58,7 @@ def lib():
         ip = ctypes.POINTER(ctypes.c_int)
         P = ctypes.POINTER(_Params)
         sig = {
+            "orc_set_threads": (ctypes.c_int, [ctypes.c_int]),
             "orc_ncons": (ctypes.c_int, [ctypes.c_int]),
             "orc_nprim": (ctypes.c_int, [ctypes.c_int]),
             "orc_prim2cons_cell": (None, [P, dp, dp, ctypes.c_double, dp]),
@@ -272,3 +273,8 @@ def ssp2_step(g: Grid, dt: float, cons: np.ndarray, prims: np.ndarray):
 
 def dt(g: Grid, cfl: float) -> float:
     return lib().orc_dt(ctypes.byref(g.params()), float(cfl))
+
+
+def set_threads(n: int) -> int:
+    """OpenMP threads of the grid loops (n <= 0: unchanged); returns the number in effect."""
+    return lib().orc_set_threads(int(n))

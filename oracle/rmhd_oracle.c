@@ -14,6 +14,7 @@
 #include "rmhd_oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -842,4 +843,12 @@ double orc_dt(const orc_params *p, double cfl)
 {
     if (p->ndim == 1) return cfl * p->dx;
     return cfl / (1.0 / p->dx + 1.0 / p->dy);
+}
+
+/* Harness control, no arithmetic of the method: OpenMP threads used by the grid loops
+ * (n <= 0 leaves the setting); returns the number now in effect. */
+int orc_set_threads(int n)
+{
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
 }

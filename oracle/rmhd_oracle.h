@@ -88,6 +88,9 @@ int    orc_ssp2_step(const orc_params *p, double dt, double *cons, double *prims
                      long long *newton_iters, int *max_newton, int *nfail);
 double orc_dt(const orc_params *p, double cfl);
 
+/* OpenMP threads of the grid loops (n <= 0: unchanged); returns the number in effect. */
+int orc_set_threads(int n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -152,51 +152,92 @@ __global__ __launch_bounds__(256) void k_infer(InferArgs A)
         fs[e] = f < NIN ? A.norm[NFS + f] : 1.0f;
     }
 
+    float fsi[8];   // reciprocal standard deviations: the standardised value is rounded to
+                    // bfloat16 next, far coarser than the multiply's rounding
+#pragma unroll
+    for (int e = 0; e < 8; ++e) fsi[e] = fs[e] > 0.0f ? 1.0f / fs[e] : 0.0f;
+
     const long nsamp = S == 0 ? A.n : A.g.plane;
     const long ntiles = (nsamp + 15) / 16;
     const long wave = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const long nwaves = ((long)gridDim.x * blockDim.x) >> 6;
-    for (long tile = wave; tile < ntiles; tile += nwaves) {
+    // raw inputs of one tile for this lane; the next tile's are fetched before the current
+    // tile's products so that their latency overlaps the arithmetic
+    struct Raw {
+        double v[8];    // S = 1: D, the lane's 4 conserved values, 2 more (q = 0), sigma (q = 0)
+        double rv[4];   // S = 1: R's values of the lane's outputs
+        bool live;
+    };
+    auto fetch = [&](long tile, Raw &r) {
         const long s = tile * 16 + col;
-        float f[8];
-        double D = 1.0;
-        bool live = s < nsamp;
+        r.live = tile < ntiles && s < nsamp;
         if constexpr (S == 1) {
             const int i = (int)(s % A.g.pitch), j = (int)(s / A.g.pitch);
-            live = live && i < A.g.nxg && j < A.g.nyg;
+            r.live = r.live && i < A.g.nxg && j < A.g.nyg;
         }
 #pragma unroll
-        for (int e = 0; e < 8; ++e) f[e] = 0.0f;
-        if (live) {
-            if constexpr (S == 0) {
-                const float *x = A.X + s * NIN;
+        for (int e = 0; e < 8; ++e) r.v[e] = 0.0;
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int fi = (e < 4 ? 0 : 16) + 4 * q + (e & 3);
-                    if (fi < NIN) f[e] = x[fi];
-                }
-            } else {
-                // features in FP32: they are rounded to bfloat16 before the first product.
-                // The plane of feature 4q + e is picked by selects on the wave-uniform plane
-                // pointers (a lane-indexed pointer table would live in scratch memory).
-                D = A.R.p[tf::D][s];
-                const float iD = 1.0f / (float)D;
+        for (int e = 0; e < 4; ++e) r.rv[e] = 0.0;
+        if (!r.live) return;
+        if constexpr (S == 0) {
+            const float *x = A.X + s * NIN;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int fi = (e < 4 ? 0 : 16) + 4 * q + (e & 3);
+                if (fi < NIN) r.v[e] = x[fi];
+            }
+        } else {
+            // planes picked by selects on the wave-uniform pointers (a lane-indexed pointer
+            // table would live in scratch memory)
+            r.v[7] = A.R.p[tf::D][s];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const double *pl = q == 0 ? A.R.p[e] : q == 1 ? A.R.p[4 + e] : q == 2 ? A.R.p[8 + e] : A.R.p[12 + e];
+                r.v[e] = pl[s];
+            }
+            if (q == 0) {
+                r.v[4] = A.R.p[16][s];
+                r.v[5] = A.R.p[17][s];
+                r.v[6] = cell_sigma(A.P, s);
+            }
+            if (q <= 1) {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const double *pl = q == 0 ? A.R.p[e] : q == 1 ? A.R.p[4 + e] : q == 2 ? A.R.p[8 + e] : A.R.p[12 + e];
-                    f[e] = (float)pl[s] * iD;
+                    const int p0 = e < 3 ? tf::SBX + e : tf::TAUB, p1 = tf::EX + (e < 3 ? e : 0);
+                    if (q == 0 || e < 3) r.rv[e] = q == 0 ? A.R.p[p0][s] : A.R.p[p1][s];
                 }
-                if (q == 0) {
-                    f[0] = log10f((float)(A.a * A.P.mu1 * A.P.mu1 * D));
-                    f[4] = (float)A.R.p[16][s] * iD;
-                    f[5] = (float)A.R.p[17][s] * iD;
-                    f[6] = log10f((float)(A.a * cell_sigma(A.P, s)));
-                }
+            }
+        }
+    };
+    Raw cur, nxt;
+    fetch(wave, cur);
+    for (long tile = wave; tile < ntiles; tile += nwaves) {
+        fetch(tile + nwaves, nxt);
+        const long s = tile * 16 + col;
+        const bool live = cur.live;
+        const double D = S == 1 ? cur.v[7] : 1.0;
+        float f[8];
+        if constexpr (S == 0) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) f[e] = (float)cur.v[e];
+        } else {
+            // features in FP32: they are rounded to bfloat16 before the first product
+            const float iD = live ? __builtin_amdgcn_rcpf((float)D) : 0.0f;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) f[e] = (float)cur.v[e] * iD;
+            f[4] = (float)cur.v[4] * iD;
+            f[5] = (float)cur.v[5] * iD;
+            f[6] = 0.0f;
+            f[7] = 0.0f;
+            if (q == 0 && live) {
+                f[0] = __log10f((float)(A.a * A.P.mu1 * A.P.mu1 * D));
+                f[6] = __log10f((float)(A.a * cur.v[6]));
             }
         }
         float u[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) u[e] = live && fs[e] > 0.0f ? (f[e] - fm[e]) / fs[e] : 0.0f;
+        for (int e = 0; e < 8; ++e) u[e] = live ? (f[e] - fm[e]) * fsi[e] : 0.0f;
         if (q > 0) u[4] = u[5] = u[6] = u[7] = 0.0f;   // padded columns 20..31
         const v4s x0 = pack4(u[0], u[1], u[2], u[3]), x1 = pack4(u[4], u[5], u[6], u[7]);
         // layer 1: H1^T (64 x 16) = W1 (64 x 32) U^T (32 x 16)
@@ -236,13 +277,13 @@ __global__ __launch_bounds__(256) void k_infer(InferArgs A)
                 // units (times |mu1|), as the stage reads its starting point.  Output 4q + e
                 // goes to Sbar/taubar (q = 0) or E (q = 1): planes picked by select.
                 const int p0 = e < 3 ? tf::SBX + e : tf::TAUB, p1 = tf::EX + (e < 3 ? e : 0);
-                const double rv = q == 0 ? A.R.p[p0][s] : A.R.p[p1][s];
                 double *out = q == 0 ? A.guess.p[p0] : A.guess.p[p1];
                 const double scale = q == 0 ? fabs(A.P.mu1) : 1.0;
-                out[s] = rv + D * scale * (double)y;
+                out[s] = cur.rv[e] + D * scale * (double)y;
             }
         }
         }
+        cur = nxt;
     }
 }
 

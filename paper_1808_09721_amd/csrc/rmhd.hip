@@ -43,6 +43,13 @@ struct rmhd_ctx {
     int *qidx, *qit;
     double *qx, *qp;
     unsigned *qcount;
+    // the step captured in a HIP graph (rmhd_set_graph), keyed by its arguments
+    int use_graph;
+    hipStream_t gstream;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    double g_dt;
+    double *g_cons, *g_prims;
     // per-kernel event timing of rmhd_imex_step
     int timing;
     hipEvent_t ev[10];
@@ -172,9 +179,19 @@ extern "C" int rmhd_create(const rmhd_params *p, void *stream, rmhd_ctx **out)
     return RMHD_OK;
 }
 
+static void free_graph(rmhd_ctx *c)
+{
+    if (c->exec) hipGraphExecDestroy(c->exec);
+    if (c->graph) hipGraphDestroy(c->graph);
+    c->exec = nullptr;
+    c->graph = nullptr;
+}
+
 extern "C" void rmhd_destroy(rmhd_ctx *c)
 {
     if (!c) return;
+    free_graph(c);
+    if (c->gstream) hipStreamDestroy(c->gstream);
     if (c->timing)
         for (int k = 0; k < 10; ++k) hipEventDestroy(c->ev[k]);
     hipFree(c->q1src);
@@ -337,10 +354,50 @@ extern "C" int rmhd_implicit_stage(rmhd_ctx *c, double a, const double *R, const
     return launch_stage(c, A);
 }
 
+static int enqueue_imex(rmhd_ctx *c, double dt, double *cons, double *prims);
+
 extern "C" int rmhd_imex_step(rmhd_ctx *c, double dt, double *cons, double *prims)
 {
     if (!c || !cons || !prims) return fail(c, RMHD_EINVAL, "rmhd_imex_step: NULL argument");
     if (!(dt > 0.0)) return fail(c, RMHD_EINVAL, "rmhd_imex_step: dt must be > 0");
+    // the graph holds fixed kernel arguments: not while timing or harvesting (both change
+    // per call)
+    if (!c->use_graph || c->timing || c->hx) return enqueue_imex(c, dt, cons, prims);
+    if (!c->exec || dt != c->g_dt || cons != c->g_cons || prims != c->g_prims) {
+        free_graph(c);
+        int rc = RMHD_OK;
+        if (!c->gstream)
+            rc = hip_check(c, hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking), "capture stream");
+        if (rc) return rc;
+        rc = hip_check(c, hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal), "begin capture");
+        if (rc) return rc;
+        const hipStream_t own = c->stream;
+        c->stream = c->gstream;
+        rc = enqueue_imex(c, dt, cons, prims);
+        c->stream = own;
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(c->gstream, &g);
+        if (rc) {
+            if (g) hipGraphDestroy(g);
+            return rc;
+        }
+        rc = hip_check(c, e, "end capture");
+        if (rc) return rc;
+        c->graph = g;
+        rc = hip_check(c, hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0), "graph instantiate");
+        if (rc) {
+            free_graph(c);
+            return rc;
+        }
+        c->g_dt = dt;
+        c->g_cons = cons;
+        c->g_prims = prims;
+    }
+    return hip_check(c, hipGraphLaunch(c->exec, c->stream), "graph launch");
+}
+
+static int enqueue_imex(rmhd_ctx *c, double dt, double *cons, double *prims)
+{
     const rmhd_layout &L = c->lay;
     const double gm = SSP2_GAMMA;
     const int M = c->prm.model;
@@ -514,6 +571,7 @@ extern "C" int rmhd_set_guess_model(rmhd_ctx *c, const rmhd_mlp *m)
         }
     }
     c->mlp = m;
+    free_graph(c);   // kernel sequence changed: capture again
     return RMHD_OK;
 }
 
@@ -522,6 +580,7 @@ extern "C" int rmhd_set_newton_cap(rmhd_ctx *c, int cap)
     if (!c) return fail(c, RMHD_EINVAL, "rmhd_set_newton_cap: NULL context");
     if (cap < 1) return fail(c, RMHD_EINVAL, "rmhd_set_newton_cap: cap must be >= 1");
     c->cap = cap;
+    free_graph(c);   // kernel arguments changed: capture again
     return RMHD_OK;
 }
 
@@ -530,6 +589,7 @@ extern "C" int rmhd_set_flux_rows(rmhd_ctx *c, int rows)
     if (!c) return fail(c, RMHD_EINVAL, "rmhd_set_flux_rows: NULL context");
     if (rows != 0 && rows != 8 && rows != 16) return fail(c, RMHD_EINVAL, "rmhd_set_flux_rows: rows must be 0, 8 or 16");
     c->flux_rows = rows;
+    free_graph(c);   // kernel arguments changed: capture again
     return RMHD_OK;
 }
 
@@ -537,5 +597,14 @@ extern "C" int rmhd_set_stats_detail(rmhd_ctx *c, int detail)
 {
     if (!c) return fail(c, RMHD_EINVAL, "rmhd_set_stats_detail: NULL context");
     c->stats_detail = detail != 0;
+    free_graph(c);   // kernel arguments changed: capture again
+    return RMHD_OK;
+}
+
+extern "C" int rmhd_set_graph(rmhd_ctx *c, int enable)
+{
+    if (!c) return fail(c, RMHD_EINVAL, "rmhd_set_graph: NULL context");
+    c->use_graph = enable != 0;
+    free_graph(c);
     return RMHD_OK;
 }

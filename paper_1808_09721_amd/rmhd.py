@@ -60,7 +60,7 @@ class rmhd_batch_tuning(ctypes.Structure):
 
 
 EXPORTS = ["rmhd_layout_of", "rmhd_create", "rmhd_destroy", "rmhd_init_state", "rmhd_cons2prim", "rmhd_F",
-           "rmhd_implicit_stage", "rmhd_imex_step", "rmhd_dt", "rmhd_get_stats", "rmhd_set_newton_cap", "rmhd_set_flux_rows", "rmhd_set_stats_detail",
+           "rmhd_implicit_stage", "rmhd_imex_step", "rmhd_set_graph", "rmhd_dt", "rmhd_get_stats", "rmhd_set_newton_cap", "rmhd_set_flux_rows", "rmhd_set_stats_detail",
            "rmhd_set_timing",
            "rmhd_get_timing", "rmhd_last_error",
            "rmhd_batch_create", "rmhd_batch_destroy", "rmhd_batch_step", "rmhd_batch_autotune",
@@ -93,6 +93,7 @@ def lib() -> ctypes.CDLL:
             "rmhd_F": (ctypes.c_int, [vp, dp, dp, dp]),
             "rmhd_implicit_stage": (ctypes.c_int, [vp, ctypes.c_double, dp, dp, dp, dp, vp, vp]),
             "rmhd_imex_step": (ctypes.c_int, [vp, ctypes.c_double, dp, dp]),
+            "rmhd_set_graph": (ctypes.c_int, [vp, ctypes.c_int]),
             "rmhd_dt": (ctypes.c_double, [vp]),
             "rmhd_get_stats": (ctypes.c_int, [vp, ctypes.POINTER(rmhd_stats), ctypes.c_int]),
             "rmhd_set_newton_cap": (ctypes.c_int, [vp, ctypes.c_int]),
@@ -203,6 +204,10 @@ def rmhd_implicit_stage(ctx, a, R, guess, Q, prims, status=None, iters=None):
 
 def rmhd_imex_step(ctx, dt, cons, prims):
     _check(lib().rmhd_imex_step(ctx, float(dt), _ptr(cons), _ptr(prims)), ctx)
+
+
+def rmhd_set_graph(ctx, enable: bool):
+    _check(lib().rmhd_set_graph(ctx, int(enable)), ctx)
 
 
 def rmhd_dt(ctx) -> float:
@@ -360,6 +365,10 @@ class Solver:
 
     def stats(self, reset: bool = False) -> dict:
         return rmhd_get_stats(self.ctx, reset)
+
+    def set_graph(self, enable: bool = True):
+        """Replay the step from a captured HIP graph while its arguments stay the same."""
+        rmhd_set_graph(self.ctx, enable)
 
     def set_stats_detail(self, detail: bool = True):
         """Also collect the Newton-step histogram and the largest final residual."""

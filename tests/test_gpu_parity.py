@@ -384,3 +384,31 @@ def test_padding_is_never_read(R, O):
     a, b = s.grid.download_all(cons), s.grid.download_all(c2)
     assert np.all(np.isfinite(b))
     np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_graph_replays_match_eager_steps(R, O, model):
+    """The step replayed from its captured graph equals the directly launched step bit for bit
+    at every replay, with unrelated eager work and synchronisation between replays and a
+    change of dt (which captures again) in the middle."""
+    banner(f"single-grid graph replays model={model}")
+    import torch
+    wl = (WL.kelvin_helmholtz_2d(70, 37, steps=5, seed=21) if model == 0 else
+          WL.two_fluid_sheet_2d(40, 28, steps=5, seed=22, sigma_range=(1e2, 1e6)))
+    sg, se = gpu_solver(R, wl), gpu_solver(R, wl)
+    sg.set_graph(True)
+    cg, pg = sg.initial_state(wl.prims, wl.EB)
+    ce, pe = se.initial_state(wl.prims, wl.EB)
+    dt = sg.dt()
+    for k in range(5):
+        h = dt if k != 3 else 0.5 * dt
+        sg.step(h, cg, pg)
+        torch.cuda.synchronize()
+        _ = torch.ones(1000, device="cuda").sum().item()
+        se.step(h, ce, pe)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(sg.grid.download_all(cg), se.grid.download_all(ce))
+        np.testing.assert_array_equal(sg.grid.download_all(pg), se.grid.download_all(pe))
+    assert sg.stats()["stage_cells"] == se.stats()["stage_cells"] == 2 * 5 * wl.cells
+    sg.close()
+    se.close()
