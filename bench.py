@@ -171,7 +171,6 @@ def learned_measure(steps: int, warmup: int, n: int = 1024, train_n: int = 512, 
         s = R.Solver.for_workload(wl)
         c, w = s.initial_state(wl.prims, wl.EB)
         dt = s.dt()
-        s.set_graph(True)
         if mode == "plain_single_pass":
             s.set_newton_cap(1000)     # no queue: every wavefront runs to its slowest cell
         if mode == "learned":
@@ -249,7 +248,6 @@ def main() -> int:
     solver = R.Solver(R.params_from(wl))
     cons, prims = solver.initial_state(wl.prims, wl.EB)
     dt = solver.dt()
-    solver.set_graph(True)            # the step is captured during the warm-up and replayed
     for _ in range(args.warmup):
         solver.step(dt, cons, prims)
     solver.stats(reset=True)

@@ -108,13 +108,13 @@ __device__ inline float fast_tanh(float z)
     return 1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + __expf(2.0f * z));
 }
 
+// Four values rounded to bfloat16 (nearest, ties to even: gfx950's packed conversion, the
+// same rounding as bf16_bits for finite values) as an MFMA operand.
 __device__ inline v4s pack4(float a, float b, float c, float d)
 {
+    const __bf16 h[4] = {(__bf16)a, (__bf16)b, (__bf16)c, (__bf16)d};
     v4s r;
-    r[0] = (short)bf16_bits(a);
-    r[1] = (short)bf16_bits(b);
-    r[2] = (short)bf16_bits(c);
-    r[3] = (short)bf16_bits(d);
+    memcpy(&r, h, sizeof(r));
     return r;
 }
 
