@@ -75,6 +75,7 @@ def lib():
             "orc_rhs": (None, [P, dp, dp, dp]),
             "orc_implicit": (None, [P, ctypes.c_double, dp, dp, dp, ctypes.c_void_p, ctypes.c_void_p]),
             "orc_ssp2_step": (ctypes.c_int, [P, ctypes.c_double, dp, dp, ctypes.POINTER(ctypes.c_longlong), ip, ip]),
+            "orc_ssp3_step": (ctypes.c_int, [P, ctypes.c_double, dp, dp, ctypes.POINTER(ctypes.c_longlong), ip, ip]),
             "orc_dt": (ctypes.c_double, [P, ctypes.c_double]),
         }
         for name, (res, args) in sig.items():
@@ -267,6 +268,16 @@ def ssp2_step(g: Grid, dt: float, cons: np.ndarray, prims: np.ndarray):
     mx = ctypes.c_int(0)
     nf = ctypes.c_int(0)
     bad = lib().orc_ssp2_step(ctypes.byref(g.params()), float(dt), _dp(cons), _dp(prims), ctypes.byref(nit),
+                              ctypes.byref(mx), ctypes.byref(nf))
+    return bad, nit.value, mx.value
+
+
+def ssp3_step(g: Grid, dt: float, cons: np.ndarray, prims: np.ndarray):
+    """Advance (cons, prims) in place by one SSP3(332) step; returns (nbad, newton_iters, max_newton)."""
+    nit = ctypes.c_longlong(0)
+    mx = ctypes.c_int(0)
+    nf = ctypes.c_int(0)
+    bad = lib().orc_ssp3_step(ctypes.byref(g.params()), float(dt), _dp(cons), _dp(prims), ctypes.byref(nit),
                               ctypes.byref(mx), ctypes.byref(nf))
     return bad, nit.value, mx.value
 

@@ -837,6 +837,82 @@ int orc_ssp2_step(const orc_params *p, double dt, double *cons, double *prims, l
     return bad;
 }
 
+/* Add the iteration counts and failures of one implicit stage over the interior cells. */
+static void stage_tally(const orc_params *p, const signed char *st, const int *it, long long *nit, int *mx,
+                        int *bad)
+{
+    const int NX = NXg(p);
+    for (int j = jlo(p); j < jhi(p); ++j)
+        for (int i = 2; i < p->nx + 2; ++i) {
+            const long idx = (long)j * NX + i;
+            *nit += it[idx];
+            *mx = it[idx] > *mx ? it[idx] : *mx;
+            *bad += st[idx] != ORC_OK;
+        }
+}
+
+/* One SSP3(332) IMEX step (Sec. 2.2.1, Eqs. 10-11 with the Table 3 tableau, gamma as for
+ * SSP2(222)), in the same standard reading of the stage sums:
+ *   Q1 = q^n + gamma dt Psi(Q1)
+ *   Q2 = q^n + dt L(Q1) + (1 - 2 gamma) dt Psi(Q1) + gamma dt Psi(Q2)
+ *   Q3 = q^n + dt/4 [L(Q1) + L(Q2)] + (1/2 - gamma) dt Psi(Q1) + gamma dt Psi(Q3)
+ *   q^{n+1} = q^n + dt [L(Q1)/6 + L(Q2)/6 + 2 L(Q3)/3] + dt [Psi(Q1)/6 + Psi(Q2)/6 + 2 Psi(Q3)/3]
+ * Each stage starts its recovery from the previous stage's primitives; the primitives of
+ * q^{n+1} are recovered from those of Q3.  Returns the number of cells with a nonzero status. */
+int orc_ssp3_step(const orc_params *p, double dt, double *cons, double *prims, long long *newton_iters,
+                  int *max_newton, int *nfail)
+{
+    const double g = 1.0 - 1.0 / sqrt(2.0);
+    const int NX = NXg(p), nc = orc_ncons(p->model), np = orc_nprim(p->model);
+    const long pl = plane(p);
+    const size_t bc = sizeof(double) * nc * pl, bp = sizeof(double) * np * pl;
+    double *Q1 = malloc(bc), *Q2 = malloc(bc), *Q3 = malloc(bc), *R = malloc(bc);
+    double *L1 = malloc(bc), *L2 = malloc(bc), *L3 = malloc(bc);
+    double *S1 = malloc(bc), *S2 = malloc(bc), *S3 = malloc(bc);
+    double *w = malloc(bp);
+    signed char *st = malloc(pl);
+    int *it = malloc(sizeof(int) * pl);
+    long long nit = 0;
+    int mx = 0, bad = 0;
+
+    memcpy(w, prims, bp);
+    orc_implicit(p, g * dt, cons, Q1, w, st, it);
+    stage_tally(p, st, it, &nit, &mx, &bad);
+    orc_rhs(p, Q1, w, L1);
+    source_grid(p, Q1, w, S1);
+
+    for (long k = 0; k < nc * pl; ++k) R[k] = cons[k] + dt * L1[k] + (1.0 - 2.0 * g) * dt * S1[k];
+    orc_implicit(p, g * dt, R, Q2, w, st, it);
+    stage_tally(p, st, it, &nit, &mx, &bad);
+    orc_rhs(p, Q2, w, L2);
+    source_grid(p, Q2, w, S2);
+
+    for (long k = 0; k < nc * pl; ++k) R[k] = cons[k] + 0.25 * dt * (L1[k] + L2[k]) + (0.5 - g) * dt * S1[k];
+    orc_implicit(p, g * dt, R, Q3, w, st, it);
+    stage_tally(p, st, it, &nit, &mx, &bad);
+    orc_rhs(p, Q3, w, L3);
+    source_grid(p, Q3, w, S3);
+
+    for (int v = 0; v < nc; ++v)
+        for (int j = jlo(p); j < jhi(p); ++j)
+            for (int i = 2; i < p->nx + 2; ++i) {
+                const long k = v * pl + (long)j * NX + i;
+                cons[k] = cons[k] + dt * (L1[k] / 6.0 + L2[k] / 6.0 + 2.0 * L3[k] / 3.0) +
+                          dt * (S1[k] / 6.0 + S2[k] / 6.0 + 2.0 * S3[k] / 3.0);
+            }
+    orc_bc_fill(p, cons, nc);
+    memcpy(prims, w, bp);
+    orc_cons2prim(p, cons, prims, st, it);
+    for (long idx = 0; idx < pl; ++idx) bad += st[idx] != ORC_OK;
+
+    if (newton_iters) *newton_iters += nit;
+    if (max_newton && mx > *max_newton) *max_newton = mx;
+    if (nfail) *nfail += bad;
+    free(Q1); free(Q2); free(Q3); free(R); free(L1); free(L2); free(L3); free(S1); free(S2); free(S3);
+    free(w); free(st); free(it);
+    return bad;
+}
+
 /* Time step dt = CFL / sum_d (1/dx_d) with the maximum signal speed c = 1 (the CFL number is
  * given per workload; the 2-D combination is the reading taken). */
 double orc_dt(const orc_params *p, double cfl)

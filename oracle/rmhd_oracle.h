@@ -86,6 +86,9 @@ void   orc_implicit(const orc_params *p, double a, const double *R, double *Q, d
                     signed char *status, int *iters);
 int    orc_ssp2_step(const orc_params *p, double dt, double *cons, double *prims,
                      long long *newton_iters, int *max_newton, int *nfail);
+/* One SSP3(332) IMEX step (Table 3 tableau), same conventions as orc_ssp2_step. */
+int    orc_ssp3_step(const orc_params *p, double dt, double *cons, double *prims,
+                     long long *newton_iters, int *max_newton, int *nfail);
 double orc_dt(const orc_params *p, double cfl);
 
 /* OpenMP threads of the grid loops (n <= 0: unchanged); returns the number in effect. */

@@ -34,8 +34,10 @@ def initial_state(wl, g: O.Grid | None = None):
 
 
 def advance(g: O.Grid, cons, prims, dt: float, steps: int | None = None, t0: float = 0.0,
-            t_end: float | None = None):
-    """SSP2(222) steps of size dt (the last one truncated to hit t_end)."""
+            t_end: float | None = None, scheme: str = "ssp2"):
+    """SSP2(222) (or, scheme="ssp3", SSP3(332)) steps of size dt (the last one truncated to
+    hit t_end)."""
+    step = O.ssp2_step if scheme == "ssp2" else O.ssp3_step
     t, n, nit, mx = t0, 0, 0, 0
     while True:
         if steps is not None and n >= steps:
@@ -43,7 +45,7 @@ def advance(g: O.Grid, cons, prims, dt: float, steps: int | None = None, t0: flo
         if t_end is not None and t >= t_end - 1e-12:
             break
         h = dt if t_end is None else min(dt, t_end - t)
-        bad, ni, m = O.ssp2_step(g, h, cons, prims)
+        bad, ni, m = step(g, h, cons, prims)
         assert bad == 0, f"oracle step {n}: {bad} cells failed"
         t += h
         n += 1

@@ -449,7 +449,7 @@ def test_implicit_stage_solves_and_is_guess_independent(model, covariant, wmax, 
 # ------------------------------------------------------------------------------------------
 # SSP2(222) (Sec. 2.2.1 Eqs. 10-11, Table 2)
 # ------------------------------------------------------------------------------------------
-def _uniform_decay_factor(sig_dt, field="E"):
+def _uniform_decay_factor(sig_dt, field="E", scheme="ssp2"):
     """One step on a uniform state at rest: the E field (decay rate sigma, through the
     nonlinear stage solve) or phi (decay rate kappa, closed form) is multiplied by R(z)."""
     O = _O()
@@ -467,7 +467,7 @@ def _uniform_decay_factor(sig_dt, field="E"):
         cons[13] = 0.01
         idx = 13
     x0 = g.interior(cons)[idx, 0, 0]
-    O.ssp2_step(g, dt, cons, prims)
+    (O.ssp2_step if scheme == "ssp2" else O.ssp3_step)(g, dt, cons, prims)
     return g.interior(cons)[idx, 0, 0] / x0
 
 
@@ -479,6 +479,83 @@ def test_ssp2_amplification_second_order_and_l_stable():
     # the closed-form phi path and the Newton E path give the same amplification factor
     for z in (0.05, 1.0, 30.0):
         assert _uniform_decay_factor(z, "E") == pytest.approx(_uniform_decay_factor(z, "phi"), rel=1e-11)
+
+
+def test_ssp3_amplification_second_order_and_l_stable():
+    """SSP3(332)'s implicit tableau: R(z) = e^-z + O(z^3), R(-inf) = 0 (L-stable), and the
+    closed-form phi path agrees with the Newton E path."""
+    for z in (1e-3, 3e-3, 1e-2):
+        r = _uniform_decay_factor(z, scheme="ssp3")
+        assert abs(r - np.exp(-z)) < 0.1 * z ** 3
+    assert abs(_uniform_decay_factor(1e6, scheme="ssp3")) < 1e-5
+    for z in (0.05, 1.0, 30.0):
+        assert _uniform_decay_factor(z, "E", "ssp3") == pytest.approx(_uniform_decay_factor(z, "phi", "ssp3"),
+                                                                      rel=1e-11)
+
+
+@pytest.mark.parametrize("scheme,order", [("ssp2", 2.0), ("ssp3", 3.0)])
+def test_explicit_part_temporal_order(scheme, order):
+    """With sigma = 0 a vacuum light wave has no source (J = rho_e v = 0, psi = phi = 0), so
+    the IMEX step is its explicit tableau alone: SSP2 is second and SSP3 third order in time.
+    Fixed grid, halving dt, errors against a run with dt/16."""
+    O = _O()
+    N, A = 64, 1e-3
+    x = (np.arange(N) + 0.5) / N
+
+    def run(cfl):
+        wl = WL.entropy_wave_1d(N, sigma=0.0, amplitude=0.0, vx=0.0)
+        wl.EB[:] = 0.0
+        wl.EB[4, 0] = wl.EB[2, 0] = A * np.sin(2 * np.pi * x)
+        g, cons, prims = initial_state(wl)
+        advance(g, cons, prims, O.dt(g, cfl), t_end=0.25, scheme=scheme)
+        return g.interior(cons)[9, 0]
+
+    ref = run(0.8 / 16)
+    errs = [np.abs(run(c) - ref).mean() for c in (0.8, 0.4, 0.2)]
+    measured = np.log2(errs[1] / errs[2])
+    assert abs(measured - order) < 0.35, (errs, measured)
+
+
+def test_ssp3_and_ssp2_agree_to_truncation_and_conserve():
+    """Both integrators advance the smooth entropy wave to the same solution within their
+    truncation error (their difference falls at least at second order as dt halves), and
+    SSP3 conserves the source-free totals of a KHI run to round-off."""
+    O = _O()
+    diffs = []
+    for cfl in (0.5, 0.25):
+        wl = WL.entropy_wave_1d(64)
+        g, c2, p2 = initial_state(wl)
+        _, c3, p3 = initial_state(wl)
+        dt = O.dt(g, cfl)
+        advance(g, c2, p2, dt, t_end=0.5)
+        advance(g, c3, p3, dt, t_end=0.5, scheme="ssp3")
+        diffs.append(np.abs(g.interior(c3)[0] - g.interior(c2)[0]).max())
+    assert diffs[0] > 0 and diffs[0] / diffs[1] > 3.5, diffs
+    wl = WL.kelvin_helmholtz_2d(24, 32, seed=7)
+    g, c3, p3 = initial_state(wl)
+    tot0 = g.interior(c3).sum(axis=(1, 2))
+    advance(g, c3, p3, O.dt(g, 0.5), steps=10, scheme="ssp3")
+    tot = g.interior(c3).sum(axis=(1, 2))
+    scale = np.abs(g.interior(c3)).sum(axis=(1, 2))
+    for v in (0, 1, 2, 3, 4, 5, 6, 7, 11):
+        assert abs(tot[v] - tot0[v]) <= 1e-13 * max(scale[v], 1e-300), v
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_ssp3_entropy_wave_convergence_order(model):
+    """The SSP3(332) IMEX scheme (order 2 overall) converges at second order on the smooth
+    advected density wave."""
+    O = _O()
+    errs = []
+    for N in (32, 64, 128):
+        wl = WL.entropy_wave_1d(N, model=model)
+        g, cons, prims = initial_state(wl)
+        advance(g, cons, prims, O.dt(g, 0.5), t_end=2.0, scheme="ssp3")
+        x = (np.arange(N) + 0.5) / N
+        rho = g.interior(prims)[0, 0] + (g.interior(prims)[5, 0] if model else 0.0)
+        errs.append(np.mean(np.abs(rho - (1 + 0.5 * np.sin(2 * np.pi * (x - 1.0))))))
+    order = np.log2(errs[0] / errs[-1]) / 2
+    assert order > 1.8, errs
 
 
 def test_psi_relaxes_to_charge_over_kappa():
