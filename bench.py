@@ -220,6 +220,39 @@ def learned_measure(steps: int, warmup: int, n: int = 1024, train_n: int = 512, 
                          "harvest_s": t_harvest, "train_s": t_train}}
 
 
+def ssp3_measure(steps: int, warmup: int) -> dict:
+    """SSP3(332) (three implicit stages and three flux passes per step) on the headline KHI
+    grid and on the two-fluid sheet at 1024^2 with sigma ~ 10^U[2, 6] per cell."""
+    import torch
+
+    from paper_1808_09721_amd import rmhd as R
+    from paper_1808_09721_amd import workloads as WL
+    out = {}
+    for name, wl in (("kelvin_helmholtz_2d 256x512", WL.kelvin_helmholtz_2d()),
+                     ("two-fluid current sheet 1024x1024, sigma~10^U[2,6] per cell", WL.learned_guess_sheet(1024))):
+        s = R.Solver.for_workload(wl, integrator=R.SSP3_332)
+        c, w = s.initial_state(wl.prims, wl.EB)
+        dt = s.dt()
+        n = steps if wl.cells < 500000 else max(3, steps // 10)
+        for _ in range(warmup):
+            s.step(dt, c, w)
+        s.stats(reset=True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(n):
+            s.step(dt, c, w)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / n
+        st = s.stats(reset=True)
+        out[name] = {"cells": wl.cells, "steps": n, "ms_per_step": ms, "value": wl.cells / (ms / 1e3),
+                     "unit": "cell-updates/s", "newton_iters_per_cell_stage": st["newton_iters"] / max(1, st["stage_cells"]),
+                     "failures": st["failures"]}
+        s.close()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -229,6 +262,7 @@ def main() -> int:
     ap.add_argument("--timing-steps", type=int, default=20)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-ssp3", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (traffic calibration)")
     args = ap.parse_args()
@@ -350,6 +384,8 @@ def main() -> int:
         out["batched"] = batched_measure(max(5, args.steps // 5), args.warmup)
     if not args.no_learned:
         out["learned"] = learned_measure(10, args.warmup)
+    if not args.no_ssp3:
+        out["ssp3"] = ssp3_measure(max(10, args.steps // 2), args.warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
         out["cpu_baseline"]["gpu_speedup"] = value / out["cpu_baseline"]["value"]

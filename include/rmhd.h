@@ -60,6 +60,10 @@ extern "C" {
 #define RMHD_CELL_NEWTON_NOCONV 3
 #define RMHD_CELL_LINESEARCH 4
 
+/* IMEX integrators (Sec. 2.2.1, Eqs. 10-11) */
+#define RMHD_SSP2_222 0
+#define RMHD_SSP3_332 1
+
 typedef struct rmhd_params {
     int32_t model;            /* RMHD_SINGLE_FLUID or RMHD_TWO_FLUID */
     int32_t ndim;             /* 1 or 2 */
@@ -79,6 +83,8 @@ typedef struct rmhd_params {
     double cfl;               /* CFL number for rmhd_dt() */
     double c2p_tol;           /* primitive-recovery residual tolerance (1e-13, Sec. 2.1.3) */
     double newton_tol;        /* implicit-stage residual tolerance (e.g. 1e-12) */
+    int32_t integrator;       /* RMHD_SSP2_222 (0, Table 2) or RMHD_SSP3_332 (1, Table 3) */
+    int32_t reserved_;        /* must be 0 */
 } rmhd_params;
 
 typedef struct rmhd_layout {
@@ -148,10 +154,11 @@ int rmhd_F(rmhd_ctx *ctx, double *cons, double *prims, double *L);
 int rmhd_implicit_stage(rmhd_ctx *ctx, double a, const double *R, const double *guess, double *Q,
                         double *prims, int8_t *status, int32_t *iters);
 
-/* One SSP2(222) IMEX step of size dt (Sec. 2.2.1, Eqs. 10-11, Table 2, gamma = 1 - 1/sqrt 2).
+/* One IMEX step of size dt (Sec. 2.2.1, Eqs. 10-11) with the context's integrator: SSP2(222)
+ * (Table 2, two implicit stages, gamma = 1 - 1/sqrt 2) or SSP3(332) (Table 3, three).
  * cons (ghosts valid) is advanced in place; prims holds the primitives of cons on entry
  * (used as root-find starting points) and those of the new cons on exit, ghosts included.
- * Counters of the two stage solves are accumulated into the context's statistics. */
+ * Counters of the stage solves are accumulated into the context's statistics. */
 int rmhd_imex_step(rmhd_ctx *ctx, double dt, double *cons, double *prims);
 
 /* With enable = 1, rmhd_imex_step captures its kernels once into a HIP graph (on a private

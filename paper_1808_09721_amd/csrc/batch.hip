@@ -234,26 +234,28 @@ __global__ __launch_bounds__(BX *BY) void kb_flux(BatchFluxArgs B)
         int k = 0;
         for (int v = 0; v < sf::NC; ++v) {
             A.q.p[v] = has_source(0, v) ? D.q1src + (k++) * g.plane : D.cons + v * g.plane;
-            A.base.p[v] = D.cons + v * g.plane;
-            A.out0.p[v] = D.r2 + v * g.plane;
-            A.out1.p[v] = D.acc + v * g.plane;
+            A.o[0].base.p[v] = D.cons + v * g.plane;
+            A.o[0].out.p[v] = D.r2 + v * g.plane;
+            A.o[1].base.p[v] = D.cons + v * g.plane;
+            A.o[1].out.p[v] = D.acc + v * g.plane;
         }
         for (int v = 0; v < sf::NP; ++v) A.w.p[v] = D.w1 + v * g.plane;
-        A.c0L = dt;
-        A.c0S = (1.0 - 2.0 * gm) * dt;
-        A.c1L = 0.5 * dt;
-        A.c1S = 0.5 * dt;
+        A.o[0].cL = dt;
+        A.o[0].cS = (1.0 - 2.0 * gm) * dt;
+        A.o[1].cL = 0.5 * dt;
+        A.o[1].cS = 0.5 * dt;
     } else {
         for (int v = 0; v < sf::NC; ++v) {
             A.q.p[v] = D.r2 + v * g.plane;
-            A.base.p[v] = D.acc + v * g.plane;
-            A.out0.p[v] = D.cons + v * g.plane;
+            A.o[0].base.p[v] = D.acc + v * g.plane;
+            A.o[0].out.p[v] = D.cons + v * g.plane;
         }
         for (int v = 0; v < sf::NP; ++v) A.w.p[v] = D.prims + v * g.plane;
-        A.c0L = 0.5 * dt;
-        A.c0S = 0.5 * dt;
+        A.o[0].cL = 0.5 * dt;
+        A.o[0].cS = 0.5 * dt;
     }
-    flux_tile<0, NDIM, BX, BY>(A, t.y, t.z);
+    if (B.pass == 1) flux_tile<0, NDIM, BX, BY, 2>(A, t.y, t.z);
+    else flux_tile<0, NDIM, BX, BY, 1>(A, t.y, t.z);
 }
 
 __global__ __launch_bounds__(256) void kb_c2p(const DomainDev *dom, const int2 *items, int nitems)
@@ -391,6 +393,8 @@ extern "C" int rmhd_batch_create(const rmhd_params *domains, int n, void *stream
             return bfail(b, RMHD_EINVAL, "domain " + std::to_string(d) + ": " + msg);
         if (domains[d].model != RMHD_SINGLE_FLUID)
             return bfail(b, RMHD_EINVAL, "rmhd_batch_create: batched domains must be single-fluid");
+        if (domains[d].integrator != RMHD_SSP2_222)
+            return bfail(b, RMHD_EINVAL, "rmhd_batch_create: batched domains use the SSP2(222) integrator");
         if (domains[d].sigma_cell)
             return bfail(b, RMHD_EINVAL, "rmhd_batch_create: per-cell conductivity is not batched");
         rmhd_layout L;

@@ -481,16 +481,24 @@ static __global__ void k_qreset(unsigned *count)
 // ---------------------------------------------------------------------------------------
 // flux pass: FVS + WENO3 and the fused stage combiners
 // ---------------------------------------------------------------------------------------
+// One output of the flux pass: out = base + cL L + cS Psi, per interior cell (base.p[0] ==
+// nullptr: no base term; out may alias base).
+struct FluxOut {
+    CPlanes base;
+    Planes out;
+    double cL, cS;
+};
+constexpr int FLUX_MAXOUT = 3;
+
 struct FluxArgs {
-    CPlanes q, w, base;   // base.p[0] == nullptr: no base term
-    Planes out0, out1;    // out1.p[0] == nullptr: one output
-    double c0L, c0S, c1L, c1S;  // out_k = base + ckL L + ckS Psi
+    CPlanes q, w;
+    FluxOut o[FLUX_MAXOUT];   // outputs 0 .. n-1 used (the launch fixes n), the rest ignored
     Geo g;
     Phys P;
-    int fuse_bc;          // also write the ghost images of out0
-    // wnew.p[0] != nullptr: also recover the primitives of out0 (guess: w) and write them,
-    // with their ghost images, to wnew, which must not alias w (halo cells of other tiles
-    // still read w)
+    int fuse_bc;          // also write the ghost images of output 0
+    // wnew.p[0] != nullptr (single fluid only): also recover the primitives of output 0
+    // (guess: w) and write them, with their ghost images, to wnew, which must not alias w
+    // (halo cells of other tiles still read w)
     Planes wnew;
 };
 
@@ -539,7 +547,7 @@ __device__ __forceinline__ void weno3_pair(double ap, double bp, double cp, doub
 // One tile of the flux pass, both directions staged through LDS (used for 1-D blocks, whose
 // rows span several wavefronts); every thread of the block must call it (it holds
 // barriers).  (bx, by) is the tile position in units of interior tiles.
-template <int M, int NDIM, int BX, int BY>
+template <int M, int NDIM, int BX, int BY, int NO>
 __device__ __forceinline__ void flux_tile_lds(const FluxArgs &A, int bx, int by)
 {
     constexpr int NC = Model<M>::NC, NP = Model<M>::NP;
@@ -570,7 +578,7 @@ __device__ __forceinline__ void flux_tile_lds(const FluxArgs &A, int bx, int by)
     const bool do_x = tx >= 1 && tx <= BX - 2 && (NDIM == 1 || (ty >= 2 && ty <= BY - 3));
     const bool do_y = NDIM == 2 && ty >= 1 && ty <= BY - 2 && tx >= 2 && tx <= BX - 3;
 
-    // ghost images of this interior cell (fused boundary fill of out0)
+    // ghost images of this interior cell (fused boundary fill of output 0)
     int xi[3] = {i, -1, -1}, yj[3] = {j, -1, -1};
     if (A.fuse_bc && interior) {
         if (g.bc == RMHD_BC_PERIODIC) {
@@ -589,7 +597,6 @@ __device__ __forceinline__ void flux_tile_lds(const FluxArgs &A, int bx, int by)
             }
         }
     }
-    const bool has_base = A.base.p[0] != nullptr, two_out = A.out1.p[0] != nullptr;
 
 #pragma unroll
     for (int v = 0; v < NC; ++v) {
@@ -623,18 +630,29 @@ __device__ __forceinline__ void flux_tile_lds(const FluxArgs &A, int bx, int by)
                 L -= ((shp[NDIM - 1][ty][tx] + shm[NDIM - 1][ty + 1][tx]) -
                       (shp[NDIM - 1][ty - 1][tx] + shm[NDIM - 1][ty][tx])) * g.idy;
             const double S = has_source(M, v) ? src[v] : 0.0;
-            const double b = has_base ? A.base.p[v][idx] : 0.0;
-            const double o0 = b + A.c0L * L + A.c0S * S;
+            double o0 = 0.0;
 #pragma unroll
-            for (int aa = 0; aa < 3; ++aa)
+            for (int k = 0; k < NO; ++k) {
+                const FluxOut &F = A.o[k];
+                const double b = F.base.p[0] ? F.base.p[v][idx] : 0.0;
+                const double o = b + F.cL * L + F.cS * S;
+                if (k == 0) {
+                    o0 = o;
 #pragma unroll
-                for (int bb = 0; bb < (NDIM == 2 ? 3 : 1); ++bb)
-                    if (xi[aa] >= 0 && yj[bb] >= 0) A.out0.p[v][(long)yj[bb] * g.pitch + xi[aa]] = o0;
-            if (two_out) A.out1.p[v][idx] = b + A.c1L * L + A.c1S * S;
+                    for (int aa = 0; aa < 3; ++aa)
+#pragma unroll
+                        for (int bb = 0; bb < (NDIM == 2 ? 3 : 1); ++bb)
+                            if (xi[aa] >= 0 && yj[bb] >= 0) F.out.p[v][(long)yj[bb] * g.pitch + xi[aa]] = o;
+                } else {
+                    F.out.p[v][idx] = o;
+                }
+            }
             q[v] = o0;   // this thread's own q[v] is not read again
         }
     }
-    if (A.wnew.p[0] && interior) flux_recover<M>(A, q, w, xi, yj, NDIM == 2 ? 3 : 1);
+    // the two-fluid step recovers in a separate kernel, so its flux pass does not carry the code
+    if constexpr (M == 0)
+        if (A.wnew.p[0] && interior) flux_recover<M>(A, q, w, xi, yj, NDIM == 2 ? 3 : 1);
 }
 
 // Values of the lanes to the left and right in the same wavefront (a lane at the edge gets
@@ -646,7 +664,7 @@ __device__ __forceinline__ double from_right(double v) { return __shfl_down(v, 1
 // the x stencil is read from neighbouring lanes (no LDS, no barrier) and only the y stencil
 // goes through LDS, G variables per pair of barriers.  The arithmetic per face and cell is
 // that of flux_tile_lds.  Every thread of the block must call it.
-template <int M, int BY>
+template <int M, int BY, int NO>
 __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by)
 {
     constexpr int NC = Model<M>::NC, NP = Model<M>::NP;
@@ -673,7 +691,7 @@ __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by
     const bool interior = tx >= 2 && tx < BX - 2 && ii < g.nx && ty >= 2 && ty < BY - 2 && jj < g.ny;
     const bool do_y = ty >= 1 && ty <= BY - 2 && tx >= 2 && tx <= BX - 3;
 
-    // ghost images of this interior cell (fused boundary fill of out0)
+    // ghost images of this interior cell (fused boundary fill of output 0)
     int xi[3] = {i, -1, -1}, yj[3] = {j, -1, -1};
     if (A.fuse_bc && interior) {
         if (g.bc == RMHD_BC_PERIODIC) {
@@ -688,7 +706,6 @@ __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by
             if (jj == g.ny - 1) { yj[1] = g.ny + 2; yj[2] = g.ny + 3; }
         }
     }
-    const bool has_base = A.base.p[0] != nullptr, two_out = A.out1.p[0] != nullptr;
 
 #pragma unroll
     for (int v0 = 0; v0 < NC; v0 += G) {
@@ -727,37 +744,49 @@ __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by
                 double L = Lx[k];
                 L -= ((shp[k][ty][tx] + shm[k][ty + 1][tx]) - (shp[k][ty - 1][tx] + shm[k][ty][tx])) * g.idy;
                 const double S = has_source(M, v) ? src[v] : 0.0;
-                const double b = has_base ? A.base.p[v][idx] : 0.0;
-                const double o0 = b + A.c0L * L + A.c0S * S;
+                double o0 = 0.0;
 #pragma unroll
-                for (int aa = 0; aa < 3; ++aa)
+                for (int kk = 0; kk < NO; ++kk) {
+                    const FluxOut &F = A.o[kk];
+                    const double b = F.base.p[0] ? F.base.p[v][idx] : 0.0;
+                    const double o = b + F.cL * L + F.cS * S;
+                    if (kk == 0) {
+                        o0 = o;
 #pragma unroll
-                    for (int bb = 0; bb < 3; ++bb)
-                        if (xi[aa] >= 0 && yj[bb] >= 0) A.out0.p[v][(long)yj[bb] * g.pitch + xi[aa]] = o0;
-                if (two_out) A.out1.p[v][idx] = b + A.c1L * L + A.c1S * S;
+                        for (int aa = 0; aa < 3; ++aa)
+#pragma unroll
+                            for (int bb = 0; bb < 3; ++bb)
+                                if (xi[aa] >= 0 && yj[bb] >= 0) F.out.p[v][(long)yj[bb] * g.pitch + xi[aa]] = o;
+                    } else {
+                        F.out.p[v][idx] = o;
+                    }
+                }
                 q[v] = o0;   // this thread's own q[v] is not read again
             }
         }
         // the next round rewrites sfp/sfm only after every thread has passed the barrier
         // above, and shp/shm only after the next round's first barrier
     }
-    if (A.wnew.p[0] && interior) flux_recover<M>(A, q, w, xi, yj, 3);
+    if constexpr (M == 0)
+        if (A.wnew.p[0] && interior) flux_recover<M>(A, q, w, xi, yj, 3);
 }
 
 // One tile of the flux pass: single-fluid 2-D tiles with 64-wide rows use the wavefront-row
 // form, everything else the LDS form (measured: for the two-fluid model the row form's
 // extra live registers cost more than its saved LDS traffic).
-template <int M, int NDIM, int BX, int BY>
+// NO: outputs used (o[0..NO-1]), fixed at compile time so unused ones cost no registers.
+template <int M, int NDIM, int BX, int BY, int NO>
 __device__ __forceinline__ void flux_tile(const FluxArgs &A, int bx, int by)
 {
-    if constexpr (M == 0 && NDIM == 2 && BX == 64) flux_tile_rows<M, BY>(A, bx, by);
-    else flux_tile_lds<M, NDIM, BX, BY>(A, bx, by);
+    static_assert(NO >= 1 && NO <= FLUX_MAXOUT, "outputs");
+    if constexpr (M == 0 && NDIM == 2 && BX == 64) flux_tile_rows<M, BY, NO>(A, bx, by);
+    else flux_tile_lds<M, NDIM, BX, BY, NO>(A, bx, by);
 }
 
-template <int M, int NDIM, int BX, int BY>
+template <int M, int NDIM, int BX, int BY, int NO>
 __global__ __launch_bounds__(BX *BY) void k_flux(FluxArgs A)
 {
-    flux_tile<M, NDIM, BX, BY>(A, blockIdx.x, blockIdx.y);
+    flux_tile<M, NDIM, BX, BY, NO>(A, blockIdx.x, blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------------------

@@ -26,7 +26,9 @@ struct rmhd_ctx {
     double *q1src;    // stage-1 source-carrying components (NX + 2 planes)
     double *w1;       // stage-1 primitives (nprim planes)
     double *r2;       // stage-2 right-hand side, solved in place (ncons planes)
-    double *acc;      // q^n + dt/2 [L(Q1) + Psi(Q1)] (ncons planes)
+    double *acc;      // q^n + sum_j w_j dt [L(Q_j) + Psi(Q_j)], accumulated (ncons planes)
+    double *r3, *w2;  // SSP3(332): third-stage right-hand side, solved in place (ncons planes);
+                      // second-stage primitives (nprim planes)
     int8_t *status;   // one plane
     int32_t *iters;   // one plane
     unsigned long long *stats;  // STATS_SLOTS x STATS_STRIDE counters
@@ -52,7 +54,7 @@ struct rmhd_ctx {
     double *g_cons, *g_prims;
     // per-kernel event timing of rmhd_imex_step
     int timing;
-    hipEvent_t ev[10];
+    hipEvent_t ev[14];
     rmhd_timing times;
     std::string err;
 };
@@ -88,6 +90,8 @@ static int check_params_impl(const rmhd_params *p, rmhd_ctx *c)
     if (p->model == RMHD_TWO_FLUID && !p->sigma_cell && !(p->sigma > 0.0))
         return fail(c, RMHD_EINVAL, "two-fluid model needs sigma > 0 (eta = 1/sigma)");
     if (p->max_c2p_iter < 1 || p->max_newton_iter < 1) return fail(c, RMHD_EINVAL, "iteration caps must be >= 1");
+    if (p->integrator != RMHD_SSP2_222 && p->integrator != RMHD_SSP3_332)
+        return fail(c, RMHD_EINVAL, "integrator must be RMHD_SSP2_222 or RMHD_SSP3_332");
     if (!(p->c2p_tol > 0.0) || !(p->newton_tol > 0.0)) return fail(c, RMHD_EINVAL, "tolerances must be > 0");
     return RMHD_OK;
 }
@@ -153,6 +157,8 @@ extern "C" int rmhd_create(const rmhd_params *p, void *stream, rmhd_ctx **out)
     if (e == hipSuccess) e = hipMalloc((void **)&c->w1, pl * L.nprim);
     if (e == hipSuccess) e = hipMalloc((void **)&c->r2, pl * L.ncons);
     if (e == hipSuccess) e = hipMalloc((void **)&c->acc, pl * L.ncons);
+    if (e == hipSuccess && p->integrator == RMHD_SSP3_332) e = hipMalloc((void **)&c->r3, pl * L.ncons);
+    if (e == hipSuccess && p->integrator == RMHD_SSP3_332) e = hipMalloc((void **)&c->w2, pl * L.nprim);
     if (e == hipSuccess) e = hipMalloc((void **)&c->status, (size_t)L.plane);
     if (e == hipSuccess) e = hipMalloc((void **)&c->iters, (size_t)L.plane * sizeof(int32_t));
     const int nx_unk = p->model == RMHD_SINGLE_FLUID ? 3 : 7;
@@ -193,11 +199,13 @@ extern "C" void rmhd_destroy(rmhd_ctx *c)
     free_graph(c);
     if (c->gstream) hipStreamDestroy(c->gstream);
     if (c->timing)
-        for (int k = 0; k < 10; ++k) hipEventDestroy(c->ev[k]);
+        for (int k = 0; k < 14; ++k) hipEventDestroy(c->ev[k]);
     hipFree(c->q1src);
     hipFree(c->w1);
     hipFree(c->r2);
     hipFree(c->acc);
+    hipFree(c->r3);
+    hipFree(c->w2);
     hipFree(c->status);
     hipFree(c->iters);
     hipFree(c->stats);
@@ -258,13 +266,13 @@ static int launch_stage(rmhd_ctx *c, const StageArgs &A)
     return launch_stage_m<1>(c, B);
 }
 
-template <int M>
-static void launch_flux_m(rmhd_ctx *c, const FluxArgs &A)
+template <int M, int NO>
+static void launch_flux_mo(rmhd_ctx *c, const FluxArgs &A)
 {
     if (c->prm.ndim == 1) {
         constexpr int BX = 256;
         dim3 grid((c->prm.nx + (BX - 4) - 1) / (BX - 4));
-        hipLaunchKernelGGL((k_flux<M, 1, BX, 1>), grid, dim3(BX, 1), 0, c->stream, A);
+        hipLaunchKernelGGL((k_flux<M, 1, BX, 1, NO>), grid, dim3(BX, 1), 0, c->stream, A);
     } else {
         // 64 x 16 tiles (12 interior rows); 64 x 8 (4 rows) on request.  Measured on the
         // 256 x 512 grid, whose 16-row tiles leave some CUs idle, 16 rows are still faster
@@ -273,10 +281,20 @@ static void launch_flux_m(rmhd_ctx *c, const FluxArgs &A)
         const unsigned gx = (unsigned)((c->prm.nx + (BX - 4) - 1) / (BX - 4));
         const int rows = c->flux_rows ? c->flux_rows : 16;
         if (rows == 8)
-            hipLaunchKernelGGL((k_flux<M, 2, BX, 8>), dim3(gx, (c->prm.ny + 3) / 4), dim3(BX, 8), 0, c->stream, A);
+            hipLaunchKernelGGL((k_flux<M, 2, BX, 8, NO>), dim3(gx, (c->prm.ny + 3) / 4), dim3(BX, 8), 0, c->stream, A);
         else
-            hipLaunchKernelGGL((k_flux<M, 2, BX, 16>), dim3(gx, (c->prm.ny + 11) / 12), dim3(BX, 16), 0, c->stream, A);
+            hipLaunchKernelGGL((k_flux<M, 2, BX, 16, NO>), dim3(gx, (c->prm.ny + 11) / 12), dim3(BX, 16), 0,
+                               c->stream, A);
     }
+}
+
+template <int M>
+static void launch_flux_m(rmhd_ctx *c, const FluxArgs &A)
+{
+    const int n = A.o[2].out.p[0] ? 3 : A.o[1].out.p[0] ? 2 : 1;
+    if (n == 3) launch_flux_mo<M, 3>(c, A);
+    else if (n == 2) launch_flux_mo<M, 2>(c, A);
+    else launch_flux_mo<M, 1>(c, A);
 }
 
 static int launch_flux(rmhd_ctx *c, const FluxArgs &A)
@@ -324,8 +342,8 @@ extern "C" int rmhd_F(rmhd_ctx *c, double *cons, double *prims, double *Lout)
     FluxArgs A{};
     A.q = cplanes_of(cons, L, L.ncons);
     A.w = cplanes_of(prims, L, L.nprim);
-    A.out0 = planes_of(Lout, L, L.ncons);
-    A.c0L = 1.0;
+    A.o[0].out = planes_of(Lout, L, L.ncons);
+    A.o[0].cL = 1.0;
     A.g = c->geo;
     A.P = c->phys;
     return launch_flux(c, A);
@@ -396,11 +414,46 @@ extern "C" int rmhd_imex_step(rmhd_ctx *c, double dt, double *cons, double *prim
     return hip_check(c, hipGraphLaunch(c->exec, c->stream), "graph launch");
 }
 
+static FluxOut flux_out(const double *base, double *out, const rmhd_layout &L, double cL, double cS)
+{
+    FluxOut o{};
+    if (base) o.base = cplanes_of(base, L, L.ncons);
+    o.out = planes_of(out, L, L.ncons);
+    o.cL = cL;
+    o.cS = cS;
+    return o;
+}
+
+// The step as a sequence of launches (Pareschi-Russo stage sums, Table 2 or Table 3):
+//   SSP2(222)  stage 1: Q1 = q^n + g dt Psi(Q1)
+//              flux 1:  R2 = q^n + dt L1 + (1-2g) dt Psi1,   ACC = q^n + dt/2 (L1 + Psi1)
+//              stage 2: Q2 = R2 + g dt Psi(Q2)
+//              flux 2:  q^{n+1} = ACC + dt/2 (L2 + Psi2)
+//   SSP3(332)  stage 1 as above
+//              flux 1:  R2 as above,  R3 = q^n + dt/4 L1 + (1/2-g) dt Psi1,  ACC = q^n + dt/6 (L1 + Psi1)
+//              stage 2: Q2 = R2 + g dt Psi(Q2)
+//              flux 2:  R3 += dt/4 L2,  ACC += dt/6 (L2 + Psi2)
+//              stage 3: Q3 = R3 + g dt Psi(Q3)
+//              flux 3:  q^{n+1} = ACC + 2 dt/3 (L3 + Psi3)
+// Every flux pass writes the ghost images of its first output; the last one also recovers the
+// primitives (single fluid; two fluid: a separate recovery kernel), from the last stage's.
 static int enqueue_imex(rmhd_ctx *c, double dt, double *cons, double *prims)
 {
     const rmhd_layout &L = c->lay;
     const double gm = SSP2_GAMMA;
     const int M = c->prm.model;
+    const bool ssp3 = c->prm.integrator == RMHD_SSP3_332;
+    const bool fused = M == RMHD_SINGLE_FLUID;
+    // event pairs: stages, flux passes, recovery (kinds 0, 1, 2)
+    int nev = 0, kinds[7];
+    auto begin = [&]() {
+        if (c->timing) hipEventRecord(c->ev[nev], c->stream);
+    };
+    auto end = [&](int kind) {
+        if (c->timing) hipEventRecord(c->ev[nev + 1], c->stream);
+        kinds[nev / 2] = kind;
+        nev += 2;
+    };
     // Q1: the source-free components are those of q^n; the others live in scratch
     Planes Q1 = planes_of(cons, L, L.ncons);
     {
@@ -408,7 +461,6 @@ static int enqueue_imex(rmhd_ctx *c, double dt, double *cons, double *prims)
         for (int v = 0; v < L.ncons; ++v)
             if (has_source(M, v)) Q1.p[v] = c->q1src + (k++) * L.plane;
     }
-    // stage 1: Q1 = q^n + gamma dt Psi(Q1)
     StageArgs S{};
     S.R = cplanes_of(cons, L, L.ncons);
     S.win = cplanes_of(prims, L, L.nprim);
@@ -421,77 +473,97 @@ static int enqueue_imex(rmhd_ctx *c, double dt, double *cons, double *prims)
     S.g = c->geo;
     S.P = c->phys;
     S.write_all = 0;
-    auto mark = [&](int k) {
-        if (c->timing) hipEventRecord(c->ev[k], c->stream);
-    };
-    mark(0);
+    begin();
     int rc = launch_stage(c, S);
-    mark(1);
+    end(0);
     if (rc) return rc;
-    // R2 = q^n + dt L(Q1) + (1 - 2 gamma) dt Psi(Q1);  ACC = q^n + dt/2 L(Q1) + dt/2 Psi(Q1)
+
     FluxArgs F{};
     F.q = as_const(Q1);
     F.w = cplanes_of(c->w1, L, L.nprim);
-    F.base = cplanes_of(cons, L, L.ncons);
-    F.out0 = planes_of(c->r2, L, L.ncons);
-    F.out1 = planes_of(c->acc, L, L.ncons);
-    F.c0L = dt;
-    F.c0S = (1.0 - 2.0 * gm) * dt;
-    F.c1L = 0.5 * dt;
-    F.c1S = 0.5 * dt;
     F.g = c->geo;
     F.P = c->phys;
     F.fuse_bc = 1;
-    mark(2);
+    F.o[0] = flux_out(cons, c->r2, L, dt, (1.0 - 2.0 * gm) * dt);
+    if (ssp3) {
+        F.o[1] = flux_out(cons, c->r3, L, 0.25 * dt, (0.5 - gm) * dt);
+        F.o[2] = flux_out(cons, c->acc, L, dt / 6.0, dt / 6.0);
+    } else {
+        F.o[1] = flux_out(cons, c->acc, L, 0.5 * dt, 0.5 * dt);
+    }
+    begin();
     rc = launch_flux(c, F);
-    mark(3);
+    end(1);
     if (rc) return rc;
-    // stage 2: Q2 = R2 + gamma dt Psi(Q2), in place.  Single fluid: its primitives replace
-    // those of Q1 (the second flux pass reads them there and writes the new ones to the
-    // caller's array); two fluid: into the caller's array, recovered over by k_c2p.
-    const bool fused = M == RMHD_SINGLE_FLUID;
+
+    // stage 2, in place in R2
+    double *w_last = ssp3 ? c->w2 : (fused ? c->w1 : prims);   // primitives of the last stage
     S.R = cplanes_of(c->r2, L, L.ncons);
     S.win = cplanes_of(c->w1, L, L.nprim);
-    S.wout = planes_of(fused ? c->w1 : prims, L, L.nprim);
+    S.wout = planes_of(ssp3 ? c->w2 : w_last, L, L.nprim);
     S.Q = planes_of(c->r2, L, L.ncons);
-    mark(4);
+    begin();
     rc = launch_stage(c, S);
-    mark(5);
+    end(0);
     if (rc) return rc;
-    // q^{n+1} = ACC + dt/2 L(Q2) + dt/2 Psi(Q2), ghosts included, and its primitives
-    // (recovered by the thread that forms each cell, from those of Q2)
-    F.q = cplanes_of(c->r2, L, L.ncons);
-    F.w = cplanes_of(fused ? c->w1 : prims, L, L.nprim);
-    F.base = cplanes_of(c->acc, L, L.ncons);
-    F.out0 = planes_of(cons, L, L.ncons);
-    F.out1 = Planes{};
+
+    double *Qlast = c->r2;
+    if (ssp3) {
+        F = FluxArgs{};
+        F.q = cplanes_of(c->r2, L, L.ncons);
+        F.w = cplanes_of(c->w2, L, L.nprim);
+        F.g = c->geo;
+        F.P = c->phys;
+        F.fuse_bc = 1;
+        F.o[0] = flux_out(c->r3, c->r3, L, 0.25 * dt, 0.0);
+        F.o[1] = flux_out(c->acc, c->acc, L, dt / 6.0, dt / 6.0);
+        begin();
+        rc = launch_flux(c, F);
+        end(1);
+        if (rc) return rc;
+        // stage 3, in place in R3
+        w_last = fused ? c->w1 : prims;
+        S.R = cplanes_of(c->r3, L, L.ncons);
+        S.win = cplanes_of(c->w2, L, L.nprim);
+        S.wout = planes_of(w_last, L, L.nprim);
+        S.Q = planes_of(c->r3, L, L.ncons);
+        begin();
+        rc = launch_stage(c, S);
+        end(0);
+        if (rc) return rc;
+        Qlast = c->r3;
+    }
+
+    // q^{n+1} = ACC + w_last dt (L + Psi) of the last stage, ghosts included, and its
+    // primitives (recovered by the thread that forms each cell, from the last stage's)
+    const double wl = ssp3 ? 2.0 * dt / 3.0 : 0.5 * dt;
+    F = FluxArgs{};
+    F.q = cplanes_of(Qlast, L, L.ncons);
+    F.w = cplanes_of(w_last, L, L.nprim);
+    F.g = c->geo;
+    F.P = c->phys;
+    F.fuse_bc = 1;
+    F.o[0] = flux_out(c->acc, cons, L, wl, wl);
     F.wnew = fused ? planes_of(prims, L, L.nprim) : Planes{};
-    F.c0L = 0.5 * dt;
-    F.c0S = 0.5 * dt;
-    mark(6);
+    begin();
     rc = launch_flux(c, F);
-    mark(7);
+    end(1);
     if (rc) return rc;
     if (!fused) {
-        // primitives of q^{n+1} (starting from those of Q2)
-        mark(8);
+        begin();
         rc = rmhd_cons2prim(c, cons, prims, nullptr, nullptr);
-        mark(9);
+        end(2);
         if (rc) return rc;
     }
     if (!c->timing) return RMHD_OK;
-    const int last = fused ? 7 : 9;
-    rc = hip_check(c, hipEventSynchronize(c->ev[last]), "timing sync");
+    rc = hip_check(c, hipEventSynchronize(c->ev[nev - 1]), "timing sync");
     if (rc) return rc;
-    float ms[5] = {0, 0, 0, 0, 0};
-    for (int k = 0; 2 * k + 1 <= last; ++k) hipEventElapsedTime(&ms[k], c->ev[2 * k], c->ev[2 * k + 1]);
-    c->times.stage_ms += ms[0] + ms[2];
-    c->times.flux_ms += ms[1] + ms[3];
-    c->times.stage_launches += 2;
-    c->times.flux_launches += 2;
-    if (!fused) {
-        c->times.c2p_ms += ms[4];
-        c->times.c2p_launches += 1;
+    for (int k = 0; 2 * k < nev; ++k) {
+        float ms = 0.0f;
+        hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]);
+        if (kinds[k] == 0) { c->times.stage_ms += ms; c->times.stage_launches += 1; }
+        if (kinds[k] == 1) { c->times.flux_ms += ms; c->times.flux_launches += 1; }
+        if (kinds[k] == 2) { c->times.c2p_ms += ms; c->times.c2p_launches += 1; }
     }
     c->times.steps += 1;
     return RMHD_OK;
@@ -501,7 +573,7 @@ extern "C" int rmhd_set_timing(rmhd_ctx *c, int enable)
 {
     if (!c) return fail(c, RMHD_EINVAL, "rmhd_set_timing: NULL context");
     if (enable && !c->timing) {
-        for (int k = 0; k < 10; ++k) {
+        for (int k = 0; k < 14; ++k) {
             int rc = hip_check(c, hipEventCreate(&c->ev[k]), "hipEventCreate");
             if (rc) {
                 for (int m = 0; m < k; ++m) hipEventDestroy(c->ev[m]);
@@ -511,7 +583,7 @@ extern "C" int rmhd_set_timing(rmhd_ctx *c, int enable)
         c->timing = 1;
     } else if (!enable && c->timing) {
         hipStreamSynchronize(c->stream);
-        for (int k = 0; k < 10; ++k) hipEventDestroy(c->ev[k]);
+        for (int k = 0; k < 14; ++k) hipEventDestroy(c->ev[k]);
         c->timing = 0;
     }
     return RMHD_OK;

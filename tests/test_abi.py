@@ -123,3 +123,15 @@ def test_stats_record_matches_header():
     body = src[src.index("typedef struct rmhd_stats {"):src.index("} rmhd_stats;")]
     names = re.findall(r"\b(\w+)(?:\[\d+\])?;", re.sub(r"/\*.*?\*/", "", body, flags=re.S))
     assert names == [n for n, _ in R.rmhd_stats._fields_]
+
+
+def test_integrator_is_validated_and_batch_rejects_ssp3():
+    p = R.params_from(WL.kelvin_helmholtz_2d(16, 16, steps=1), integrator=2)
+    with pytest.raises(R.RmhdError, match="integrator"):
+        R.rmhd_layout_of(p)
+    if not os.path.exists(R.LIB_PATH):
+        pytest.skip("librmhd.so not built")
+    ok = R.params_from(WL.brio_wu_1d(128))
+    s3 = R.params_from(WL.brio_wu_1d(128), integrator=R.SSP3_332)
+    rc, msg = _batch_create_error([ok, s3])
+    assert rc == -1 and "SSP2" in msg

@@ -215,11 +215,11 @@ def test_implicit_stage_start_independent(R, O):
 # ------------------------------------------------------------------------------------------
 # full SSP2(222) runs
 # ------------------------------------------------------------------------------------------
-def run_both(R, O, wl, steps, t_end=None):
+def run_both(R, O, wl, steps, t_end=None, scheme="ssp2"):
     g, ocons, oprims = initial_state(wl)
     dt = O.dt(g, wl.cfl)
-    advance(g, ocons, oprims, dt, steps=steps, t_end=t_end)
-    s = gpu_solver(R, wl)
+    advance(g, ocons, oprims, dt, steps=steps, t_end=t_end, scheme=scheme)
+    s = gpu_solver(R, wl, integrator=R.SSP3_332 if scheme == "ssp3" else R.SSP2_222)
     cons, prims = s.initial_state(wl.prims, wl.EB)
     assert abs(s.dt() - dt) <= 1e-16 * dt
     t, n = 0.0, 0
@@ -288,6 +288,23 @@ def test_newton_cap_queue_agrees_with_uninterrupted_solve(R, O, model):
         assert abs(st["newton_max"] - ref[2]["newton_max"]) <= 1
         assert np.all(rel_linf(c, ref[0]) < 1e-9) and np.all(rel_linf(p, ref[1]) < 1e-9)
         assert np.all(rel_linf(c, oc) < 1e-9)
+
+
+@pytest.mark.parametrize("case", ["brio_wu", "khi", "sheet"])
+def test_ssp3_steps_match_oracle(R, O, case):
+    """SSP3(332) (Table 3) on the GPU against the oracle's SSP3 step: Brio-Wu and ragged KHI
+    100 steps, the two-fluid sheet with per-cell conductivity 50 steps."""
+    banner(f"SSP3(332) {case}")
+    wl, steps = {"brio_wu": (WL.brio_wu_1d(), 100),
+                 "khi": (WL.kelvin_helmholtz_2d(70, 37, steps=100, seed=31), 100),
+                 "sheet": (WL.two_fluid_sheet_2d(48, 40, steps=50, seed=32, sigma_range=(1e2, 1e6)), 50)}[case]
+    g, oc, op, gc, gp, st = run_both(R, O, wl, steps, scheme="ssp3")
+    assert st["failures"] == 0
+    assert st["stage_cells"] == 3 * steps * wl.cells
+    err = rel_linf(gc, oc)
+    print("rel Linf per variable", err)
+    assert np.all(err < 1e-9)
+    assert np.all(rel_linf(gp, op) < 1e-9)
 
 
 def family_scale(g, c):
@@ -386,16 +403,16 @@ def test_padding_is_never_read(R, O):
     np.testing.assert_array_equal(a, b)
 
 
-@pytest.mark.parametrize("model", [0, 1])
-def test_graph_replays_match_eager_steps(R, O, model):
+@pytest.mark.parametrize("model,integrator", [(0, 0), (1, 0), (0, 1)])
+def test_graph_replays_match_eager_steps(R, O, model, integrator):
     """The step replayed from its captured graph equals the directly launched step bit for bit
     at every replay, with unrelated eager work and synchronisation between replays and a
     change of dt (which captures again) in the middle."""
-    banner(f"single-grid graph replays model={model}")
+    banner(f"single-grid graph replays model={model} integrator={integrator}")
     import torch
     wl = (WL.kelvin_helmholtz_2d(70, 37, steps=5, seed=21) if model == 0 else
           WL.two_fluid_sheet_2d(40, 28, steps=5, seed=22, sigma_range=(1e2, 1e6)))
-    sg, se = gpu_solver(R, wl), gpu_solver(R, wl)
+    sg, se = gpu_solver(R, wl, integrator=integrator), gpu_solver(R, wl, integrator=integrator)
     sg.set_graph(True)
     cg, pg = sg.initial_state(wl.prims, wl.EB)
     ce, pe = se.initial_state(wl.prims, wl.EB)
@@ -409,6 +426,6 @@ def test_graph_replays_match_eager_steps(R, O, model):
         torch.cuda.synchronize()
         np.testing.assert_array_equal(sg.grid.download_all(cg), se.grid.download_all(ce))
         np.testing.assert_array_equal(sg.grid.download_all(pg), se.grid.download_all(pe))
-    assert sg.stats()["stage_cells"] == se.stats()["stage_cells"] == 2 * 5 * wl.cells
+    assert sg.stats()["stage_cells"] == se.stats()["stage_cells"] == (3 if integrator else 2) * 5 * wl.cells
     sg.close()
     se.close()
