@@ -221,7 +221,9 @@ struct BatchFluxArgs {
 template <int NDIM, int BX, int BY>
 __global__ __launch_bounds__(BX *BY) void kb_flux(BatchFluxArgs B)
 {
-    const int4 t = B.tiles[blockIdx.x];
+    // tiles are listed domain by domain in row-major order: the XCD-aware renumbering keeps
+    // neighbouring tiles of a domain on one XCD
+    const int4 t = B.tiles[xcd_order(blockIdx.x, gridDim.x)];
     const DomainDev &D = B.dom[t.x];
     const Geo &g = D.g;
     const double gm = SSP2_GAMMA;

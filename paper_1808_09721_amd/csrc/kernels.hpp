@@ -783,10 +783,27 @@ __device__ __forceinline__ void flux_tile(const FluxArgs &A, int bx, int by)
     else flux_tile_lds<M, NDIM, BX, BY, NO>(A, bx, by);
 }
 
+// Workgroups are dealt to the 8 XCDs in turn (linear id mod 8), each XCD with its own L2.
+// Renumbering so that each XCD receives one contiguous run of tiles (row-major) keeps the
+// halo rows that vertically adjacent tiles share inside one L2.  A bijection of the tiles.
+__device__ __forceinline__ int xcd_order(int lin, int n)
+{
+    const int q = n >> 3, r = n & 7, x = lin & 7, slot = lin >> 3;
+    return x * q + min(x, r) + slot;
+}
+__device__ __forceinline__ void xcd_tile(int &bx, int &by)
+{
+    const int t = xcd_order(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    bx = t % gridDim.x;
+    by = t / gridDim.x;
+}
+
 template <int M, int NDIM, int BX, int BY, int NO>
 __global__ __launch_bounds__(BX *BY) void k_flux(FluxArgs A)
 {
-    flux_tile<M, NDIM, BX, BY, NO>(A, blockIdx.x, blockIdx.y);
+    int bx = blockIdx.x, by = blockIdx.y;
+    if constexpr (NDIM == 2) xcd_tile(bx, by);
+    flux_tile<M, NDIM, BX, BY, NO>(A, bx, by);
 }
 
 // ---------------------------------------------------------------------------------------
