@@ -84,7 +84,9 @@ typedef struct rmhd_params {
     double c2p_tol;           /* primitive-recovery residual tolerance (1e-13, Sec. 2.1.3) */
     double newton_tol;        /* implicit-stage residual tolerance (e.g. 1e-12) */
     int32_t integrator;       /* RMHD_SSP2_222 (0, Table 2) or RMHD_SSP3_332 (1, Table 3) */
-    int32_t reserved_;        /* must be 0 */
+    int32_t c2p_primary_only; /* 0: where the recovery's z = rho h W^2 iteration does not
+                                 converge, a Newton iteration on the pressure takes over (the
+                                 paper keeps two residuals, Sec. 2.1.3); 1: z iteration only */
 } rmhd_params;
 
 typedef struct rmhd_layout {

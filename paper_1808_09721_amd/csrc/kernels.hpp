@@ -871,6 +871,7 @@ static inline Phys phys_from(const rmhd_params *p)
     P.max_c2p = p->max_c2p_iter;
     P.max_newton = p->max_newton_iter;
     P.friction_covariant = p->friction_covariant;
+    P.c2p_fallback = p->c2p_primary_only ? 0 : 1;
     return P;
 }
 

@@ -37,7 +37,7 @@ struct Phys {
     double c2p_tol, newton_tol;
     int max_c2p, max_newton;
     int friction_covariant;
-    int pad_;
+    int c2p_fallback;  // 1: the pressure residual takes over where the z residual fails
 };
 
 __device__ __forceinline__ double cell_sigma(const Phys &P, long idx)
@@ -180,7 +180,7 @@ struct Root {
     int iters;
 };
 
-__device__ __forceinline__ Root fluid_root(double D, double s2, double Eh, double zguess, const Phys &P)
+__device__ __forceinline__ Root fluid_root_z(double D, double s2, double Eh, double zguess, const Phys &P)
 {
     Root r;
     r.iters = 0;
@@ -221,6 +221,68 @@ __device__ __forceinline__ Root fluid_root(double D, double s2, double Eh, doubl
     const double u = 1.0 - s2 * iz * iz;
     r.iW = u * frsqrt(u);
     if (r.status == CELL_OK && !(r.iW > 0.0)) r.status = CELL_C2P_UNPHYS;
+    return r;
+}
+
+// The second recovery residual (Sec. 2.1.3 keeps two, so that one can take over where the
+// other fails): Newton on the pressure, f(p) = (Gamma - 1) rho eps - p with Q = E_h + p,
+// v^2 = s^2/Q^2, rho = D sqrt(1 - v^2), rho eps = Q (1 - v^2) - rho - p, and
+// f'(p) = (Gamma - 1) v^2 (1 - D W / Q) - 1, bracketed on (max(s - E_h, 0), (Gamma - 1) E_h]
+// with bisection where a Newton step leaves the bracket.  Same root as fluid_root_z
+// (z = Q = E_h + p), returned in the same form.
+__device__ __forceinline__ Root fluid_root_p(double D, double s2, double Eh, double pguess, const Phys &P)
+{
+    Root r;
+    r.iters = 0;
+    r.iW = 1.0;
+    const double s = sqrt(s2);
+    double lo = fmax(s - Eh, 0.0), hi = (P.gamma - 1.0) * Eh;
+    r.z = Eh + pguess;
+    if (!(D > 0.0) || !(Eh > 0.0) || !(hi > lo)) {
+        r.status = CELL_C2P_UNPHYS;
+        return r;
+    }
+    double p = (pguess > lo && pguess < hi) ? pguess : 0.5 * (lo + hi);
+    r.status = CELL_C2P_NOCONV;
+    for (int it = 1; it <= P.max_c2p; ++it) {
+        const double Q = Eh + p, iQ = frcp(Q);
+        const double v2 = s2 * iQ * iQ, u = 1.0 - v2;
+        const double W = frsqrt(u);
+        const double f = (P.gamma - 1.0) * (Q * u - D * u * W - p) - p;
+        const double df = (P.gamma - 1.0) * v2 * (1.0 - D * W * iQ) - 1.0;
+        if (f > 0.0) lo = p; else hi = p;
+        double pn = p - f * frcp(df);
+        if (fabs(f) <= P.c2p_tol * fmax(1.0, p)) {
+            if (pn >= 0.0 && Eh + pn > s) p = pn;
+            r.status = CELL_OK;
+            r.iters = it;
+            break;
+        }
+        if (!(pn > lo && pn < hi)) pn = 0.5 * (lo + hi);
+        p = pn;
+        r.iters = it;
+    }
+    r.z = Eh + p;
+    const double iz = frcp(r.z);
+    const double u = 1.0 - s2 * iz * iz;
+    r.iW = u * frsqrt(u);
+    if (r.status == CELL_OK && !(r.iW > 0.0)) r.status = CELL_C2P_UNPHYS;
+    return r;
+}
+
+// Recovery of one fluid: the z residual, and where it does not converge (unless
+// P.c2p_fallback is 0) the pressure residual, started from the last z iterate.  The z
+// residual stalls above its tolerance where rounding in z - Eh exceeds it (large rho h W^2
+// against max(1, p)); the pressure residual then usually still converges.  The iterations
+// of both count.
+__device__ __forceinline__ Root fluid_root(double D, double s2, double Eh, double zguess, const Phys &P)
+{
+    Root r = fluid_root_z(D, s2, Eh, zguess, P);
+    if (r.status == CELL_C2P_NOCONV && P.c2p_fallback) {
+        const int used = r.iters;
+        r = fluid_root_p(D, s2, Eh, r.z - Eh, P);
+        r.iters += used;
+    }
     return r;
 }
 

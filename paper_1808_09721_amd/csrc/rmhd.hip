@@ -92,6 +92,8 @@ static int check_params_impl(const rmhd_params *p, rmhd_ctx *c)
     if (p->max_c2p_iter < 1 || p->max_newton_iter < 1) return fail(c, RMHD_EINVAL, "iteration caps must be >= 1");
     if (p->integrator != RMHD_SSP2_222 && p->integrator != RMHD_SSP3_332)
         return fail(c, RMHD_EINVAL, "integrator must be RMHD_SSP2_222 or RMHD_SSP3_332");
+    if (p->c2p_primary_only != 0 && p->c2p_primary_only != 1)
+        return fail(c, RMHD_EINVAL, "c2p_primary_only must be 0 or 1");
     if (!(p->c2p_tol > 0.0) || !(p->newton_tol > 0.0)) return fail(c, RMHD_EINVAL, "tolerances must be > 0");
     return RMHD_OK;
 }

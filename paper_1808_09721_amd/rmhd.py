@@ -32,7 +32,7 @@ class rmhd_params(ctypes.Structure):
         ("gamma_eos", ctypes.c_double), ("sigma", ctypes.c_double), ("sigma_cell", ctypes.c_void_p),
         ("mu1", ctypes.c_double), ("mu2", ctypes.c_double), ("kappa", ctypes.c_double), ("cfl", ctypes.c_double),
         ("c2p_tol", ctypes.c_double), ("newton_tol", ctypes.c_double),
-        ("integrator", ctypes.c_int32), ("reserved_", ctypes.c_int32),
+        ("integrator", ctypes.c_int32), ("c2p_primary_only", ctypes.c_int32),
     ]
 
 
@@ -156,7 +156,7 @@ SSP2_222, SSP3_332 = 0, 1
 
 
 def params_from(wl, sigma_cell=None, c2p_tol=1e-13, newton_tol=1e-12, max_c2p_iter=100, max_newton_iter=50,
-                friction_covariant=0, integrator=SSP2_222) -> rmhd_params:
+                friction_covariant=0, integrator=SSP2_222, c2p_primary_only=0) -> rmhd_params:
     """rmhd_params from a workload description (paper_1808_09721_amd.workloads.Workload)."""
     p = rmhd_params()
     p.model, p.ndim, p.nx, p.ny, p.bc = wl.model, wl.ndim, wl.nx, wl.ny if wl.ndim == 2 else 1, wl.bc
@@ -167,6 +167,7 @@ def params_from(wl, sigma_cell=None, c2p_tol=1e-13, newton_tol=1e-12, max_c2p_it
     p.mu1, p.mu2, p.kappa, p.cfl = wl.mu1, wl.mu2, wl.kappa, wl.cfl
     p.c2p_tol, p.newton_tol = c2p_tol, newton_tol
     p.integrator = integrator
+    p.c2p_primary_only = c2p_primary_only
     return p
 
 

@@ -125,6 +125,14 @@ def test_stats_record_matches_header():
     assert names == [n for n, _ in R.rmhd_stats._fields_]
 
 
+def test_recovery_fallback_switch_is_validated():
+    p = R.params_from(WL.kelvin_helmholtz_2d(16, 16, steps=1), c2p_primary_only=2)
+    with pytest.raises(R.RmhdError, match="c2p_primary_only"):
+        R.rmhd_layout_of(p)
+    for v in (0, 1):
+        R.rmhd_layout_of(R.params_from(WL.kelvin_helmholtz_2d(16, 16, steps=1), c2p_primary_only=v))
+
+
 def test_integrator_is_validated_and_batch_rejects_ssp3():
     p = R.params_from(WL.kelvin_helmholtz_2d(16, 16, steps=1), integrator=2)
     with pytest.raises(R.RmhdError, match="integrator"):

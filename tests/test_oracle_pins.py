@@ -179,6 +179,43 @@ def test_c2p_forward_roundtrip_well_conditioned(model, gamma, wmax, lpr):
     assert worst < 1e-12
 
 
+@pytest.mark.parametrize("model", [0, 1])
+def test_c2p_cold_fast_dense_states(model):
+    """Cold, fast, dense states (one fluid: W <= 100, rho in [0.1, 1e3], p/rho in [1e-4, 1];
+    two fluids: W_s <= 30, rho_s within a factor 2 of 100, p/rho in [1e-4, 0.1]), where the
+    rest-mass energy dwarfs the pressure: the pressure residual converges on every state, the
+    recovered primitives reproduce the conserved state to round-off, and they match the
+    generating primitives within the conditioning of the map: 1 - v^2 = 1/W^2 loses a factor
+    W^2 to cancellation, so the conserved state comes back to max(2e-13, 8 eps W^2) relative,
+    rho and v carry 64 eps W^2 relative error, and p an absolute 1e-12 max(1, p) +
+    64 eps max(rho h W^2), the maximum taken over the species (the split of the summed state
+    into species spreads the rounding of the larger one over both)."""
+    O = _O()
+    if model == 0:
+        g = sf_grid(4.0 / 3.0)
+        prims, EB = WL.random_states(600, 0, seed=203, w_max=100.0, field_max=1.0, log_rho=(-1, 3),
+                                     log_p_over_rho=(-4, 0))
+    else:
+        g = tf_grid()
+        prims, EB = WL.random_states(600, 1, seed=204, w_max=30.0, field_max=1.0, log_rho=(1.7, 2.3),
+                                     log_p_over_rho=(-4, -1))
+    eps = np.finfo(float).eps
+    for k in range(len(prims)):
+        q = O.prim2cons_cell(g, prims[k], EB[k])
+        w, st, _ = O.cons2prim_cell(g, q)
+        assert st == O.OK
+        sp = [prims[k, 5 * s:5 * s + 5] for s in range(len(w) // 5)]
+        W2s = [1.0 / (1.0 - ps[1:4] @ ps[1:4]) for ps in sp]
+        zmax = max(ps[0] * (1.0 + g.gamma / (g.gamma - 1.0) * ps[4] / ps[0]) * W2 for ps, W2 in zip(sp, W2s))
+        q2 = O.prim2cons_cell(g, w, EB[k])
+        assert np.max(np.abs(q2 - q)) <= max(2e-13, 8 * eps * max(W2s)) * np.max(np.abs(q))
+        for s, (ps, W2) in enumerate(zip(sp, W2s)):
+            ws = w[5 * s:5 * s + 5]
+            rel = max(64 * eps * W2, 1e-12)
+            assert abs(ws[0] / ps[0] - 1) <= rel and np.max(np.abs(ws[1:4] - ps[1:4])) <= rel
+            assert abs(ws[4] - ps[4]) <= 1e-12 * max(1.0, ps[4]) + 64 * eps * zmax
+
+
 def test_c2p_independent_of_guess_and_flags_unphysical():
     O = _O()
     g = sf_grid()
