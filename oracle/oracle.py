@@ -5,7 +5,7 @@ CPU-baseline leg of ``bench.py`` may import this module.  It never imports the p
 package; the product never imports it.
 
 Arrays use the oracle's own layout ``[var][NY][NX]`` (``NX = nx + 4``; ``NY = ny + 4`` in
-2-D, 1 in 1-D), float64, C-contiguous.
+2-D, 1 in 1-D) or, in 3-D, ``[var][NZ][NY][NX]`` (``NZ = nz + 4``), float64, C-contiguous.
 """
 from __future__ import annotations
 
@@ -42,6 +42,7 @@ class _Params(ctypes.Structure):
         ("sigma", ctypes.c_double), ("mu1", ctypes.c_double), ("mu2", ctypes.c_double),
         ("kappa", ctypes.c_double), ("c2p_tol", ctypes.c_double), ("newton_tol", ctypes.c_double),
         ("sigma_cell", ctypes.POINTER(ctypes.c_double)),
+        ("nz", ctypes.c_int), ("dz", ctypes.c_double),
     ]
 
 
@@ -111,7 +112,9 @@ class Grid:
     max_c2p_iter: int = 100
     max_newton_iter: int = 50
     friction_covariant: int = 0
-    sigma_cell: np.ndarray | None = None   # [NY][NX] or None
+    sigma_cell: np.ndarray | None = None   # cell shape ([NY][NX], 3-D [NZ][NY][NX]) or None
+    nz: int = 1
+    dz: float = 1.0
     _keep: list = field(default_factory=list, repr=False)
 
     @property
@@ -120,7 +123,16 @@ class Grid:
 
     @property
     def NY(self) -> int:
-        return self.ny + 4 if self.ndim == 2 else 1
+        return self.ny + 4 if self.ndim >= 2 else 1
+
+    @property
+    def NZ(self) -> int:
+        return self.nz + 4 if self.ndim == 3 else 1
+
+    @property
+    def cell_shape(self) -> tuple:
+        """Shape of one variable's array: (NY, NX), or (NZ, NY, NX) in 3-D."""
+        return (self.NZ, self.NY, self.NX) if self.ndim == 3 else (self.NY, self.NX)
 
     @property
     def ncons(self) -> int:
@@ -131,16 +143,19 @@ class Grid:
         return 5 if self.model == 0 else 10
 
     def interior(self, a: np.ndarray) -> np.ndarray:
-        """View of the interior cells of a [var][NY][NX] array."""
+        """View of the interior cells of a [var][NY][NX] (3-D: [var][NZ][NY][NX]) array."""
+        if self.ndim == 3:
+            return a[..., 2:-2, 2:-2, 2:-2]
         if self.ndim == 2:
             return a[..., 2:-2, 2:-2]
         return a[..., :, 2:-2]
 
     def zeros(self, nvar: int) -> np.ndarray:
-        return np.zeros((nvar, self.NY, self.NX))
+        return np.zeros((nvar,) + self.cell_shape)
 
     def embed(self, interior: np.ndarray) -> np.ndarray:
-        """[var][ny][nx] interior values -> [var][NY][NX] with zero ghosts."""
+        """[var][ny][nx] (3-D: [var][nz][ny][nx]) interior values -> the full layout with zero
+        ghosts."""
         out = self.zeros(interior.shape[0])
         self.interior(out)[...] = interior.reshape(self.interior(out).shape)
         return out
@@ -238,8 +253,8 @@ def init_state(g: Grid, prims: np.ndarray, EB: np.ndarray) -> np.ndarray:
 
 def cons2prim(g: Grid, cons: np.ndarray, prims_guess: np.ndarray):
     prims = np.array(prims_guess, dtype=np.float64, order="C")
-    status = np.zeros((g.NY, g.NX), dtype=np.int8)
-    iters = np.zeros((g.NY, g.NX), dtype=np.int32)
+    status = np.zeros(g.cell_shape, dtype=np.int8)
+    iters = np.zeros(g.cell_shape, dtype=np.int32)
     lib().orc_cons2prim(ctypes.byref(g.params()), _dp(np.ascontiguousarray(cons)), _dp(prims),
                         status.ctypes.data, iters.ctypes.data)
     return prims, status, iters
@@ -255,8 +270,8 @@ def rhs(g: Grid, cons: np.ndarray, prims: np.ndarray) -> np.ndarray:
 def implicit(g: Grid, a: float, R: np.ndarray, prims_guess: np.ndarray):
     Q = g.zeros(g.ncons)
     prims = np.array(prims_guess, dtype=np.float64, order="C")
-    status = np.zeros((g.NY, g.NX), dtype=np.int8)
-    iters = np.zeros((g.NY, g.NX), dtype=np.int32)
+    status = np.zeros(g.cell_shape, dtype=np.int8)
+    iters = np.zeros(g.cell_shape, dtype=np.int32)
     lib().orc_implicit(ctypes.byref(g.params()), float(a), _dp(np.ascontiguousarray(R)), _dp(Q), _dp(prims),
                        status.ctypes.data, iters.ctypes.data)
     return Q, prims, status, iters

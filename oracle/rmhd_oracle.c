@@ -389,7 +389,7 @@ static int stage_residual(const stage_t *c, const double *x, double *w, double *
     int st = orc_cons2prim_cell(c->p, q, w, &it);
     if (st != ORC_OK) return st;
     orc_source_cell(c->p, q, w, c->sigma, s);
-    for (int k = 0; k < MAXC; ++k)
+    for (int k = 0; k < orc_ncons(c->p->model); ++k)
         if (!isfinite(s[k])) return ORC_C2P_UNPHYS;
     const double *R = c->R, a = c->a;
     if (c->p->model == 0) {
@@ -587,11 +587,24 @@ void orc_weno3_face(const double *fa, const double *fb, const double *fc, double
 /* ------------------------------------------------------------------------------------------
  * Grid helpers
  * ---------------------------------------------------------------------------------------- */
+/* Cell (i, j, k) of a [var][NZ][NY][NX] array lives at v * plane + (k * NY + j) * NX + i;
+ * NY = 1 in 1-D, NZ = 1 below 3-D.  The interior rows (j, k) are numbered r = 0, 1, ... with
+ * j fastest. */
 static int NXg(const orc_params *p) { return p->nx + 4; }
-static int NYg(const orc_params *p) { return p->ndim == 2 ? p->ny + 4 : 1; }
-static long plane(const orc_params *p) { return (long)NXg(p) * NYg(p); }
-static int jlo(const orc_params *p) { return p->ndim == 2 ? 2 : 0; }
-static int jhi(const orc_params *p) { return p->ndim == 2 ? p->ny + 2 : 1; }
+static int NYg(const orc_params *p) { return p->ndim >= 2 ? p->ny + 4 : 1; }
+static int NZg(const orc_params *p) { return p->ndim == 3 ? p->nz + 4 : 1; }
+static long plane(const orc_params *p) { return (long)NXg(p) * NYg(p) * NZg(p); }
+static long nrows(const orc_params *p)
+{
+    return (long)(p->ndim >= 2 ? p->ny : 1) * (p->ndim == 3 ? p->nz : 1);
+}
+static long row_base(const orc_params *p, long r)
+{
+    const int ny = p->ndim >= 2 ? p->ny : 1;
+    const long j = r % ny + (p->ndim >= 2 ? 2 : 0);
+    const long k = r / ny + (p->ndim == 3 ? 2 : 0);
+    return (k * NYg(p) + j) * NXg(p);
+}
 static double cell_sigma(const orc_params *p, long idx) { return p->sigma_cell ? p->sigma_cell[idx] : p->sigma; }
 
 static void gather(const double *arr, long pl, long idx, int n, double *out)
@@ -605,37 +618,54 @@ static void scatter(double *arr, long pl, long idx, int n, const double *in)
 
 /* Boundary conditions on two ghost layers: outflow copies the nearest interior cell (zero
  * gradient), periodic wraps.  x ghosts are filled on the interior rows first, then y ghosts
- * on every column, which fills the corners consistently. */
+ * on every column of the interior z planes, then z ghosts on every (x, y) column, which
+ * fills edges and corners consistently. */
 void orc_bc_fill(const orc_params *p, double *arr, int nvar)
 {
-    const int NX = NXg(p), NY = NYg(p), nx = p->nx, ny = p->ny;
-    const long pl = plane(p);
+    const int NX = NXg(p), NY = NYg(p), nx = p->nx, ny = p->ny, nz = p->nz;
+    const long pl = plane(p), slab = (long)NX * NY;
     for (int v = 0; v < nvar; ++v) {
         double *a = arr + v * pl;
-        for (int j = jlo(p); j < jhi(p); ++j)
+        for (long r = 0; r < nrows(p); ++r) {
+            double *row = a + row_base(p, r);
             for (int g = 0; g < 2; ++g) {
                 const int il = g, ir = nx + 2 + g; /* ghost columns 0,1 and nx+2,nx+3 */
                 if (p->bc == 1) {
-                    a[(long)j * NX + il] = a[(long)j * NX + il + nx];
-                    a[(long)j * NX + ir] = a[(long)j * NX + ir - nx];
+                    row[il] = row[il + nx];
+                    row[ir] = row[ir - nx];
                 } else {
-                    a[(long)j * NX + il] = a[(long)j * NX + 2];
-                    a[(long)j * NX + ir] = a[(long)j * NX + nx + 1];
+                    row[il] = row[2];
+                    row[ir] = row[nx + 1];
                 }
             }
-        if (p->ndim == 2)
-            for (int i = 0; i < NX; ++i)
+        }
+        if (p->ndim >= 2)
+            for (int k = (p->ndim == 3 ? 2 : 0); k < (p->ndim == 3 ? nz + 2 : 1); ++k) {
+                double *b = a + k * slab;
+                for (int i = 0; i < NX; ++i)
+                    for (int g = 0; g < 2; ++g) {
+                        const int jl = g, jr = ny + 2 + g;
+                        if (p->bc == 1) {
+                            b[(long)jl * NX + i] = b[(long)(jl + ny) * NX + i];
+                            b[(long)jr * NX + i] = b[(long)(jr - ny) * NX + i];
+                        } else {
+                            b[(long)jl * NX + i] = b[(long)2 * NX + i];
+                            b[(long)jr * NX + i] = b[(long)(ny + 1) * NX + i];
+                        }
+                    }
+            }
+        if (p->ndim == 3)
+            for (long c = 0; c < slab; ++c)
                 for (int g = 0; g < 2; ++g) {
-                    const int jl = g, jr = ny + 2 + g;
+                    const int kl = g, kr = nz + 2 + g;
                     if (p->bc == 1) {
-                        a[(long)jl * NX + i] = a[(long)(jl + ny) * NX + i];
-                        a[(long)jr * NX + i] = a[(long)(jr - ny) * NX + i];
+                        a[kl * slab + c] = a[(kl + nz) * slab + c];
+                        a[kr * slab + c] = a[(kr - nz) * slab + c];
                     } else {
-                        a[(long)jl * NX + i] = a[(long)2 * NX + i];
-                        a[(long)jr * NX + i] = a[(long)(ny + 1) * NX + i];
+                        a[kl * slab + c] = a[2 * slab + c];
+                        a[kr * slab + c] = a[(nz + 1) * slab + c];
                     }
                 }
-        (void)NY;
     }
 }
 
@@ -645,19 +675,20 @@ void orc_bc_fill(const orc_params *p, double *arr, int nvar)
 void orc_init_state(const orc_params *p, const double *prims, const double *EB, double *cons)
 {
     const int NX = NXg(p);
-    const long pl = plane(p);
+    const long pl = plane(p), slab = (long)NX * NYg(p);
     const int np = orc_nprim(p->model), nc = orc_ncons(p->model);
     double *E = (double *)malloc(sizeof(double) * 6 * pl);
     memcpy(E, EB, sizeof(double) * 6 * pl);
     orc_bc_fill(p, E, 6);
-    for (int j = jlo(p); j < jhi(p); ++j)
+    for (long r = 0; r < nrows(p); ++r)
         for (int i = 2; i < p->nx + 2; ++i) {
-            const long idx = (long)j * NX + i;
+            const long idx = row_base(p, r) + i;
             double w[MAXP], eb[6], q[MAXC];
             gather(prims, pl, idx, np, w);
             gather(E, pl, idx, 6, eb);
             double div = (E[3 * pl + idx + 1] - E[3 * pl + idx - 1]) / (2.0 * p->dx);
-            if (p->ndim == 2) div += (E[4 * pl + idx + NX] - E[4 * pl + idx - NX]) / (2.0 * p->dy);
+            if (p->ndim >= 2) div += (E[4 * pl + idx + NX] - E[4 * pl + idx - NX]) / (2.0 * p->dy);
+            if (p->ndim == 3) div += (E[5 * pl + idx + slab] - E[5 * pl + idx - slab]) / (2.0 * p->dz);
             orc_prim2cons_cell(p, w, eb, div, q);
             scatter(cons, pl, idx, nc, q);
         }
@@ -684,25 +715,27 @@ void orc_cons2prim(const orc_params *p, const double *cons, double *prims, signe
 }
 
 /* Numerical flux function L(q) = -d_k f^k(q) (Sec. 2.2.1, Eq. 9) on the interior cells:
- * L_i = -(F_{i+1/2} - F_{i-1/2})/dx - (G_{j+1/2} - G_{j-1/2})/dy, with the face fluxes from
- * the split-and-reconstruct procedure above.  Ghost cells of cons and prims must be valid. */
+ * L_i = -(F_{i+1/2} - F_{i-1/2})/dx - (G_{j+1/2} - G_{j-1/2})/dy - (H_{k+1/2} - H_{k-1/2})/dz,
+ * one term per dimension, with the face fluxes from the split-and-reconstruct procedure
+ * above.  Ghost cells of cons and prims must be valid. */
 void orc_rhs(const orc_params *p, const double *cons, const double *prims, double *L)
 {
     const int NX = NXg(p), nc = orc_ncons(p->model), np = orc_nprim(p->model);
     const long pl = plane(p);
     for (long k = 0; k < nc * pl; ++k) L[k] = 0.0;
 #pragma omp parallel for schedule(static)
-    for (int j = jlo(p); j < jhi(p); ++j)
+    for (long r = 0; r < nrows(p); ++r)
         for (int i = 2; i < p->nx + 2; ++i) {
+            const long c = row_base(p, r) + i;
             double Lc[MAXC];
             for (int v = 0; v < nc; ++v) Lc[v] = 0.0;
             for (int dir = 0; dir < p->ndim; ++dir) {
-                const long stride = dir == 0 ? 1 : NX;
-                const double h = dir == 0 ? p->dx : p->dy;
+                const long stride = dir == 0 ? 1 : dir == 1 ? NX : (long)NX * NYg(p);
+                const double h = dir == 0 ? p->dx : dir == 1 ? p->dy : p->dz;
                 /* split fluxes at the five cells i-2..i+2 along dir */
                 double fp[5][MAXC], fm[5][MAXC];
                 for (int o = -2; o <= 2; ++o) {
-                    const long idx = (long)j * NX + i + o * stride;
+                    const long idx = c + o * stride;
                     double q[MAXC], w[MAXP], f[MAXC];
                     gather(cons, pl, idx, nc, q);
                     gather(prims, pl, idx, np, w);
@@ -722,20 +755,20 @@ void orc_rhs(const orc_params *p, const double *cons, const double *prims, doubl
                 for (int v = 0; v < nc; ++v)
                     Lc[v] -= ((Fr_p[v] + Fr_m[v]) - (Fl_p[v] + Fl_m[v])) / h;
             }
-            scatter(L, pl, (long)j * NX + i, nc, Lc);
+            scatter(L, pl, c, nc, Lc);
         }
 }
 
 /* Source Psi on the interior cells (zero elsewhere). */
 static void source_grid(const orc_params *p, const double *cons, const double *prims, double *S)
 {
-    const int NX = NXg(p), nc = orc_ncons(p->model), np = orc_nprim(p->model);
+    const int nc = orc_ncons(p->model), np = orc_nprim(p->model);
     const long pl = plane(p);
     for (long k = 0; k < nc * pl; ++k) S[k] = 0.0;
 #pragma omp parallel for schedule(static)
-    for (int j = jlo(p); j < jhi(p); ++j)
+    for (long r = 0; r < nrows(p); ++r)
         for (int i = 2; i < p->nx + 2; ++i) {
-            const long idx = (long)j * NX + i;
+            const long idx = row_base(p, r) + i;
             double q[MAXC], w[MAXP], s[MAXC];
             gather(cons, pl, idx, nc, q);
             gather(prims, pl, idx, np, w);
@@ -749,13 +782,13 @@ static void source_grid(const orc_params *p, const double *cons, const double *p
 void orc_implicit(const orc_params *p, double a, const double *R, double *Q, double *prims, signed char *status,
                   int *iters)
 {
-    const int NX = NXg(p), nc = orc_ncons(p->model), np = orc_nprim(p->model);
+    const int nc = orc_ncons(p->model), np = orc_nprim(p->model);
     const long pl = plane(p);
     memcpy(Q, R, sizeof(double) * nc * pl);
 #pragma omp parallel for schedule(dynamic, 16)
-    for (int j = jlo(p); j < jhi(p); ++j)
+    for (long r = 0; r < nrows(p); ++r)
         for (int i = 2; i < p->nx + 2; ++i) {
-            const long idx = (long)j * NX + i;
+            const long idx = row_base(p, r) + i;
             double r[MAXC], q[MAXC], w[MAXP];
             int it = 0;
             gather(R, pl, idx, nc, r);
@@ -782,7 +815,7 @@ int orc_ssp2_step(const orc_params *p, double dt, double *cons, double *prims, l
                   int *max_newton, int *nfail)
 {
     const double g = 1.0 - 1.0 / sqrt(2.0);
-    const int NX = NXg(p), nc = orc_ncons(p->model), np = orc_nprim(p->model);
+    const int nc = orc_ncons(p->model), np = orc_nprim(p->model);
     const long pl = plane(p);
     double *Q1 = malloc(sizeof(double) * nc * pl), *Q2 = malloc(sizeof(double) * nc * pl);
     double *R2 = malloc(sizeof(double) * nc * pl);
@@ -796,9 +829,9 @@ int orc_ssp2_step(const orc_params *p, double dt, double *cons, double *prims, l
 
     memcpy(w1, prims, sizeof(double) * np * pl);
     orc_implicit(p, g * dt, cons, Q1, w1, st, it);
-    for (int j = jlo(p); j < jhi(p); ++j)
+    for (long r = 0; r < nrows(p); ++r)
         for (int i = 2; i < p->nx + 2; ++i) {
-            const long idx = (long)j * NX + i;
+            const long idx = row_base(p, r) + i;
             nit += it[idx];
             mx = it[idx] > mx ? it[idx] : mx;
             bad += st[idx] != ORC_OK;
@@ -809,9 +842,9 @@ int orc_ssp2_step(const orc_params *p, double dt, double *cons, double *prims, l
 
     memcpy(w2, w1, sizeof(double) * np * pl);
     orc_implicit(p, g * dt, R2, Q2, w2, st, it);
-    for (int j = jlo(p); j < jhi(p); ++j)
+    for (long r = 0; r < nrows(p); ++r)
         for (int i = 2; i < p->nx + 2; ++i) {
-            const long idx = (long)j * NX + i;
+            const long idx = row_base(p, r) + i;
             nit += it[idx];
             mx = it[idx] > mx ? it[idx] : mx;
             bad += st[idx] != ORC_OK;
@@ -819,9 +852,9 @@ int orc_ssp2_step(const orc_params *p, double dt, double *cons, double *prims, l
     orc_rhs(p, Q2, w2, L2);
     source_grid(p, Q2, w2, S2);
     for (int v = 0; v < nc; ++v)
-        for (int j = jlo(p); j < jhi(p); ++j)
+        for (long r = 0; r < nrows(p); ++r)
             for (int i = 2; i < p->nx + 2; ++i) {
-                const long k = v * pl + (long)j * NX + i;
+                const long k = v * pl + row_base(p, r) + i;
                 cons[k] = cons[k] + 0.5 * dt * (L1[k] + L2[k]) + 0.5 * dt * (S1[k] + S2[k]);
             }
     orc_bc_fill(p, cons, nc);
@@ -841,10 +874,9 @@ int orc_ssp2_step(const orc_params *p, double dt, double *cons, double *prims, l
 static void stage_tally(const orc_params *p, const signed char *st, const int *it, long long *nit, int *mx,
                         int *bad)
 {
-    const int NX = NXg(p);
-    for (int j = jlo(p); j < jhi(p); ++j)
+    for (long r = 0; r < nrows(p); ++r)
         for (int i = 2; i < p->nx + 2; ++i) {
-            const long idx = (long)j * NX + i;
+            const long idx = row_base(p, r) + i;
             *nit += it[idx];
             *mx = it[idx] > *mx ? it[idx] : *mx;
             *bad += st[idx] != ORC_OK;
@@ -863,7 +895,7 @@ int orc_ssp3_step(const orc_params *p, double dt, double *cons, double *prims, l
                   int *max_newton, int *nfail)
 {
     const double g = 1.0 - 1.0 / sqrt(2.0);
-    const int NX = NXg(p), nc = orc_ncons(p->model), np = orc_nprim(p->model);
+    const int nc = orc_ncons(p->model), np = orc_nprim(p->model);
     const long pl = plane(p);
     const size_t bc = sizeof(double) * nc * pl, bp = sizeof(double) * np * pl;
     double *Q1 = malloc(bc), *Q2 = malloc(bc), *Q3 = malloc(bc), *R = malloc(bc);
@@ -894,9 +926,9 @@ int orc_ssp3_step(const orc_params *p, double dt, double *cons, double *prims, l
     source_grid(p, Q3, w, S3);
 
     for (int v = 0; v < nc; ++v)
-        for (int j = jlo(p); j < jhi(p); ++j)
+        for (long r = 0; r < nrows(p); ++r)
             for (int i = 2; i < p->nx + 2; ++i) {
-                const long k = v * pl + (long)j * NX + i;
+                const long k = v * pl + row_base(p, r) + i;
                 cons[k] = cons[k] + dt * (L1[k] / 6.0 + L2[k] / 6.0 + 2.0 * L3[k] / 3.0) +
                           dt * (S1[k] / 6.0 + S2[k] / 6.0 + 2.0 * S3[k] / 3.0);
             }
@@ -918,7 +950,8 @@ int orc_ssp3_step(const orc_params *p, double dt, double *cons, double *prims, l
 double orc_dt(const orc_params *p, double cfl)
 {
     if (p->ndim == 1) return cfl * p->dx;
-    return cfl / (1.0 / p->dx + 1.0 / p->dy);
+    if (p->ndim == 2) return cfl / (1.0 / p->dx + 1.0 / p->dy);
+    return cfl / (1.0 / p->dx + 1.0 / p->dy + 1.0 / p->dz);
 }
 
 /* Harness control, no arithmetic of the method: OpenMP threads used by the grid loops

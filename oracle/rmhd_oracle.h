@@ -33,7 +33,7 @@ extern "C" {
 
 typedef struct orc_params {
     int model;              /* 0 = resistive single fluid, 1 = resistive two fluid */
-    int ndim;               /* 1 or 2 */
+    int ndim;               /* 1, 2 or 3 */
     int nx, ny;             /* interior cells (ny = 1 in 1-D) */
     int bc;                 /* 0 = outflow (zero-gradient copy), 1 = periodic */
     int max_c2p_iter;
@@ -46,7 +46,9 @@ typedef struct orc_params {
     double kappa;           /* divergence-cleaning damping rate */
     double c2p_tol;         /* primitive-recovery residual tolerance */
     double newton_tol;      /* implicit-stage residual tolerance */
-    const double *sigma_cell; /* optional per-cell conductivity [NY][NX], or NULL */
+    const double *sigma_cell; /* optional per-cell conductivity [NZ][NY][NX], or NULL */
+    int nz;                 /* interior cells along z in 3-D (unused below 3-D) */
+    double dz;
 } orc_params;
 
 /* Status codes written per cell. */

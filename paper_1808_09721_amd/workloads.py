@@ -7,7 +7,7 @@ by whoever consumes the data.
 
 Every generator returns a :class:`Workload`: grid and physics parameters plus interior
 arrays ``prims[var][ny][nx]`` and ``EB[6][ny][nx]`` (Bx, By, Bz, Ex, Ey, Ez), float64,
-with ``ny = 1`` in 1-D.  Primitive order: single fluid (rho, vx, vy, vz, p); two fluid
+with ``ny = 1`` in 1-D, and ``prims[var][nz][ny][nx]``, ``EB[6][nz][ny][nx]`` in 3-D.  Primitive order: single fluid (rho, vx, vy, vz, p); two fluid
 (rho1, v1x, v1y, v1z, p1, rho2, v2x, v2y, v2z, p2).
 
 Set-ups follow the paper's Sec. 4 (Brio-Wu shock tube, self-similar current sheet,
@@ -45,7 +45,10 @@ class Workload:
     t_end: float | None = None
     prims: np.ndarray = field(default=None, repr=False)
     EB: np.ndarray = field(default=None, repr=False)
-    sigma_cell: np.ndarray | None = field(default=None, repr=False)  # interior [ny][nx] or None
+    sigma_cell: np.ndarray | None = field(default=None, repr=False)  # interior cell shape or None
+    nz: int = 1
+    z0: float = 0.0
+    z1: float = 1.0
 
     @property
     def dx(self) -> float:
@@ -53,7 +56,11 @@ class Workload:
 
     @property
     def dy(self) -> float:
-        return (self.y1 - self.y0) / self.ny if self.ndim == 2 else 1.0
+        return (self.y1 - self.y0) / self.ny if self.ndim >= 2 else 1.0
+
+    @property
+    def dz(self) -> float:
+        return (self.z1 - self.z0) / self.nz if self.ndim == 3 else 1.0
 
     @property
     def ncons(self) -> int:
@@ -65,7 +72,7 @@ class Workload:
 
     @property
     def cells(self) -> int:
-        return self.nx * (self.ny if self.ndim == 2 else 1)
+        return self.nx * (self.ny if self.ndim >= 2 else 1) * (self.nz if self.ndim == 3 else 1)
 
 
 def _centres(n: int, lo: float, hi: float) -> np.ndarray:
@@ -112,6 +119,100 @@ def kelvin_helmholtz_2d(nx: int = 256, ny: int = 512, sigma: float = 1e3, seed: 
     del x
     return Workload("kelvin_helmholtz_2d", SINGLE_FLUID, 2, nx, ny, -0.5, 0.5, -1.0, 1.0, gamma=4.0 / 3.0,
                     sigma=sigma, bc=BC_PERIODIC, steps=steps, prims=prims, EB=EB)
+
+
+def kelvin_helmholtz_3d(nx: int = 128, ny: int = 256, nz: int = 128, sigma: float = 1e3, seed: int = 6,
+                        steps: int = 100) -> Workload:
+    """3-D version of :func:`kelvin_helmholtz_2d` on [-1/2, 1/2] x [-1, 1] x [-1/2, 1/2],
+    periodic: the same shear-layer profile in y, uniform in z, with seeded perturbations
+    v_y = 0.01 xi exp(-(|y| - 1/2)^2/l^2) and v_z = 0.01 zeta exp(-(|y| - 1/2)^2/l^2),
+    xi, zeta ~ U(-1, 1) independently per cell."""
+    rng = np.random.default_rng(seed)
+    y = _centres(ny, -1.0, 1.0)
+    Y = np.broadcast_to(y[None, :, None], (nz, ny, nx))
+    a, l = 0.01, 0.1
+    t = np.tanh((np.abs(Y) - 0.5) / a)
+    env = np.exp(-((np.abs(Y) - 0.5) ** 2) / l ** 2)
+    prims = np.zeros((5, nz, ny, nx))
+    EB = np.zeros((6, nz, ny, nx))
+    prims[0] = 0.55 - 0.45 * t
+    prims[1] = 0.5 * t
+    prims[2] = 0.01 * rng.uniform(-1.0, 1.0, (nz, ny, nx)) * env
+    prims[3] = 0.01 * rng.uniform(-1.0, 1.0, (nz, ny, nx)) * env
+    prims[4] = 1.0
+    EB[2] = 0.1
+    return Workload("kelvin_helmholtz_3d", SINGLE_FLUID, 3, nx, ny, -0.5, 0.5, -1.0, 1.0, gamma=4.0 / 3.0,
+                    sigma=sigma, bc=BC_PERIODIC, steps=steps, prims=prims, EB=EB, nz=nz, z0=-0.5, z1=0.5)
+
+
+def two_fluid_sheet_3d(nx: int = 64, ny: int = 64, nz: int = 64, sigma: float = 1e4, mu: float = 1000.0,
+                       seed: int = 7, noise: float = 1e-3, delta: float = 0.05, steps: int = 100) -> Workload:
+    """3-D version of :func:`two_fluid_sheet_2d` on [-1/2, 1/2)^3, periodic: the same B_y(x)
+    sheets, uniform in y and z, with seeded velocity noise per component, species and cell."""
+    rng = np.random.default_rng(seed)
+    x = _centres(nx, -0.5, 0.5)
+    X = np.broadcast_to(x[None, None, :], (nz, ny, nx))
+    prims = np.zeros((10, nz, ny, nx))
+    EB = np.zeros((6, nz, ny, nx))
+    for s in range(2):
+        prims[5 * s + 0] = 1.0
+        prims[5 * s + 4] = 1.0
+        for c in range(3):
+            prims[5 * s + 1 + c] = noise * rng.uniform(-1.0, 1.0, (nz, ny, nx))
+    EB[1] = np.tanh(X / delta) - np.tanh((X - 0.5) / delta) - np.tanh((X + 0.5) / delta)
+    return Workload("two_fluid_sheet_3d", TWO_FLUID, 3, nx, ny, -0.5, 0.5, -0.5, 0.5, gamma=4.0 / 3.0,
+                    sigma=sigma, bc=BC_PERIODIC, mu1=mu, mu2=-mu, steps=steps, prims=prims, EB=EB,
+                    nz=nz, z0=-0.5, z1=0.5)
+
+
+def _vector_slots(model: int) -> list[tuple[int, int, int]]:
+    """Indices of the (x, y, z) components of each velocity in a primitive array."""
+    return [(1, 2, 3)] if model == SINGLE_FLUID else [(1, 2, 3), (6, 7, 8)]
+
+
+def _rotate_components(arr: np.ndarray, slots) -> np.ndarray:
+    """Cyclic rotation of vector components, (a_x, a_y, a_z) -> (a_z, a_x, a_y)."""
+    out = arr.copy()
+    for (ix, iy, iz) in slots:
+        out[ix], out[iy], out[iz] = arr[iz], arr[ix], arr[iy]
+    return out
+
+
+def extrude_z(wl: Workload, nz: int, z0: float = -0.5, z1: float = 0.5) -> Workload:
+    """A 2-D workload copied onto every plane of a 3-D grid with nz planes (z-independent)."""
+    assert wl.ndim == 2
+    rep = lambda a: np.ascontiguousarray(np.repeat(a[:, None], nz, axis=1))
+    return Workload(wl.name + "_z", wl.model, 3, wl.nx, wl.ny, wl.x0, wl.x1, wl.y0, wl.y1, gamma=wl.gamma,
+                    sigma=wl.sigma, bc=wl.bc, cfl=wl.cfl, mu1=wl.mu1, mu2=wl.mu2, kappa=wl.kappa, steps=wl.steps,
+                    t_end=wl.t_end, prims=rep(wl.prims), EB=rep(wl.EB),
+                    sigma_cell=None if wl.sigma_cell is None else np.repeat(wl.sigma_cell[None], nz, axis=0),
+                    nz=nz, z0=z0, z1=z1)
+
+
+def rotate_axes(wl: Workload) -> Workload:
+    """The same physical set-up turned by the cyclic rotation of the axes that takes x to y,
+    y to z and z to x; vector components turn with the grid, (a_x, a_y, a_z) ->
+    (a_z, a_x, a_y).  A 1-D or 2-D workload is first embedded in 3-D (uniform copies: 4 along
+    each missing axis, spaced as x), so a 1-D set-up along x comes out along y, and rotated
+    twice along z."""
+    if wl.ndim < 3:
+        ny = wl.ny if wl.ndim == 2 else 4
+        pr = wl.prims if wl.ndim == 2 else np.repeat(wl.prims, ny, axis=1)
+        eb = wl.EB if wl.ndim == 2 else np.repeat(wl.EB, ny, axis=1)
+        y0, y1 = (wl.y0, wl.y1) if wl.ndim == 2 else (0.0, ny * wl.dx)
+        wl = Workload(wl.name, wl.model, 3, wl.nx, ny, wl.x0, wl.x1, y0, y1, gamma=wl.gamma, sigma=wl.sigma,
+                      bc=wl.bc, cfl=wl.cfl, mu1=wl.mu1, mu2=wl.mu2, kappa=wl.kappa, steps=wl.steps,
+                      t_end=wl.t_end, prims=np.repeat(pr[:, None], 4, axis=1),
+                      EB=np.repeat(eb[:, None], 4, axis=1), nz=4, z0=0.0, z1=4 * wl.dx)
+    # arrays are [var][z][y][x]; new x = old z, new y = old x, new z = old y
+    move = lambda a: np.ascontiguousarray(np.transpose(a, (0, 2, 3, 1)))
+    prims = _rotate_components(move(wl.prims), _vector_slots(wl.model))
+    EB = _rotate_components(move(wl.EB), [(0, 1, 2), (3, 4, 5)])
+    sc = None if wl.sigma_cell is None else np.ascontiguousarray(np.transpose(wl.sigma_cell, (1, 2, 0)))
+    return Workload(wl.name + "_rot", wl.model, 3, wl.nz, wl.nx, wl.z0, wl.z1, wl.x0, wl.x1, gamma=wl.gamma,
+                    sigma=wl.sigma, bc=wl.bc, cfl=wl.cfl, mu1=wl.mu1, mu2=wl.mu2, kappa=wl.kappa,
+                    steps=wl.steps, t_end=wl.t_end, prims=prims, EB=EB, sigma_cell=sc, nz=wl.ny, z0=wl.y0,
+                    z1=wl.y1)
 
 
 def two_fluid_sheet_2d(nx: int = 512, ny: int = 512, sigma: float = 1e4, mu: float = 1000.0, seed: int = 3,

@@ -9,9 +9,26 @@ import numpy as np
 from oracle import oracle as O
 
 
+# (x, y, z) component triples of the vectors in each array, by model: conserved (S, [Sbar,]
+# B, E), primitive (the velocity of each fluid)
+CONS_VECTORS = {0: [(1, 2, 3), (5, 6, 7), (8, 9, 10)], 1: [(1, 2, 3), (6, 7, 8), (10, 11, 12), (13, 14, 15)]}
+PRIM_VECTORS = {0: [(1, 2, 3)], 1: [(1, 2, 3), (6, 7, 8)]}
+
+
+def rotate_state(arr: np.ndarray, slots) -> np.ndarray:
+    """A [var][NZ][NY][NX] field turned like workloads.rotate_axes: x -> y, y -> z, z -> x,
+    (a_x, a_y, a_z) -> (a_z, a_x, a_y)."""
+    moved = np.ascontiguousarray(np.transpose(arr, (0, 2, 3, 1)))
+    out = moved.copy()
+    for (ix, iy, iz) in slots:
+        out[ix], out[iy], out[iz] = moved[iz], moved[ix], moved[iy]
+    return out
+
+
 def grid_of(wl, **overrides) -> O.Grid:
     g = O.Grid(model=wl.model, ndim=wl.ndim, nx=wl.nx, ny=wl.ny, dx=wl.dx, dy=wl.dy, gamma=wl.gamma,
-               sigma=wl.sigma, bc=wl.bc, mu1=wl.mu1, mu2=wl.mu2, kappa=wl.kappa)
+               sigma=wl.sigma, bc=wl.bc, mu1=wl.mu1, mu2=wl.mu2, kappa=wl.kappa,
+               nz=wl.nz if wl.ndim == 3 else 1, dz=wl.dz)
     if wl.sigma_cell is not None:
         sc = g.embed(wl.sigma_cell[None])[0]
         O.bc_fill(g, sc[None])
