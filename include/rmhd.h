@@ -4,16 +4,17 @@
  * Hawke, "Resistive and multi-fluid RMHD on graphics processing units" (arXiv:1808.09721).
  *
  * The problem is the balance law  d_t q = L(q) + Psi(q)  (Sec. 2.2.1, Eq. 9) with
- * L(q) = -d_k f^k(q) from Lax-Friedrichs flux-vector splitting and WENO3 (Sec. 2.2.2,
- * Eq. 12) and the stiff source Psi (Sec. 2.1.1 Eq. 1; Appendix A Eq. A2), advanced by the
+ * L(q) = -d_k f^k(q) (one flux difference per dimension, in 1-D, 2-D or 3-D) from
+ * Lax-Friedrichs flux-vector splitting and WENO3 (Sec. 2.2.2, Eq. 12) and the stiff source Psi (Sec. 2.1.1 Eq. 1; Appendix A Eq. A2), advanced by the
  * SSP2(222) IMEX Runge-Kutta scheme (Sec. 2.2.1, Eqs. 10-11, Table 2).
  *
  * Memory.  Every array argument is a DEVICE pointer owned by the caller; the library never
- * frees or reallocates it.  Arrays are FP64 structure-of-arrays: variable v of cell (i, j)
- * lives at  base[v * plane + j * pitch + i],  i = 0 .. nx+3 (two ghost cells each side),
- * j = 0 .. ny+3 in 2-D and j = 0 in 1-D; interior cells are i = 2 .. nx+1 (and
- * j = 2 .. ny+1 in 2-D).  pitch and plane come from rmhd_layout_of(); pitch is nx+4 rounded
- * up to a multiple of 8 doubles; columns beyond nx+3 are padding that is never read.
+ * frees or reallocates it.  Arrays are FP64 structure-of-arrays: variable v of cell (i, j, k)
+ * lives at  base[v * plane + k * slab + j * pitch + i],  i = 0 .. nx+3 (two ghost cells each
+ * side), j = 0 .. ny+3 in 2-D and 3-D (j = 0 in 1-D), k = 0 .. nz+3 in 3-D (k = 0 below);
+ * interior cells are i = 2 .. nx+1 (and j = 2 .. ny+1, k = 2 .. nz+1 where present).
+ * pitch, slab and plane come from rmhd_layout_of(); pitch is nx+4 rounded up to a multiple
+ * of 8 doubles (columns beyond nx+3 are padding that is never read); slab = pitch * nyg.
  * Status arrays (int8) and iteration arrays (int32) use one plane of the same indexing.
  *
  * Variable orders:
@@ -66,8 +67,8 @@ extern "C" {
 
 typedef struct rmhd_params {
     int32_t model;            /* RMHD_SINGLE_FLUID or RMHD_TWO_FLUID */
-    int32_t ndim;             /* 1 or 2 */
-    int32_t nx, ny;           /* interior cells (ny = 1 in 1-D) */
+    int32_t ndim;             /* 1, 2 or 3 */
+    int32_t nx, ny;           /* interior cells (ny = 1 in 1-D); nz below */
     int32_t bc;               /* RMHD_BC_OUTFLOW or RMHD_BC_PERIODIC, all sides */
     int32_t max_c2p_iter;     /* primitive-recovery iteration cap (e.g. 100) */
     int32_t max_newton_iter;  /* implicit-stage iteration cap (e.g. 50) */
@@ -87,13 +88,18 @@ typedef struct rmhd_params {
     int32_t c2p_primary_only; /* 0: where the recovery's z = rho h W^2 iteration does not
                                  converge, a Newton iteration on the pressure takes over (the
                                  paper keeps two residuals, Sec. 2.1.3); 1: z iteration only */
+    int32_t nz;               /* 3-D: interior cells along z (>= 4); 0 or 1 below 3-D */
+    int32_t reserved_;        /* must be 0 */
+    double z0, z1;            /* 3-D: domain along z; dz = (z1-z0)/nz */
 } rmhd_params;
 
 typedef struct rmhd_layout {
-    int64_t nxg, nyg;         /* cells per row / rows, ghosts included */
+    int64_t nxg, nyg;         /* cells per row / rows per z plane, ghosts included */
     int64_t pitch;            /* doubles between rows */
     int64_t plane;            /* doubles between variables */
     int32_t ncons, nprim;
+    int64_t nzg;              /* z planes, ghosts included (1 below 3-D) */
+    int64_t slab;             /* doubles between z planes (pitch * nyg) */
 } rmhd_layout;
 
 typedef struct rmhd_stats {
@@ -169,7 +175,7 @@ int rmhd_imex_step(rmhd_ctx *ctx, double dt, double *cons, double *prims);
  * are launched directly.  Results are identical either way.  Default 0. */
 int rmhd_set_graph(rmhd_ctx *ctx, int enable);
 
-/* Time step CFL / sum_d (1/dx_d) (maximum signal speed c = 1). */
+/* Time step CFL / sum_d (1/dx_d) over the grid's dimensions (maximum signal speed c = 1). */
 double rmhd_dt(const rmhd_ctx *ctx);
 
 /* Copy the accumulated statistics (synchronises the stream); reset != 0 zeroes them. */
@@ -191,7 +197,7 @@ int rmhd_set_newton_cap(rmhd_ctx *ctx, int cap);
 
 /* Rows of the 2-D flux-pass thread block: 16 (12 interior rows per 64 x 16 block) or 8
  * (4 interior rows, more blocks and more halo work); 0 (default) = 16.  Results do not
- * depend on it. */
+ * depend on it.  (3-D grids always use 16.) */
 int rmhd_set_flux_rows(rmhd_ctx *ctx, int rows);
 
 /* Enable (1) or disable (0) per-kernel event timing of rmhd_imex_step.  While enabled each
@@ -233,8 +239,8 @@ typedef struct rmhd_batch_tuning {
     double step_ms;             /* set by rmhd_batch_autotune: time of the chosen shape */
 } rmhd_batch_tuning;
 
-/* Create a batch of n domains (each validated as for rmhd_create; single fluid, scalar
- * sigma).  Allocates pooled stage scratch for all domains.  *out is set even on failure so
+/* Create a batch of n domains (each validated as for rmhd_create; single fluid, 1-D or 2-D,
+ * scalar sigma).  Allocates pooled stage scratch for all domains.  *out is set even on failure so
  * that rmhd_batch_last_error() can explain it; always release with rmhd_batch_destroy(). */
 int rmhd_batch_create(const rmhd_params *domains, int n, void *hip_stream, rmhd_batch **out);
 void rmhd_batch_destroy(rmhd_batch *batch);

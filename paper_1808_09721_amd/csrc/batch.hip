@@ -397,6 +397,8 @@ extern "C" int rmhd_batch_create(const rmhd_params *domains, int n, void *stream
             return bfail(b, RMHD_EINVAL, "rmhd_batch_create: batched domains must be single-fluid");
         if (domains[d].integrator != RMHD_SSP2_222)
             return bfail(b, RMHD_EINVAL, "rmhd_batch_create: batched domains use the SSP2(222) integrator");
+        if (domains[d].ndim == 3)
+            return bfail(b, RMHD_EINVAL, "rmhd_batch_create: batched domains are 1-D or 2-D");
         if (domains[d].sigma_cell)
             return bfail(b, RMHD_EINVAL, "rmhd_batch_create: per-cell conductivity is not batched");
         rmhd_layout L;

@@ -31,11 +31,16 @@ struct CPlanes {
     const double *p[18];
 };
 
+// Cell (i, j, k) of a variable lives at k * slab + j * pitch + i; r = k * nyg + j numbers the
+// rows of all z planes together (rows = nyg * nzg), so pointwise kernels see one 2-D array.
 struct Geo {
     int nx, ny, nxg, nyg;
-    int pitch, ndim, bc, pad_;
+    int pitch, ndim, bc, nz;
     long plane;
     double idx, idy;  // 1/dx, 1/dy
+    int nzg, rows;
+    long slab;
+    double idz;       // 1/dz
 };
 
 template <int M>
@@ -57,9 +62,23 @@ __host__ __device__ constexpr bool has_source(int M, int v)
                      v == tf::EY || v == tf::EZ || v == tf::PSI || v == tf::PHI);
 }
 
-__device__ __forceinline__ bool is_interior(const Geo &g, int i, int j)
+// Whether cell i of row r (= k * nyg + j) is an interior cell.
+__device__ __forceinline__ bool is_interior(const Geo &g, int i, int r)
 {
-    return i >= 2 && i < g.nx + 2 && (g.ndim == 1 || (j >= 2 && j < g.ny + 2));
+    if (!(i >= 2 && i < g.nx + 2)) return false;
+    if (g.ndim == 1) return true;
+    if (g.ndim == 2) return r >= 2 && r < g.ny + 2;
+    const int j = r % g.nyg, k = r / g.nyg;
+    return j >= 2 && j < g.ny + 2 && k >= 2 && k < g.nz + 2;
+}
+
+// Row-major rank of an interior cell among the interior cells (x fastest, then y, then z).
+__device__ __forceinline__ long interior_rank(const Geo &g, int i, int r)
+{
+    if (g.ndim == 1) return i - 2;
+    if (g.ndim == 2) return (long)(r - 2) * g.nx + (i - 2);
+    const int j = r % g.nyg, k = r / g.nyg;
+    return ((long)(k - 2) * g.ny + (j - 2)) * g.nx + (i - 2);
 }
 
 // padded index of the interior cell that a ghost (or interior) index copies
@@ -76,11 +95,13 @@ __device__ __forceinline__ int bc_src(int i, int n, int bc)
 static __global__ __launch_bounds__(256) void k_bc(Planes a, int nvar, Geo g)
 {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = (int)(t % g.pitch), j = (int)(t / g.pitch);
-    if (i >= g.nxg || j >= g.nyg || is_interior(g, i, j)) return;
+    const int i = (int)(t % g.pitch), r = (int)(t / g.pitch);
+    if (i >= g.nxg || r >= g.rows || is_interior(g, i, r)) return;
+    const int j = r % g.nyg, k = r / g.nyg;
     const int si = bc_src(i, g.nx, g.bc);
-    const int sj = g.ndim == 2 ? bc_src(j, g.ny, g.bc) : 0;
-    const long d = (long)j * g.pitch + i, s = (long)sj * g.pitch + si;
+    const int sj = g.ndim >= 2 ? bc_src(j, g.ny, g.bc) : 0;
+    const int sk = g.ndim == 3 ? bc_src(k, g.nz, g.bc) : 0;
+    const long d = (long)r * g.pitch + i, s = (long)sk * g.slab + (long)sj * g.pitch + si;
     for (int v = 0; v < nvar; ++v) a.p[v][d] = a.p[v][s];
 }
 
@@ -92,9 +113,11 @@ __global__ __launch_bounds__(256) void k_init(CPlanes prims, CPlanes EB, Planes 
 {
     constexpr int NC = Model<M>::NC, NP = Model<M>::NP;
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = (int)(t % g.pitch), j = (int)(t / g.pitch);
-    if (i >= g.nxg || j >= g.nyg || !is_interior(g, i, j)) return;
-    const long idx = (long)j * g.pitch + i;
+    const int i = (int)(t % g.pitch), r = (int)(t / g.pitch);
+    if (i >= g.nxg || r >= g.rows || !is_interior(g, i, r)) return;
+    const long idx = (long)r * g.pitch + i;
+    const int j = r % g.nyg, k = r / g.nyg;
+    const long zo = (long)k * g.slab;
     double w[NP], eb[6], q[NC];
 #pragma unroll
     for (int v = 0; v < NP; ++v) w[v] = prims.p[v][idx];
@@ -102,13 +125,18 @@ __global__ __launch_bounds__(256) void k_init(CPlanes prims, CPlanes EB, Planes 
     for (int v = 0; v < 6; ++v) eb[v] = EB.p[v][idx];
     if constexpr (M == 0) {
         // Gauss's law rho_e = div E, central differences; neighbours through the boundary map
-        const long xm = (long)j * g.pitch + bc_src(i - 1, g.nx, g.bc);
-        const long xp = (long)j * g.pitch + bc_src(i + 1, g.nx, g.bc);
+        const long xm = zo + (long)j * g.pitch + bc_src(i - 1, g.nx, g.bc);
+        const long xp = zo + (long)j * g.pitch + bc_src(i + 1, g.nx, g.bc);
         double div = (EB.p[3][xp] - EB.p[3][xm]) * (0.5 * g.idx);
-        if (g.ndim == 2) {
-            const long ym = (long)bc_src(j - 1, g.ny, g.bc) * g.pitch + i;
-            const long yp = (long)bc_src(j + 1, g.ny, g.bc) * g.pitch + i;
+        if (g.ndim >= 2) {
+            const long ym = zo + (long)bc_src(j - 1, g.ny, g.bc) * g.pitch + i;
+            const long yp = zo + (long)bc_src(j + 1, g.ny, g.bc) * g.pitch + i;
             div += (EB.p[4][yp] - EB.p[4][ym]) * (0.5 * g.idy);
+        }
+        if (g.ndim == 3) {
+            const long zm = (long)bc_src(k - 1, g.nz, g.bc) * g.slab + (long)j * g.pitch + i;
+            const long zp = (long)bc_src(k + 1, g.nz, g.bc) * g.slab + (long)j * g.pitch + i;
+            div += (EB.p[5][zp] - EB.p[5][zm]) * (0.5 * g.idz);
         }
         sf_prim2cons(w, eb, div, P, q);
     } else {
@@ -127,9 +155,9 @@ __global__ __launch_bounds__(256) void k_c2p(CPlanes cons, Planes prims, int8_t 
 {
     constexpr int NC = Model<M>::NC, NP = Model<M>::NP;
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = (int)(t % g.pitch), j = (int)(t / g.pitch);
-    if (i >= g.nxg || j >= g.nyg) return;
-    const long idx = (long)j * g.pitch + i;
+    const int i = (int)(t % g.pitch), r = (int)(t / g.pitch);
+    if (i >= g.nxg || r >= g.rows) return;
+    const long idx = (long)r * g.pitch + i;
     double q[NC], w[NP];
 #pragma unroll
     for (int v = 0; v < NC; ++v) q[v] = cons.p[v][idx];
@@ -330,7 +358,7 @@ __device__ __forceinline__ void stage_write(const StageArgs &A, long idx, int i,
         A.Q.p[tf::PSI][idx] = (R[tf::PSI] + A.a * R[tf::DB]) * aK;
         if (A.hx && is_interior(g, i, j)) {
             // features of R and target (x* - R_x) / D of the learned guess
-            const long row = A.hbase + (g.ndim == 2 ? (long)(j - 2) * g.nx : 0) + (i - 2);
+            const long row = A.hbase + interior_rank(g, i, j);
             const double iD = 1.0 / R[tf::D];
             float *f = A.hx + row * 19;
             f[0] = (float)log10(A.a * A.P.mu1 * A.P.mu1 * R[tf::D]);
@@ -365,7 +393,7 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs A)
     const Geo &g = A.g;
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const int i = (int)(t % g.pitch), j = (int)(t / g.pitch);
-    const bool live = i < g.nxg && j < g.nyg;
+    const bool live = i < g.nxg && j < g.rows;   // j: row of all z planes
     const long idx = (long)j * g.pitch + i;
     int nit = 0, cit = 0, rit = 0, st = CELL_OK;
     bool push = false;
@@ -505,7 +533,7 @@ struct FluxArgs {
 // Primitives of a cell's new state q (guess w), written with the ghost images of the cell.
 template <int M>
 __device__ __forceinline__ void flux_recover(const FluxArgs &A, const double *q, const double *w,
-                                            const int (&xi)[3], const int (&yj)[3], int ny_img)
+                                            const int (&xi)[3], const int (&yj)[3], int ny_img, long zoff)
 {
     constexpr int NP = Model<M>::NP;
     double wn[NP];
@@ -520,7 +548,8 @@ __device__ __forceinline__ void flux_recover(const FluxArgs &A, const double *q,
         for (int aa = 0; aa < 3; ++aa)
 #pragma unroll
             for (int bb = 0; bb < 3; ++bb)
-                if (bb < ny_img && xi[aa] >= 0 && yj[bb] >= 0) A.wnew.p[v][(long)yj[bb] * A.g.pitch + xi[aa]] = wn[v];
+                if (bb < ny_img && xi[aa] >= 0 && yj[bb] >= 0)
+                    A.wnew.p[v][zoff + (long)yj[bb] * A.g.pitch + xi[aa]] = wn[v];
 }
 
 // WENO3 value at the downwind face of b from the upwind-ordered stencil (a, b, c):
@@ -546,9 +575,10 @@ __device__ __forceinline__ void weno3_pair(double ap, double bp, double cp, doub
 
 // One tile of the flux pass, both directions staged through LDS (used for 1-D blocks, whose
 // rows span several wavefronts); every thread of the block must call it (it holds
-// barriers).  (bx, by) is the tile position in units of interior tiles.
+// barriers).  (bx, by) is the tile position in units of interior tiles; zoff is the offset of
+// the z plane (0 below 3-D, where a 2-D tile forms the x and y terms of one plane).
 template <int M, int NDIM, int BX, int BY, int NO>
-__device__ __forceinline__ void flux_tile_lds(const FluxArgs &A, int bx, int by)
+__device__ __forceinline__ void flux_tile_lds(const FluxArgs &A, int bx, int by, long zoff)
 {
     constexpr int NC = Model<M>::NC, NP = Model<M>::NP;
     constexpr int TX = BX - 4, TY = NDIM == 2 ? BY - 4 : 1;
@@ -562,7 +592,7 @@ __device__ __forceinline__ void flux_tile_lds(const FluxArgs &A, int bx, int by)
     const int jj = NDIM == 2 ? by * TY + ty - 2 : 0;
     const int i = min(max(ii + 2, 0), g.nxg - 1);
     const int j = NDIM == 2 ? min(max(jj + 2, 0), g.nyg - 1) : 0;
-    const long idx = (long)j * g.pitch + i;
+    const long idx = zoff + (long)j * g.pitch + i;
 
     double q[NC], w[NP], fx[NC], fy[NC], src[NC];
 #pragma unroll
@@ -642,7 +672,7 @@ __device__ __forceinline__ void flux_tile_lds(const FluxArgs &A, int bx, int by)
                     for (int aa = 0; aa < 3; ++aa)
 #pragma unroll
                         for (int bb = 0; bb < (NDIM == 2 ? 3 : 1); ++bb)
-                            if (xi[aa] >= 0 && yj[bb] >= 0) F.out.p[v][(long)yj[bb] * g.pitch + xi[aa]] = o;
+                            if (xi[aa] >= 0 && yj[bb] >= 0) F.out.p[v][zoff + (long)yj[bb] * g.pitch + xi[aa]] = o;
                 } else {
                     F.out.p[v][idx] = o;
                 }
@@ -652,7 +682,7 @@ __device__ __forceinline__ void flux_tile_lds(const FluxArgs &A, int bx, int by)
     }
     // the two-fluid step recovers in a separate kernel, so its flux pass does not carry the code
     if constexpr (M == 0)
-        if (A.wnew.p[0] && interior) flux_recover<M>(A, q, w, xi, yj, NDIM == 2 ? 3 : 1);
+        if (A.wnew.p[0] && interior) flux_recover<M>(A, q, w, xi, yj, NDIM == 2 ? 3 : 1, zoff);
 }
 
 // Values of the lanes to the left and right in the same wavefront (a lane at the edge gets
@@ -665,7 +695,7 @@ __device__ __forceinline__ double from_right(double v) { return __shfl_down(v, 1
 // goes through LDS, G variables per pair of barriers.  The arithmetic per face and cell is
 // that of flux_tile_lds.  Every thread of the block must call it.
 template <int M, int BY, int NO>
-__device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by)
+__device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by, long zoff)
 {
     constexpr int NC = Model<M>::NC, NP = Model<M>::NP;
     constexpr int BX = 64, TX = BX - 4, TY = BY - 4;
@@ -677,7 +707,7 @@ __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by
     const int jj = by * TY + ty - 2;
     const int i = min(max(ii + 2, 0), g.nxg - 1);
     const int j = min(max(jj + 2, 0), g.nyg - 1);
-    const long idx = (long)j * g.pitch + i;
+    const long idx = zoff + (long)j * g.pitch + i;
 
     double q[NC], w[NP], fx[NC], fy[NC], src[NC];
 #pragma unroll
@@ -756,7 +786,8 @@ __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by
                         for (int aa = 0; aa < 3; ++aa)
 #pragma unroll
                             for (int bb = 0; bb < 3; ++bb)
-                                if (xi[aa] >= 0 && yj[bb] >= 0) F.out.p[v][(long)yj[bb] * g.pitch + xi[aa]] = o;
+                                if (xi[aa] >= 0 && yj[bb] >= 0)
+                                    F.out.p[v][zoff + (long)yj[bb] * g.pitch + xi[aa]] = o;
                     } else {
                         F.out.p[v][idx] = o;
                     }
@@ -768,7 +799,7 @@ __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by
         // above, and shp/shm only after the next round's first barrier
     }
     if constexpr (M == 0)
-        if (A.wnew.p[0] && interior) flux_recover<M>(A, q, w, xi, yj, 3);
+        if (A.wnew.p[0] && interior) flux_recover<M>(A, q, w, xi, yj, 3, zoff);
 }
 
 // One tile of the flux pass: single-fluid 2-D tiles with 64-wide rows use the wavefront-row
@@ -776,11 +807,11 @@ __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by
 // extra live registers cost more than its saved LDS traffic).
 // NO: outputs used (o[0..NO-1]), fixed at compile time so unused ones cost no registers.
 template <int M, int NDIM, int BX, int BY, int NO>
-__device__ __forceinline__ void flux_tile(const FluxArgs &A, int bx, int by)
+__device__ __forceinline__ void flux_tile(const FluxArgs &A, int bx, int by, long zoff = 0)
 {
     static_assert(NO >= 1 && NO <= FLUX_MAXOUT, "outputs");
-    if constexpr (M == 0 && NDIM == 2 && BX == 64) flux_tile_rows<M, BY, NO>(A, bx, by);
-    else flux_tile_lds<M, NDIM, BX, BY, NO>(A, bx, by);
+    if constexpr (M == 0 && NDIM == 2 && BX == 64) flux_tile_rows<M, BY, NO>(A, bx, by, zoff);
+    else flux_tile_lds<M, NDIM, BX, BY, NO>(A, bx, by, zoff);
 }
 
 // Workgroups are dealt to the 8 XCDs in turn (linear id mod 8), each XCD with its own L2.
@@ -798,12 +829,102 @@ __device__ __forceinline__ void xcd_tile(int &bx, int &by)
     by = t / gridDim.x;
 }
 
+// The same over a 3-D grid of blocks (x fastest, then y, then z).
+__device__ __forceinline__ void xcd_tile3(int &bx, int &by, int &bz)
+{
+    const int gxy = gridDim.x * gridDim.y;
+    const int t = xcd_order((blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x, gxy * gridDim.z);
+    bx = t % gridDim.x;
+    by = (t % gxy) / gridDim.x;
+    bz = t / gxy;
+}
+
+// Flux pass.  NDIM = 3: one 2-D tile of an interior z plane (blockIdx.z), forming
+// out_k = base_k + c_kL (Lx + Ly) + c_kS Psi; k_flux_z then adds c_kL Lz.
 template <int M, int NDIM, int BX, int BY, int NO>
 __global__ __launch_bounds__(BX *BY) void k_flux(FluxArgs A)
 {
     int bx = blockIdx.x, by = blockIdx.y;
-    if constexpr (NDIM == 2) xcd_tile(bx, by);
-    flux_tile<M, NDIM, BX, BY, NO>(A, bx, by);
+    if constexpr (NDIM == 3) {
+        int bz;
+        xcd_tile3(bx, by, bz);
+        flux_tile<M, 2, BX, BY, NO>(A, bx, by, (long)(bz + 2) * A.g.slab);
+    } else {
+        if constexpr (NDIM == 2) xcd_tile(bx, by);
+        flux_tile<M, NDIM, BX, BY, NO>(A, bx, by);
+    }
+}
+
+// z term of a 3-D flux pass, after k_flux: out_k += c_kL Lz on every interior cell, with
+// Lz = -(H_{k+1/2} - H_{k-1/2}) / dz from the split z fluxes reconstructed as in x and y.
+// Blocks of 64 (x) x 16 (z) threads: one x row of one y row per wavefront, the z stencil
+// through LDS with two halo planes on each side (12 interior planes per block, no x halo).
+// Every thread of the block reaches every barrier.
+template <int M, int NO>
+__global__ __launch_bounds__(1024) void k_flux_z(FluxArgs A)
+{
+    constexpr int NC = Model<M>::NC, NP = Model<M>::NP;
+    constexpr int BX = 64, BZ = 16, TZ = BZ - 4, G = 2;
+    __shared__ double sfp[G][BZ][BX], sfm[G][BZ][BX], shp[G][BZ][BX], shm[G][BZ][BX];
+    const Geo &g = A.g;
+    int bx, by, bz;
+    xcd_tile3(bx, by, bz);
+    const int tx = threadIdx.x, tz = threadIdx.y;
+    const int ii = bx * BX + tx;        // interior column
+    const int kk = bz * TZ + tz - 2;    // interior plane (two halo planes each side)
+    const int i = min(ii + 2, g.nxg - 1);
+    const int k = min(max(kk + 2, 0), g.nzg - 1);
+    const long idx = (long)k * g.slab + (long)(by + 2) * g.pitch + i;
+
+    double q[NC], w[NP], fz[NC];
+#pragma unroll
+    for (int v = 0; v < NC; ++v) q[v] = A.q.p[v][idx];
+#pragma unroll
+    for (int v = 0; v < NP; ++v) w[v] = A.w.p[v][idx];
+    if constexpr (M == 0) sf_flux_z(q, w, cell_sigma(A.P, idx), A.P, fz);
+    else tf_flux_z(q, w, A.P, fz);
+
+    const bool interior = ii < g.nx && tz >= 2 && tz < BZ - 2 && kk < g.nz;
+    const bool do_z = tz >= 1 && tz <= BZ - 2;
+#pragma unroll
+    for (int v0 = 0; v0 < NC; v0 += G) {
+#pragma unroll
+        for (int c = 0; c < G; ++c) {
+            const int v = v0 + c;
+            if (v >= NC) break;
+            sfp[c][tz][tx] = 0.5 * (fz[v] + q[v]);
+            sfm[c][tz][tx] = 0.5 * (fz[v] - q[v]);
+        }
+        __syncthreads();
+        if (do_z) {
+#pragma unroll
+            for (int c = 0; c < G; ++c) {
+                if (v0 + c >= NC) break;
+                double vp, vm;
+                weno3_pair(sfp[c][tz - 1][tx], sfp[c][tz][tx], sfp[c][tz + 1][tx], sfm[c][tz + 1][tx], sfm[c][tz][tx],
+                           sfm[c][tz - 1][tx], vp, vm);
+                shp[c][tz][tx] = vp;
+                shm[c][tz][tx] = vm;
+            }
+        }
+        __syncthreads();
+        if (interior) {
+#pragma unroll
+            for (int c = 0; c < G; ++c) {
+                const int v = v0 + c;
+                if (v >= NC) break;
+                const double Lz =
+                    -((shp[c][tz][tx] + shm[c][tz + 1][tx]) - (shp[c][tz - 1][tx] + shm[c][tz][tx])) * g.idz;
+#pragma unroll
+                for (int o = 0; o < NO; ++o) {
+                    const FluxOut &F = A.o[o];
+                    F.out.p[v][idx] += F.cL * Lz;
+                }
+            }
+        }
+        // sfp/sfm are rewritten only after every thread has passed the second barrier above,
+        // shp/shm only after the next round's first barrier
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -832,9 +953,11 @@ static inline void stats_fold(const unsigned long long *raw, rmhd_stats *out)
 static inline void layout_from(const rmhd_params *p, rmhd_layout *out)
 {
     out->nxg = p->nx + 4;
-    out->nyg = p->ndim == 2 ? p->ny + 4 : 1;
+    out->nyg = p->ndim >= 2 ? p->ny + 4 : 1;
+    out->nzg = p->ndim == 3 ? p->nz + 4 : 1;
     out->pitch = (out->nxg + 7) / 8 * 8;
-    out->plane = out->pitch * out->nyg;
+    out->slab = out->pitch * out->nyg;
+    out->plane = out->slab * out->nzg;
     out->ncons = p->model == RMHD_SINGLE_FLUID ? 14 : 18;
     out->nprim = p->model == RMHD_SINGLE_FLUID ? 5 : 10;
 }
@@ -843,15 +966,20 @@ static inline Geo geo_from(const rmhd_params *p, const rmhd_layout &L)
 {
     Geo g{};
     g.nx = p->nx;
-    g.ny = p->ndim == 2 ? p->ny : 1;
+    g.ny = p->ndim >= 2 ? p->ny : 1;
+    g.nz = p->ndim == 3 ? p->nz : 1;
     g.nxg = (int)L.nxg;
     g.nyg = (int)L.nyg;
+    g.nzg = (int)L.nzg;
+    g.rows = (int)(L.nyg * L.nzg);
     g.pitch = (int)L.pitch;
+    g.slab = L.slab;
     g.ndim = p->ndim;
     g.bc = p->bc;
     g.plane = L.plane;
     g.idx = p->nx / (p->x1 - p->x0);
-    g.idy = p->ndim == 2 ? p->ny / (p->y1 - p->y0) : 0.0;
+    g.idy = p->ndim >= 2 ? p->ny / (p->y1 - p->y0) : 0.0;
+    g.idz = p->ndim == 3 ? p->nz / (p->z1 - p->z0) : 0.0;
     return g;
 }
 
@@ -880,7 +1008,9 @@ static inline double cfl_dt(const rmhd_params *p)
     const double dx = (p->x1 - p->x0) / p->nx;
     if (p->ndim == 1) return p->cfl * dx;
     const double dy = (p->y1 - p->y0) / p->ny;
-    return p->cfl / (1.0 / dx + 1.0 / dy);
+    if (p->ndim == 2) return p->cfl / (1.0 / dx + 1.0 / dy);
+    const double dz = (p->z1 - p->z0) / p->nz;
+    return p->cfl / (1.0 / dx + 1.0 / dy + 1.0 / dz);
 }
 
 }  // namespace rmhd

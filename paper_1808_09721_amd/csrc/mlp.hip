@@ -173,7 +173,7 @@ __global__ __launch_bounds__(256) void k_infer(InferArgs A)
         r.live = tile < ntiles && s < nsamp;
         if constexpr (S == 1) {
             const int i = (int)(s % A.g.pitch), j = (int)(s / A.g.pitch);
-            r.live = r.live && i < A.g.nxg && j < A.g.nyg;
+            r.live = r.live && i < A.g.nxg && j < A.g.rows;
         }
 #pragma unroll
         for (int e = 0; e < 8; ++e) r.v[e] = 0.0;

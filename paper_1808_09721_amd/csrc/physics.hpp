@@ -398,6 +398,28 @@ __device__ inline void sf_flux_source(const double *q, const double *w, double s
     src[sf::PHI] = -P.kappa * q[sf::PHI];
 }
 
+// Flux vector f^z of one cell from (q, w), for 3-D grids: the z column of the fluxes of
+// Eq. 1 (induction -E x, Ampere +B x, cleaning psi, phi along z).
+__device__ inline void sf_flux_z(const double *q, const double *w, double sig, const Phys &P, double *fz)
+{
+    const vec3<double> v = v3(w[1], w[2], w[3]);
+    const vec3<double> B = v3(q[sf::BX], q[sf::BY], q[sf::BZ]), E = v3(q[sf::EX], q[sf::EY], q[sf::EZ]);
+    const double W = frsqrt(1.0 - dot(v, v));
+    const double A = (w[0] + P.hk * w[4]) * (W * W);
+    const double pt = w[4] + 0.5 * (dot(E, E) + dot(B, B));
+    const vec3<double> J = sf_current(v, W, E, B, q[sf::RHOE], sig);
+    fz[sf::D] = q[sf::D] * v.z;
+    fz[sf::SX] = A * v.x * v.z - E.x * E.z - B.x * B.z;
+    fz[sf::SY] = A * v.y * v.z - E.y * E.z - B.y * B.z;
+    fz[sf::SZ] = A * v.z * v.z + pt - E.z * E.z - B.z * B.z;
+    fz[sf::TAU] = q[sf::SZ] - q[sf::D] * v.z;
+    fz[sf::BX] = -E.y; fz[sf::BY] = E.x; fz[sf::BZ] = q[sf::PHI];
+    fz[sf::EX] = B.y; fz[sf::EY] = -B.x; fz[sf::EZ] = q[sf::PSI];
+    fz[sf::RHOE] = J.z;
+    fz[sf::PSI] = E.z;
+    fz[sf::PHI] = B.z;
+}
+
 // ---------------------------------------------------------------------------------------
 // Two fluid (Sec. 2.1.2 Eq. 6; Appendix A Eqs. A1-A3)
 // ---------------------------------------------------------------------------------------
@@ -547,6 +569,32 @@ __device__ inline void tf_flux_source(const double *q, const double *w, double s
     src[tf::EX] = -S.J.x; src[tf::EY] = -S.J.y; src[tf::EZ] = -S.J.z;
     src[tf::PSI] = q[tf::DB] - P.kappa * q[tf::PSI];
     src[tf::PHI] = -P.kappa * q[tf::PHI];
+}
+
+// Flux vector f^z of one cell from (q, w), for 3-D grids (Appendix A Eq. A3, z column).
+__device__ inline void tf_flux_z(const double *q, const double *w, const Phys &P, double *fz)
+{
+    const vec3<double> B = v3(q[tf::BX], q[tf::BY], q[tf::BZ]), E = v3(q[tf::EX], q[tf::EY], q[tf::EZ]);
+    const double mu[2] = {P.mu1, P.mu2};
+    const double em = 0.5 * (dot(E, E) + dot(B, B));
+    for (int k = 0; k < tf::NC; ++k) fz[k] = 0.0;
+    for (int s = 0; s < 2; ++s) {
+        const double *ws = w + 5 * s;
+        const vec3<double> vs = v3(ws[1], ws[2], ws[3]);
+        const double Wl = frsqrt(1.0 - dot(vs, vs));
+        const double Dw = ws[0] * Wl, A = (ws[0] + P.hk * ws[4]) * (Wl * Wl);
+        const double Sxz = A * vs.x * vs.z, Syz = A * vs.y * vs.z, Szz = A * vs.z * vs.z + ws[4];
+        fz[tf::D] += Dw * vs.z;
+        fz[tf::SX] += Sxz; fz[tf::SY] += Syz; fz[tf::SZ] += Szz;
+        fz[tf::DB] += mu[s] * Dw * vs.z;
+        fz[tf::SBX] += mu[s] * Sxz; fz[tf::SBY] += mu[s] * Syz; fz[tf::SBZ] += mu[s] * Szz;
+        fz[tf::TAUB] += mu[s] * (A - Dw) * vs.z;
+    }
+    fz[tf::SX] += -E.x * E.z - B.x * B.z; fz[tf::SY] += -E.y * E.z - B.y * B.z; fz[tf::SZ] += em - E.z * E.z - B.z * B.z;
+    fz[tf::TAU] = q[tf::SZ] - fz[tf::D];
+    fz[tf::BX] = -E.y; fz[tf::BY] = E.x; fz[tf::BZ] = q[tf::PHI];
+    fz[tf::EX] = B.y; fz[tf::EY] = -B.x; fz[tf::EZ] = q[tf::PSI];
+    fz[tf::PSI] = E.z; fz[tf::PHI] = B.z;
 }
 
 }  // namespace rmhd

@@ -78,12 +78,19 @@ static int check_params_impl(const rmhd_params *p, rmhd_ctx *c)
 {
     if (!p) return fail(c, RMHD_EINVAL, "params is NULL");
     if (p->model != RMHD_SINGLE_FLUID && p->model != RMHD_TWO_FLUID) return fail(c, RMHD_EINVAL, "model must be 0 or 1");
-    if (p->ndim != 1 && p->ndim != 2) return fail(c, RMHD_EINVAL, "ndim must be 1 or 2");
-    if (p->nx < 4 || (p->ndim == 2 && p->ny < 4) || (p->ndim == 1 && p->ny != 1))
-        return fail(c, RMHD_EINVAL, "need nx >= 4 (and ny >= 4 in 2-D, ny == 1 in 1-D)");
-    if ((long)p->nx * (p->ndim == 2 ? p->ny : 1) > (1l << 30)) return fail(c, RMHD_EINVAL, "grid too large");
+    if (p->ndim < 1 || p->ndim > 3) return fail(c, RMHD_EINVAL, "ndim must be 1, 2 or 3");
+    if (p->nx < 4 || (p->ndim >= 2 && p->ny < 4) || (p->ndim == 1 && p->ny != 1))
+        return fail(c, RMHD_EINVAL, "need nx >= 4 (and ny >= 4 in 2-D and 3-D, ny == 1 in 1-D)");
+    if ((p->ndim == 3 && p->nz < 4) || (p->ndim < 3 && p->nz != 0 && p->nz != 1))
+        return fail(c, RMHD_EINVAL, "need nz >= 4 in 3-D (nz 0 or 1 below 3-D)");
+    if (p->ndim == 3 && (p->ny > 65535 || p->nz > 65535)) return fail(c, RMHD_EINVAL, "3-D: ny, nz <= 65535");
+    if (p->reserved_ != 0) return fail(c, RMHD_EINVAL, "reserved_ must be 0");
+    if ((long)p->nx * (p->ndim >= 2 ? p->ny : 1) * (p->ndim == 3 ? p->nz : 1) > (1l << 30) ||
+        (long)(p->nx + 4) * (p->ndim >= 2 ? p->ny + 4 : 1) * (p->ndim == 3 ? p->nz + 4 : 1) >= (1l << 31))
+        return fail(c, RMHD_EINVAL, "grid too large");
     if (p->bc != RMHD_BC_OUTFLOW && p->bc != RMHD_BC_PERIODIC) return fail(c, RMHD_EINVAL, "bc must be 0 or 1");
-    if (!(p->x1 > p->x0) || (p->ndim == 2 && !(p->y1 > p->y0))) return fail(c, RMHD_EINVAL, "empty domain");
+    if (!(p->x1 > p->x0) || (p->ndim >= 2 && !(p->y1 > p->y0)) || (p->ndim == 3 && !(p->z1 > p->z0)))
+        return fail(c, RMHD_EINVAL, "empty domain");
     if (!(p->gamma_eos > 1.0 && p->gamma_eos <= 2.0)) return fail(c, RMHD_EINVAL, "gamma_eos must lie in (1, 2]");
     if (p->model == RMHD_TWO_FLUID && !(p->mu1 != p->mu2 && p->mu1 != 0.0))
         return fail(c, RMHD_EINVAL, "two-fluid model needs mu1 != mu2 and mu1 != 0");
@@ -258,7 +265,7 @@ static int launch_stage(rmhd_ctx *c, const StageArgs &A)
         B.guess = as_const(G);
         B.use_guess = 1;
     }
-    const long cells = (long)c->prm.nx * c->prm.ny;
+    const long cells = (long)c->prm.nx * c->geo.ny * c->geo.nz;
     if (c->hx && c->hcount + cells <= c->hcap) {
         B.hx = c->hx;
         B.ht = c->ht;
@@ -271,7 +278,15 @@ static int launch_stage(rmhd_ctx *c, const StageArgs &A)
 template <int M, int NO>
 static void launch_flux_mo(rmhd_ctx *c, const FluxArgs &A)
 {
-    if (c->prm.ndim == 1) {
+    if (c->prm.ndim == 3) {
+        // x and y terms per interior z plane (64 x 16 tiles), then the z term added in place
+        constexpr int BX = 64;
+        const dim3 gxy((unsigned)((c->prm.nx + (BX - 4) - 1) / (BX - 4)), (unsigned)((c->prm.ny + 11) / 12),
+                       (unsigned)c->prm.nz);
+        hipLaunchKernelGGL((k_flux<M, 3, BX, 16, NO>), gxy, dim3(BX, 16), 0, c->stream, A);
+        const dim3 gz((unsigned)((c->prm.nx + BX - 1) / BX), (unsigned)c->prm.ny, (unsigned)((c->prm.nz + 11) / 12));
+        hipLaunchKernelGGL((k_flux_z<M, NO>), gz, dim3(BX, 16), 0, c->stream, A);
+    } else if (c->prm.ndim == 1) {
         constexpr int BX = 256;
         dim3 grid((c->prm.nx + (BX - 4) - 1) / (BX - 4));
         hipLaunchKernelGGL((k_flux<M, 1, BX, 1, NO>), grid, dim3(BX, 1), 0, c->stream, A);
@@ -299,11 +314,23 @@ static void launch_flux_m(rmhd_ctx *c, const FluxArgs &A)
     else launch_flux_mo<M, 1>(c, A);
 }
 
+// 3-D: the flux kernels write interior cells only; the ghost images of output 0 are filled by
+// the boundary kernel afterwards, and the step recovers the primitives in a separate kernel.
 static int launch_flux(rmhd_ctx *c, const FluxArgs &A)
 {
-    if (c->prm.model == RMHD_SINGLE_FLUID) launch_flux_m<0>(c, A);
-    else launch_flux_m<1>(c, A);
-    return hip_check(c, hipGetLastError(), "k_flux launch");
+    FluxArgs B = A;
+    if (c->prm.ndim == 3) {
+        if (A.wnew.p[0]) return fail(c, RMHD_EINVAL, "internal: fused recovery on a 3-D grid");
+        B.fuse_bc = 0;
+    }
+    if (c->prm.model == RMHD_SINGLE_FLUID) launch_flux_m<0>(c, B);
+    else launch_flux_m<1>(c, B);
+    int rc = hip_check(c, hipGetLastError(), "k_flux launch");
+    if (!rc && c->prm.ndim == 3 && A.fuse_bc) {
+        hipLaunchKernelGGL(k_bc, cells_grid(c), dim3(256), 0, c->stream, A.o[0].out, (int)c->lay.ncons, c->geo);
+        rc = hip_check(c, hipGetLastError(), "k_bc launch");
+    }
+    return rc;
 }
 
 extern "C" int rmhd_init_state(rmhd_ctx *c, const double *prims, const double *EB, double *cons)
@@ -445,7 +472,8 @@ static int enqueue_imex(rmhd_ctx *c, double dt, double *cons, double *prims)
     const double gm = SSP2_GAMMA;
     const int M = c->prm.model;
     const bool ssp3 = c->prm.integrator == RMHD_SSP3_332;
-    const bool fused = M == RMHD_SINGLE_FLUID;
+    // single fluid: the last flux pass also recovers the primitives (1-D and 2-D)
+    const bool fused = M == RMHD_SINGLE_FLUID && c->prm.ndim < 3;
     // event pairs: stages, flux passes, recovery (kinds 0, 1, 2)
     int nev = 0, kinds[7];
     auto begin = [&]() {

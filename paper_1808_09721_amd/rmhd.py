@@ -33,12 +33,14 @@ class rmhd_params(ctypes.Structure):
         ("mu1", ctypes.c_double), ("mu2", ctypes.c_double), ("kappa", ctypes.c_double), ("cfl", ctypes.c_double),
         ("c2p_tol", ctypes.c_double), ("newton_tol", ctypes.c_double),
         ("integrator", ctypes.c_int32), ("c2p_primary_only", ctypes.c_int32),
+        ("nz", ctypes.c_int32), ("reserved_", ctypes.c_int32), ("z0", ctypes.c_double), ("z1", ctypes.c_double),
     ]
 
 
 class rmhd_layout(ctypes.Structure):
     _fields_ = [("nxg", ctypes.c_int64), ("nyg", ctypes.c_int64), ("pitch", ctypes.c_int64),
-                ("plane", ctypes.c_int64), ("ncons", ctypes.c_int32), ("nprim", ctypes.c_int32)]
+                ("plane", ctypes.c_int64), ("ncons", ctypes.c_int32), ("nprim", ctypes.c_int32),
+                ("nzg", ctypes.c_int64), ("slab", ctypes.c_int64)]
 
 
 class rmhd_stats(ctypes.Structure):
@@ -159,7 +161,9 @@ def params_from(wl, sigma_cell=None, c2p_tol=1e-13, newton_tol=1e-12, max_c2p_it
                 friction_covariant=0, integrator=SSP2_222, c2p_primary_only=0) -> rmhd_params:
     """rmhd_params from a workload description (paper_1808_09721_amd.workloads.Workload)."""
     p = rmhd_params()
-    p.model, p.ndim, p.nx, p.ny, p.bc = wl.model, wl.ndim, wl.nx, wl.ny if wl.ndim == 2 else 1, wl.bc
+    p.model, p.ndim, p.nx, p.ny, p.bc = wl.model, wl.ndim, wl.nx, wl.ny if wl.ndim >= 2 else 1, wl.bc
+    if wl.ndim == 3:
+        p.nz, p.z0, p.z1 = wl.nz, wl.z0, wl.z1
     p.max_c2p_iter, p.max_newton_iter, p.friction_covariant = max_c2p_iter, max_newton_iter, friction_covariant
     p.x0, p.x1, p.y0, p.y1 = wl.x0, wl.x1, wl.y0, wl.y1
     p.gamma_eos, p.sigma = wl.gamma, wl.sigma
@@ -282,21 +286,29 @@ class Grid:
         self.layout = rmhd_layout_of(params)
         self.ndim = params.ndim
         self.nx, self.ny = params.nx, params.ny
+        self.nz = params.nz if params.ndim == 3 else 1
+
+    @property
+    def cell_shape(self) -> tuple:
+        """Shape of one variable's padded array: (nyg, pitch), or (nzg, nyg, pitch) in 3-D."""
+        L = self.layout
+        return (L.nzg, L.nyg, L.pitch) if self.ndim == 3 else (L.nyg, L.pitch)
 
     def alloc(self, nvar: int, dtype=None, fill: float = 0.0):
         import torch
         dtype = dtype or torch.float64
-        L = self.layout
-        return torch.full((nvar, L.nyg, L.pitch), fill, dtype=dtype, device="cuda")
+        return torch.full((nvar,) + self.cell_shape, fill, dtype=dtype, device="cuda")
 
     def interior_view(self, t):
+        if self.ndim == 3:
+            return t[..., 2:self.nz + 2, 2:self.ny + 2, 2:self.nx + 2]
         if self.ndim == 2:
             return t[..., 2:self.ny + 2, 2:self.nx + 2]
         return t[..., :, 2:self.nx + 2]
 
     def all_view(self, t):
         """All cells, ghosts included, without the row padding."""
-        return t[..., :, :self.layout.nxg]
+        return t[..., :self.layout.nxg]
 
     def upload_interior(self, arr: np.ndarray, nvar: int | None = None, fill: float = 0.0):
         import torch
@@ -315,9 +327,13 @@ class Grid:
         """Per-cell conductivity as one padded device plane, ghosts copied as the boundary
         condition copies state (periodic wrap or outflow edge)."""
         import torch
-        a = np.asarray(sigma_interior, dtype=np.float64).reshape(self.ny if self.ndim == 2 else 1, self.nx)
         mode = "wrap" if self.params.bc == BC_PERIODIC else "edge"
-        full = np.pad(a, ((2, 2) if self.ndim == 2 else (0, 0), (2, 2)), mode=mode)
+        if self.ndim == 3:
+            a = np.asarray(sigma_interior, dtype=np.float64).reshape(self.nz, self.ny, self.nx)
+            full = np.pad(a, ((2, 2), (2, 2), (2, 2)), mode=mode)
+        else:
+            a = np.asarray(sigma_interior, dtype=np.float64).reshape(self.ny if self.ndim == 2 else 1, self.nx)
+            full = np.pad(a, ((2, 2) if self.ndim == 2 else (0, 0), (2, 2)), mode=mode)
         t = self.alloc(1)
         self.all_view(t)[...] = torch.from_numpy(full[None]).cuda()
         return t

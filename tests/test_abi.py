@@ -47,6 +47,29 @@ def test_layout_of_pads_rows_and_counts_variables():
     assert (L.nxg, L.nyg, L.pitch, L.plane) == (404, 1, 408, 408)
 
 
+def test_layout_of_3d_grids():
+    p = R.params_from(WL.kelvin_helmholtz_3d(10, 6, 5, steps=1))
+    L = R.rmhd_layout_of(p)
+    assert (L.nxg, L.nyg, L.nzg, L.pitch) == (14, 10, 9, 16)
+    assert L.slab == 16 * 10 and L.plane == 16 * 10 * 9
+    # below 3-D there is one z plane
+    L2 = R.rmhd_layout_of(R.params_from(WL.kelvin_helmholtz_2d(10, 7, steps=1)))
+    assert (L2.nzg, L2.slab) == (1, L2.plane)
+
+
+@pytest.mark.parametrize("field,value,msg", [("nz", 3, "nz >= 4"), ("ndim", 4, "ndim"), ("reserved_", 1, "reserved_"),
+                                             ("z1", -0.5, "empty domain")])
+def test_layout_of_rejects_bad_3d_parameters(field, value, msg):
+    p = R.params_from(WL.kelvin_helmholtz_3d(8, 8, 8, steps=1))
+    setattr(p, field, value)
+    with pytest.raises(R.RmhdError, match=msg):
+        R.rmhd_layout_of(p)
+    p2 = R.params_from(WL.kelvin_helmholtz_2d(8, 8, steps=1))
+    p2.nz = 5
+    with pytest.raises(R.RmhdError, match="nz"):
+        R.rmhd_layout_of(p2)
+
+
 @pytest.mark.parametrize("field,value,msg", [("nx", 2, "nx >= 4"), ("model", 5, "model"), ("gamma_eos", 2.5, "gamma"),
                                              ("bc", 3, "bc"), ("max_newton_iter", 0, "iteration")])
 def test_layout_of_rejects_bad_parameters(field, value, msg):
