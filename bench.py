@@ -253,6 +253,59 @@ def ssp3_measure(steps: int, warmup: int) -> dict:
     return out
 
 
+def grid3d_measure(steps: int, warmup: int) -> dict:
+    """3-D grids (SSP2(222)): Kelvin-Helmholtz 128 x 256 x 128 (single fluid, 4.2 M cells) and
+    the two-fluid sheet at 128^3 (2.1 M cells); and one y-slab of the two-fluid 1024^2 sheet
+    as eight GPUs would hold it (1024 x 128 cells, sigma ~ 10^U[2, 6] per cell), the shape a
+    sharded step runs on each GPU.  Per-kernel times from a separate timed pass."""
+    import numpy as np
+    import torch
+
+    from paper_1808_09721_amd import rmhd as R
+    from paper_1808_09721_amd import workloads as WL
+    slab = WL.learned_guess_sheet(1024)
+    slab = WL.Workload("two-fluid sheet slab", slab.model, 2, 1024, 128, slab.x0, slab.x1, slab.y0,
+                       slab.y0 + (slab.y1 - slab.y0) / 8, gamma=slab.gamma, sigma=slab.sigma, bc=slab.bc,
+                       mu1=slab.mu1, mu2=slab.mu2, prims=np.ascontiguousarray(slab.prims[:, :128]),
+                       EB=np.ascontiguousarray(slab.EB[:, :128]),
+                       sigma_cell=np.ascontiguousarray(slab.sigma_cell[:128]))
+    out = {}
+    for name, wl in (("kelvin_helmholtz_3d 128x256x128", WL.kelvin_helmholtz_3d()),
+                     ("two_fluid_sheet_3d 128x128x128", WL.two_fluid_sheet_3d(128, 128, 128)),
+                     ("two-fluid sheet 1024x128 (one of 8 y-slabs of 1024^2, sigma~10^U[2,6])", slab)):
+        s = R.Solver.for_workload(wl)
+        c, w = s.initial_state(wl.prims, wl.EB)
+        dt = s.dt()
+        n = max(3, steps)
+        for _ in range(warmup):
+            s.step(dt, c, w)
+        s.stats(reset=True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(n):
+            s.step(dt, c, w)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / n
+        st = s.stats(reset=True)
+        R.rmhd_set_timing(s.ctx, True)
+        R.rmhd_get_timing(s.ctx, reset=True)
+        for _ in range(3):
+            s.step(dt, c, w)
+        tm = R.rmhd_get_timing(s.ctx, reset=True)
+        R.rmhd_set_timing(s.ctx, False)
+        out[name] = {"cells": wl.cells, "steps": n, "ms_per_step": ms, "value": wl.cells / (ms / 1e3),
+                     "unit": "cell-updates/s",
+                     "newton_iters_per_cell_stage": st["newton_iters"] / max(1, st["stage_cells"]),
+                     "failures": st["failures"],
+                     "stage_ms_per_launch": tm["stage_ms"] / max(1, tm["stage_launches"]),
+                     "flux_ms_per_pass": tm["flux_ms"] / max(1, tm["flux_launches"]),
+                     "c2p_ms_per_launch": tm["c2p_ms"] / tm["c2p_launches"] if tm["c2p_launches"] else None}
+        s.close()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -263,6 +316,7 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-ssp3", action="store_true")
+    ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (traffic calibration)")
     args = ap.parse_args()
@@ -386,6 +440,8 @@ def main() -> int:
         out["learned"] = learned_measure(10, args.warmup)
     if not args.no_ssp3:
         out["ssp3"] = ssp3_measure(max(10, args.steps // 2), args.warmup)
+    if not args.no_3d:
+        out["grid3d"] = grid3d_measure(max(3, args.steps // 20), args.warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
         out["cpu_baseline"]["gpu_speedup"] = value / out["cpu_baseline"]["value"]
