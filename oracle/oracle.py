@@ -136,11 +136,11 @@ class Grid:
 
     @property
     def ncons(self) -> int:
-        return 14 if self.model == 0 else 18
+        return {0: 14, 1: 18, 2: 9}[self.model]
 
     @property
     def nprim(self) -> int:
-        return 5 if self.model == 0 else 10
+        return 10 if self.model == 1 else 5
 
     def interior(self, a: np.ndarray) -> np.ndarray:
         """View of the interior cells of a [var][NY][NX] (3-D: [var][NZ][NY][NX]) array."""

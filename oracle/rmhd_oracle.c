@@ -23,12 +23,17 @@ enum { SF_D, SF_SX, SF_SY, SF_SZ, SF_TAU, SF_BX, SF_BY, SF_BZ, SF_EX, SF_EY, SF_
        SF_RHOE, SF_PSI, SF_PHI, SF_NC };
 enum { TF_D, TF_SX, TF_SY, TF_SZ, TF_TAU, TF_DB, TF_SBX, TF_SBY, TF_SBZ, TF_TAUB,
        TF_BX, TF_BY, TF_BZ, TF_EX, TF_EY, TF_EZ, TF_PSI, TF_PHI, TF_NC };
+enum { ID_D, ID_SX, ID_SY, ID_SZ, ID_TAU, ID_BX, ID_BY, ID_BZ, ID_PHI, ID_NC };
 enum { P_RHO, P_VX, P_VY, P_VZ, P_P, FLUID_NP };
 #define MAXC 18
 #define MAXP 10
 
-int orc_ncons(int model) { return model == 0 ? SF_NC : TF_NC; }
-int orc_nprim(int model) { return model == 0 ? FLUID_NP : 2 * FLUID_NP; }
+int orc_ncons(int model) { return model == 0 ? SF_NC : model == 1 ? TF_NC : ID_NC; }
+int orc_nprim(int model) { return model == 1 ? 2 * FLUID_NP : FLUID_NP; }
+
+static void ideal_prim2cons(const orc_params *p, const double *w, const double *B, double *q);
+static int ideal_c2p(const orc_params *p, const double *q, double *w, int *iters);
+static void ideal_flux(const orc_params *p, const double *q, const double *w, int k, double *f);
 
 static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 static void cross3(const double *a, const double *b, double *c)
@@ -53,6 +58,10 @@ static double enthalpy(double gam, double rho, double p) { return 1.0 + gam * p 
  * Two fluid, Sec. 2.1.2 Eq. 6, summed over the species s = 1, 2. */
 void orc_prim2cons_cell(const orc_params *p, const double *w, const double *EB, double rho_e, double *q)
 {
+    if (p->model == 2) {
+        ideal_prim2cons(p, w, EB, q);
+        return;
+    }
     const double *B = EB, *E = EB + 3;
     double ExB[3];
     cross3(E, B, ExB);
@@ -161,6 +170,7 @@ static int fluid_c2p(double gam, double D, const double *St, double taut, double
  * w holds the pressure guess(es) on entry and the primitives on exit. */
 int orc_cons2prim_cell(const orc_params *p, const double *q, double *w, int *iters)
 {
+    if (p->model == 2) return ideal_c2p(p, q, w, iters);
     const int model = p->model;
     const double *B = q + (model == 0 ? SF_BX : TF_BX), *E = q + (model == 0 ? SF_EX : TF_EX);
     double ExB[3], St[3];
@@ -241,6 +251,10 @@ static void em_flux(const double *B, const double *E, double psi, double phi, in
 void orc_flux_cell(const orc_params *p, const double *q, const double *w, double sigma, int k,
                    double *f)
 {
+    if (p->model == 2) {
+        ideal_flux(p, q, w, k, f);
+        return;
+    }
     if (p->model == 0) {
         const double *B = q + SF_BX, *E = q + SF_EX, *v = w + P_VX;
         const double rho = w[P_RHO], pr = w[P_P];
@@ -297,6 +311,11 @@ void orc_flux_cell(const orc_params *p, const double *q, const double *w, double
  * rho_e in Psi(psi) is the conserved Dbar, which equals sum mu_s rho_s W_s by Eq. 6. */
 void orc_source_cell(const orc_params *p, const double *q, const double *w, double sigma, double *s)
 {
+    if (p->model == 2) {   /* ideal: only the divergence cleaning damps */
+        for (int c = 0; c < ID_NC; ++c) s[c] = 0.0;
+        s[ID_PHI] = -p->kappa * q[ID_PHI];
+        return;
+    }
     if (p->model == 0) {
         for (int c = 0; c < SF_NC; ++c) s[c] = 0.0;
         double J[3];
@@ -585,6 +604,123 @@ void orc_weno3_face(const double *fa, const double *fb, const double *fc, double
 }
 
 /* ------------------------------------------------------------------------------------------
+ * Ideal RMHD, the comparison model advanced with explicit integrators (Sec. 2.1 lists it
+ * among the models; its recovery is a two-dimensional root-find in the formulation of the
+ * cited Anton et al. 2010, Sec. 2.1.3).  Conserved (9): D, Sx, Sy, Sz, tau, Bx, By, Bz, phi;
+ * primitive (5): rho, vx, vy, vz, p.  The electric field is E = -v x B, and the magnetic
+ * field is cleaned as in the resistive models: d_t phi + d_k B^k = -kappa phi, the flux of
+ * B^i gaining phi along i.
+ * ---------------------------------------------------------------------------------------- */
+
+/* D = rho W, S = (rho h W^2 + B^2) v - (v.B) B,
+ * tau = rho h W^2 - p + (B^2 + v^2 B^2 - (v.B)^2)/2 - D  (the resistive expressions with
+ * E = -v x B: E x B = v B^2 - (v.B) B and E^2 = v^2 B^2 - (v.B)^2); phi = 0 at t = 0. */
+static void ideal_prim2cons(const orc_params *p, const double *w, const double *B, double *q)
+{
+    const double rho = w[P_RHO], *v = w + P_VX, pr = w[P_P];
+    const double W = lorentz(v), h = enthalpy(p->gamma, rho, pr);
+    const double vB = dot3(v, B), B2 = dot3(B, B), v2 = dot3(v, v);
+    q[ID_D] = rho * W;
+    for (int i = 0; i < 3; ++i) q[ID_SX + i] = (rho * h * W * W + B2) * v[i] - vB * B[i];
+    q[ID_TAU] = rho * h * W * W - pr + 0.5 * (B2 + v2 * B2 - vB * vB) - rho * W;
+    for (int i = 0; i < 3; ++i) q[ID_BX + i] = B[i];
+    q[ID_PHI] = 0.0;
+}
+
+/* Energy residual of the recovery reduced to one unknown, Z = rho h W^2.  From
+ * S^2 = (Z + B^2)^2 v^2 - (2Z + B^2) (S.B)^2 / Z^2 the velocity follows from Z,
+ *   v^2(Z) = (S^2 Z^2 + (S.B)^2 (2Z + B^2)) / (Z^2 (Z + B^2)^2),
+ * and with u = 1 - v^2, rho = D sqrt(u), p = (Gamma-1)/Gamma (Z u - rho) (Gamma law), the
+ * energy equation tau + D = Z + B^2 - p - B^2 u / 2 - (S.B)^2 / (2 Z^2) leaves
+ *   f(Z) = Z + B^2 - p - B^2 u/2 - (S.B)^2/(2 Z^2) - (tau + D).
+ * Returns 0 where v^2(Z) >= 1 (Z too small); f and f' otherwise. */
+static int ideal_residual(double gam, double D, double S2, double SB2, double B2, double Et, double Z,
+                          double *f, double *df)
+{
+    const double N = S2 * Z * Z + SB2 * (2.0 * Z + B2);
+    const double M = Z * Z * (Z + B2) * (Z + B2);
+    const double v2 = N / M;
+    if (!(v2 < 1.0)) return 0;
+    const double u = 1.0 - v2, su = sqrt(u);
+    const double g = (gam - 1.0) / gam;
+    const double pr = g * (Z * u - D * su);
+    *f = Z + B2 - pr - 0.5 * B2 * u - 0.5 * SB2 / (Z * Z) - Et;
+    const double dN = 2.0 * S2 * Z + 2.0 * SB2;
+    const double dM = 2.0 * Z * (Z + B2) * (2.0 * Z + B2);
+    const double du = -(dN * M - N * dM) / (M * M);
+    const double dp = g * (u + Z * du - D * du / (2.0 * su));
+    *df = 1.0 - dp - 0.5 * B2 * du + SB2 / (Z * Z * Z);
+    return 1;
+}
+
+/* Recovery: the unique Z > 0 with v^2 < 1 and f(Z) = 0, bracketed (a Z with v^2 >= 1 or
+ * f < 0 lies below the root, f > 0 above) and found by Newton steps kept inside the bracket
+ * (bisection otherwise), until the step is at rounding level; then v = (S + (S.B) B / Z) /
+ * (Z + B^2), rho = D sqrt(1 - v^2) and p as above.  The guess in w is not needed. */
+static int ideal_c2p(const orc_params *p, const double *q, double *w, int *iters)
+{
+    const double D = q[ID_D], *S = q + ID_SX, *B = q + ID_BX;
+    const double Et = q[ID_TAU] + D, S2 = dot3(S, S), SB = dot3(S, B), B2 = dot3(B, B), SB2 = SB * SB;
+    *iters = 0;
+    if (!(D > 0.0) || !(Et > 0.0) || !isfinite(S2 + B2)) return ORC_C2P_UNPHYS;
+    double lo = 0.0, hi = 2.0 * Et + 1.0, f, df;
+    int k;
+    for (k = 0; k < 200; ++k) {   /* an upper end where f > 0 */
+        if (ideal_residual(p->gamma, D, S2, SB2, B2, Et, hi, &f, &df) && f > 0.0) break;
+        lo = hi;
+        hi *= 2.0;
+    }
+    if (k == 200) return ORC_C2P_UNPHYS;
+    double Z = 0.5 * (lo + hi);
+    int conv = 0, it;
+    for (it = 1; it <= 400; ++it) {
+        double Zn;
+        if (!ideal_residual(p->gamma, D, S2, SB2, B2, Et, Z, &f, &df)) {
+            lo = Z;
+            Zn = 0.5 * (lo + hi);
+        } else {
+            if (f > 0.0) hi = Z; else lo = Z;
+            Zn = (df > 0.0 && it <= 60) ? Z - f / df : 0.5 * (lo + hi);   /* bisection after 60 */
+            if (!(Zn > lo && Zn < hi)) Zn = 0.5 * (lo + hi);
+        }
+        const double step = fabs(Zn - Z);
+        Z = Zn;
+        if (step <= 4.0 * 2.220446049250313e-16 * Z || hi - lo <= 4.0 * 2.220446049250313e-16 * hi) {
+            conv = 1;
+            break;
+        }
+    }
+    *iters = it;
+    if (!conv || !ideal_residual(p->gamma, D, S2, SB2, B2, Et, Z, &f, &df)) return ORC_C2P_NOCONV;
+    for (int i = 0; i < 3; ++i) w[P_VX + i] = (S[i] + SB * B[i] / Z) / (Z + B2);
+    const double u = 1.0 - dot3(w + P_VX, w + P_VX);
+    w[P_RHO] = D * sqrt(u);
+    w[P_P] = (p->gamma - 1.0) / p->gamma * (Z * u - w[P_RHO]);
+    if (!(w[P_RHO] > 0.0) || !(w[P_P] > 0.0) || !(u > 0.0)) return ORC_C2P_UNPHYS;
+    return ORC_OK;
+}
+
+/* Fluxes along k (Anton et al. 2010 form): with b^0 = W (v.B), b^i = B^i / W + b^0 v^i,
+ * b^2 = B^2 / W^2 + (v.B)^2,
+ *   f(D) = D v^k,  f(S_i) = S_i v^k + (p + b^2/2) delta_ik - b_i B^k / W,
+ *   f(tau) = S_k - D v^k,  f(B^i) = v^k B^i - v^i B^k + phi delta_ik,  f(phi) = B^k. */
+static void ideal_flux(const orc_params *p, const double *q, const double *w, int k, double *f)
+{
+    const double *v = w + P_VX, pr = w[P_P], *B = q + ID_BX;
+    const double W = lorentz(v), vB = dot3(v, B), B2 = dot3(B, B);
+    const double b0 = W * vB, b2 = B2 / (W * W) + vB * vB;
+    (void)p;
+    f[ID_D] = q[ID_D] * v[k];
+    for (int i = 0; i < 3; ++i) {
+        const double bi = B[i] / W + b0 * v[i];
+        f[ID_SX + i] = q[ID_SX + i] * v[k] + ((i == k) ? pr + 0.5 * b2 : 0.0) - bi * B[k] / W;
+    }
+    f[ID_TAU] = q[ID_SX + k] - q[ID_D] * v[k];
+    for (int i = 0; i < 3; ++i) f[ID_BX + i] = v[k] * B[i] - v[i] * B[k] + ((i == k) ? q[ID_PHI] : 0.0);
+    f[ID_PHI] = B[k];
+}
+
+/* ------------------------------------------------------------------------------------------
  * Grid helpers
  * ---------------------------------------------------------------------------------------- */
 /* Cell (i, j, k) of a [var][NZ][NY][NX] array lives at v * plane + (k * NY + j) * NX + i;
@@ -811,9 +947,12 @@ void orc_implicit(const orc_params *p, double a, const double *R, double *Q, dou
  *   q^{n+1} = q^n + dt/2 [L(Q1) + L(Q2)] + dt/2 [Psi(Q1) + Psi(Q2)]
  * Psi(Q_i) is evaluated from the converged primitives.  The primitives of q^{n+1} are then
  * recovered (guess: those of Q2).  Returns the number of cells with a nonzero status. */
+static int explicit_step(const orc_params *p, double dt, int stages, double *cons, double *prims, int *nfail);
+
 int orc_ssp2_step(const orc_params *p, double dt, double *cons, double *prims, long long *newton_iters,
                   int *max_newton, int *nfail)
 {
+    if (p->model == 2) return explicit_step(p, dt, 2, cons, prims, nfail);
     const double g = 1.0 - 1.0 / sqrt(2.0);
     const int nc = orc_ncons(p->model), np = orc_nprim(p->model);
     const long pl = plane(p);
@@ -894,6 +1033,7 @@ static void stage_tally(const orc_params *p, const signed char *st, const int *i
 int orc_ssp3_step(const orc_params *p, double dt, double *cons, double *prims, long long *newton_iters,
                   int *max_newton, int *nfail)
 {
+    if (p->model == 2) return explicit_step(p, dt, 3, cons, prims, nfail);
     const double g = 1.0 - 1.0 / sqrt(2.0);
     const int nc = orc_ncons(p->model), np = orc_nprim(p->model);
     const long pl = plane(p);
@@ -942,6 +1082,61 @@ int orc_ssp3_step(const orc_params *p, double dt, double *cons, double *prims, l
     if (nfail) *nfail += bad;
     free(Q1); free(Q2); free(Q3); free(R); free(L1); free(L2); free(L3); free(S1); free(S2); free(S3);
     free(w); free(st); free(it);
+    return bad;
+}
+
+/* The ideal model's explicit step: the explicit halves of the IMEX tableaux (Eq. 11),
+ * Table 2 (stages = 2: at_21 = 1, weights 1/2, 1/2) or Table 3 (stages = 3: at_21 = 1,
+ * at_31 = at_32 = 1/4, weights 1/6, 1/6, 2/3), with the cleaning source explicit too:
+ *   q(i) = q^n + dt sum_{j<i} at_ij K_j,   q^{n+1} = q^n + dt sum_i w_i K_i,
+ *   K_j = L(q(j)) + Psi(q(j)).
+ * Each stage's primitives are recovered from the previous ones; returns the number of cells
+ * whose recovery failed. */
+static int explicit_step(const orc_params *p, double dt, int stages, double *cons, double *prims, int *nfail)
+{
+    const double at[3][3] = { { 0.0, 0.0, 0.0 }, { 1.0, 0.0, 0.0 }, { 0.25, 0.25, 0.0 } };
+    const double w2[3] = { 0.5, 0.5, 0.0 }, w3[3] = { 1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0 };
+    const double *wt = stages == 2 ? w2 : w3;
+    const int nc = orc_ncons(p->model), np = orc_nprim(p->model);
+    const long pl = plane(p);
+    const size_t bc = sizeof(double) * nc * pl, bp = sizeof(double) * np * pl;
+    double *K[3], *q = malloc(bc), *w = malloc(bp), *S = malloc(bc);
+    signed char *st = malloc(pl);
+    int *it = malloc(sizeof(int) * pl);
+    int bad = 0;
+    for (int i = 0; i < stages; ++i) K[i] = malloc(bc);
+    memcpy(q, cons, bc);
+    memcpy(w, prims, bp);
+    for (int i = 0; i < stages; ++i) {
+        if (i > 0) {
+            for (long k = 0; k < nc * pl; ++k) {
+                double sum = 0.0;
+                for (int j = 0; j < i; ++j) sum += at[i][j] * K[j][k];
+                q[k] = cons[k] + dt * sum;
+            }
+            orc_bc_fill(p, q, nc);
+            orc_cons2prim(p, q, w, st, it);
+            for (long idx = 0; idx < pl; ++idx) bad += st[idx] != ORC_OK;
+        }
+        orc_rhs(p, q, w, K[i]);
+        source_grid(p, q, w, S);
+        for (long k = 0; k < nc * pl; ++k) K[i][k] += S[k];
+    }
+    for (int v = 0; v < nc; ++v)
+        for (long r = 0; r < nrows(p); ++r)
+            for (int i = 2; i < p->nx + 2; ++i) {
+                const long k = v * pl + row_base(p, r) + i;
+                double sum = 0.0;
+                for (int j = 0; j < stages; ++j) sum += wt[j] * K[j][k];
+                cons[k] = cons[k] + dt * sum;
+            }
+    orc_bc_fill(p, cons, nc);
+    memcpy(prims, w, bp);
+    orc_cons2prim(p, cons, prims, st, it);
+    for (long idx = 0; idx < pl; ++idx) bad += st[idx] != ORC_OK;
+    if (nfail) *nfail += bad;
+    for (int i = 0; i < stages; ++i) free(K[i]);
+    free(q); free(w); free(S); free(st); free(it);
     return bad;
 }
 

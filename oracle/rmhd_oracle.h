@@ -11,10 +11,10 @@
  * hold none of the method's arithmetic) and through numpy arrays in the tests.
  *
  * Layout used by every grid-level routine here (independent of the GPU layout):
- *   array[v][j][i], v = variable, j = 0..NY-1, i = 0..NX-1, x fastest, where
- *   NX = nx + 4 and NY = ny + 4 in 2-D, NY = 1 in 1-D (two ghost cells per side in
- *   every simulated direction).  Interior cell (ix, iy) sits at i = ix + 2,
- *   j = iy + 2 (2-D) or j = 0 (1-D).
+ *   array[v][k][j][i], v = variable, k = 0..NZ-1, j = 0..NY-1, i = 0..NX-1, x fastest,
+ *   where NX = nx + 4, NY = ny + 4 in 2-D and 3-D (1 in 1-D), NZ = nz + 4 in 3-D (1
+ *   below): two ghost cells per side in every simulated direction.  Interior cell
+ *   (ix, iy, iz) sits at i = ix + 2, j = iy + 2, k = iz + 2 (or 0 where absent).
  *
  * Variable orders:
  *   single fluid, conserved (14): D, Sx, Sy, Sz, tau, Bx, By, Bz, Ex, Ey, Ez, rho_e, psi, phi
@@ -23,6 +23,10 @@
  *                                 Bx, By, Bz, Ex, Ey, Ez, psi, phi
  *   two fluid, primitive (10):    rho1, v1x, v1y, v1z, p1, rho2, v2x, v2y, v2z, p2
  *                                 (species 1 has charge-to-mass ratio mu1, species 2 mu2)
+ *   ideal, conserved (9):         D, Sx, Sy, Sz, tau, Bx, By, Bz, phi
+ *   ideal, primitive (5):         rho, vx, vy, vz, p
+ * The ideal model has no stiff source: orc_ssp2_step / orc_ssp3_step advance it with the
+ * explicit halves of the same tableaux (no implicit stage).
  */
 #ifndef RMHD_ORACLE_H
 #define RMHD_ORACLE_H
@@ -32,7 +36,7 @@ extern "C" {
 #endif
 
 typedef struct orc_params {
-    int model;              /* 0 = resistive single fluid, 1 = resistive two fluid */
+    int model;              /* 0 = resistive single fluid, 1 = resistive two fluid, 2 = ideal */
     int ndim;               /* 1, 2 or 3 */
     int nx, ny;             /* interior cells (ny = 1 in 1-D) */
     int bc;                 /* 0 = outflow (zero-gradient copy), 1 = periodic */

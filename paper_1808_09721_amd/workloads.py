@@ -19,7 +19,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-SINGLE_FLUID, TWO_FLUID = 0, 1
+SINGLE_FLUID, TWO_FLUID, IDEAL = 0, 1, 2
 BC_OUTFLOW, BC_PERIODIC = 0, 1
 
 
@@ -64,11 +64,11 @@ class Workload:
 
     @property
     def ncons(self) -> int:
-        return 14 if self.model == SINGLE_FLUID else 18
+        return {SINGLE_FLUID: 14, TWO_FLUID: 18, IDEAL: 9}[self.model]
 
     @property
     def nprim(self) -> int:
-        return 5 if self.model == SINGLE_FLUID else 10
+        return 10 if self.model == TWO_FLUID else 5
 
     @property
     def cells(self) -> int:
@@ -165,9 +165,18 @@ def two_fluid_sheet_3d(nx: int = 64, ny: int = 64, nz: int = 64, sigma: float = 
                     nz=nz, z0=-0.5, z1=0.5)
 
 
+def as_ideal(wl: Workload) -> Workload:
+    """The same single-fluid set-up for the ideal model: the same primitives and B (the ideal
+    model's electric field is -v x B, so the given E is not used)."""
+    assert wl.model == SINGLE_FLUID
+    return Workload(wl.name + "_ideal", IDEAL, wl.ndim, wl.nx, wl.ny, wl.x0, wl.x1, wl.y0, wl.y1, gamma=wl.gamma,
+                    sigma=wl.sigma, bc=wl.bc, cfl=wl.cfl, kappa=wl.kappa, steps=wl.steps, t_end=wl.t_end,
+                    prims=wl.prims, EB=wl.EB, nz=wl.nz, z0=wl.z0, z1=wl.z1)
+
+
 def _vector_slots(model: int) -> list[tuple[int, int, int]]:
     """Indices of the (x, y, z) components of each velocity in a primitive array."""
-    return [(1, 2, 3)] if model == SINGLE_FLUID else [(1, 2, 3), (6, 7, 8)]
+    return [(1, 2, 3), (6, 7, 8)] if model == TWO_FLUID else [(1, 2, 3)]
 
 
 def _rotate_components(arr: np.ndarray, slots) -> np.ndarray:

@@ -11,8 +11,9 @@ from oracle import oracle as O
 
 # (x, y, z) component triples of the vectors in each array, by model: conserved (S, [Sbar,]
 # B, E), primitive (the velocity of each fluid)
-CONS_VECTORS = {0: [(1, 2, 3), (5, 6, 7), (8, 9, 10)], 1: [(1, 2, 3), (6, 7, 8), (10, 11, 12), (13, 14, 15)]}
-PRIM_VECTORS = {0: [(1, 2, 3)], 1: [(1, 2, 3), (6, 7, 8)]}
+CONS_VECTORS = {0: [(1, 2, 3), (5, 6, 7), (8, 9, 10)], 1: [(1, 2, 3), (6, 7, 8), (10, 11, 12), (13, 14, 15)],
+                2: [(1, 2, 3), (5, 6, 7)]}
+PRIM_VECTORS = {0: [(1, 2, 3)], 1: [(1, 2, 3), (6, 7, 8)], 2: [(1, 2, 3)]}
 
 
 def rotate_state(arr: np.ndarray, slots) -> np.ndarray:

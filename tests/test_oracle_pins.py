@@ -805,3 +805,163 @@ def test_3d_periodic_conservation():
     sums1 = g.interior(c).reshape(g.ncons, -1).sum(axis=1)
     for v in (0, 1, 2, 3, 4, 5, 6, 7):
         assert abs(sums1[v] - sums0[v]) <= 1e-13 * max(scale[v], scale[0])
+
+
+# ------------------------------------------------------------------------------------------
+# ideal RMHD, the explicit comparison model (Sec. 2.1, Sec. 2.1.3)
+# ------------------------------------------------------------------------------------------
+def id_grid(gamma=4.0 / 3.0):
+    return _O().Grid(model=2, ndim=1, nx=8, ny=1, dx=0.1, dy=1.0, gamma=gamma, sigma=1.0, bc=1)
+
+
+def ideal_tensors(rho, p, gamma, v, B):
+    """T^{mu nu}, N^mu and the dual Faraday tensor *F^{mu nu} of an ideal magnetised fluid,
+    built from the comoving field b^mu: T = (e + p + b^2) u u + (p + b^2/2) eta - b b,
+    *F = b u - u b, with b^0 = W (v.B), b^i = B^i / W + b^0 v^i."""
+    v, B = np.asarray(v, float), np.asarray(B, float)
+    W = 1.0 / np.sqrt(1.0 - v @ v)
+    u = W * np.array([1.0, *v])
+    b0 = W * (v @ B)
+    b = np.array([b0, *(B / W + b0 * v)])
+    eta = np.diag([-1.0, 1.0, 1.0, 1.0])
+    b2 = b @ eta @ b
+    e = rho + p / (gamma - 1.0)
+    T = (e + p + b2) * np.outer(u, u) + (p + 0.5 * b2) * np.linalg.inv(eta) - np.outer(b, b)
+    N = rho * u
+    Fd = np.outer(b, u) - np.outer(u, b)
+    return T, N, Fd
+
+
+@pytest.mark.parametrize("gamma", [4.0 / 3.0, 2.0])
+def test_ideal_prim2cons_and_flux_are_the_stress_energy_tensor(gamma):
+    """D = N^0, S_i = T^{0i}, tau = T^{00} - N^0, B^i = *F^{i0}; fluxes along k: N^k, T^{ik},
+    T^{0k} - N^k and *F^{ik}, with phi = 0 (tensors built with numpy from b^mu)."""
+    O = _O()
+    g = id_grid(gamma)
+    prims, EB = WL.random_states(300, 0, seed=61, w_max=5.0, field_max=3.0)
+    for k in range(len(prims)):
+        w, B = prims[k], EB[k, :3]
+        q = O.prim2cons_cell(g, w, EB[k])
+        T, N, Fd = ideal_tensors(w[0], w[4], gamma, w[1:4], B)
+        np.testing.assert_allclose(q[0], N[0], rtol=1e-13)
+        np.testing.assert_allclose(q[1:4], T[0, 1:], rtol=1e-12, atol=1e-12 * abs(T[0, 0]))
+        np.testing.assert_allclose(q[4], T[0, 0] - N[0], rtol=1e-12, atol=1e-12 * abs(T[0, 0]))
+        np.testing.assert_allclose(q[5:8], Fd[1:, 0], rtol=1e-13, atol=1e-15)
+        assert q[8] == 0.0
+        for d in range(3):
+            f = O.flux_cell(g, q, w, d)
+            sc = np.abs(T).max()
+            np.testing.assert_allclose(f[0], N[1 + d], rtol=1e-12, atol=1e-13 * abs(N[0]))
+            np.testing.assert_allclose(f[1:4], T[1:, 1 + d], rtol=1e-11, atol=1e-12 * sc)
+            np.testing.assert_allclose(f[4], T[0, 1 + d] - N[1 + d], rtol=1e-11, atol=1e-12 * sc)
+            np.testing.assert_allclose(f[5:8], Fd[1:, 1 + d], rtol=1e-12, atol=1e-13 * np.abs(B).max())
+            assert f[8] == B[d]
+
+
+def test_ideal_is_the_resistive_model_with_ideal_ohms_law():
+    """At E = -v x B the resistive single-fluid model's D, S, tau and B, and their fluxes,
+    are the ideal model's (the ideal model carries no E, rho_e or psi)."""
+    O = _O()
+    gi, gr = id_grid(), sf_grid()
+    prims, EB = WL.random_states(300, 0, seed=62, w_max=5.0, field_max=3.0)
+    for k in range(len(prims)):
+        w, B = prims[k], EB[k, :3]
+        E = -np.cross(w[1:4], B)
+        qi = O.prim2cons_cell(gi, w, EB[k])
+        qr = O.prim2cons_cell(gr, w, np.concatenate([B, E]))
+        sel = [0, 1, 2, 3, 4, 5, 6, 7]
+        np.testing.assert_allclose(qi[sel], qr[sel], rtol=1e-12, atol=1e-12 * abs(qr[4]))
+        for d in range(3):
+            fi = O.flux_cell(gi, qi, w, d)
+            fr = O.flux_cell(gr, qr, w, d)
+            sc = np.abs(fr[:5]).max()
+            np.testing.assert_allclose(fi[:5], fr[:5], rtol=1e-11, atol=1e-12 * sc)
+            np.testing.assert_allclose(fi[5:8], fr[5:8], rtol=1e-12, atol=1e-13 * np.abs(B).max())
+
+
+@pytest.mark.parametrize("gamma", [4.0 / 3.0, 2.0])
+def test_ideal_c2p_inverts_prim2cons(gamma):
+    """The ideal recovery (one unknown Z = rho h W^2, bracketed Newton) reproduces the
+    conserved state to round-off on hard states (W to 10, |B| to 10, p/rho over six
+    decades), and the primitives to 1e-11 on well-conditioned ones (W <= 3, |B| <= 1,
+    p/rho in [0.1, 10], rho in [0.1, 10])."""
+    O = _O()
+    g = id_grid(gamma)
+    prims, EB = WL.random_states(1500, 0, seed=63, w_max=10.0)
+    worst = 0.0
+    for k in range(len(prims)):
+        q = O.prim2cons_cell(g, prims[k], EB[k])
+        w, st, _ = O.cons2prim_cell(g, q)
+        assert st == O.OK, k
+        q2 = O.prim2cons_cell(g, w, EB[k])
+        worst = max(worst, np.max(np.abs(q2 - q)) / np.max(np.abs(q)))
+    assert worst < 2e-13
+    prims, EB = WL.random_states(1500, 0, seed=64, w_max=3.0, field_max=1.0, log_rho=(-1, 1),
+                                 log_p_over_rho=(-1, 1))
+    worst = 0.0
+    for k in range(len(prims)):
+        q = O.prim2cons_cell(g, prims[k], EB[k])
+        w, st, _ = O.cons2prim_cell(g, q)
+        assert st == O.OK
+        ps = prims[k]
+        worst = max(worst, abs(w[0] / ps[0] - 1), abs(w[4] / ps[4] - 1), np.max(np.abs(w[1:4] - ps[1:4])))
+    assert worst < 1e-11
+
+
+@pytest.mark.parametrize("scheme,order", [("ssp2", 2.0), ("ssp3", 3.0)])
+def test_ideal_explicit_temporal_order(scheme, order):
+    """The ideal model's explicit steps are the explicit halves of Tables 2 and 3: second and
+    third order in time on a smooth advected density wave (fixed grid, halving dt, errors
+    against a run with dt/16)."""
+    O = _O()
+
+    def run(cfl):
+        wl = WL.as_ideal(WL.entropy_wave_1d(64))
+        g, cons, prims = initial_state(wl)
+        advance(g, cons, prims, O.dt(g, cfl), t_end=0.25, scheme=scheme)
+        return g.interior(prims)[0, 0]
+
+    ref = run(0.8 / 16)
+    errs = [np.abs(run(c) - ref).mean() for c in (0.8, 0.4, 0.2)]
+    measured = np.log2(errs[1] / errs[2])
+    assert abs(measured - order) < 0.35, (errs, measured)
+
+
+def test_ideal_entropy_wave_converges_and_conserves():
+    """The smooth wave converges at second order in space and time (SSP2), and a periodic
+    Kelvin-Helmholtz run conserves D, S, tau and B to round-off."""
+    O = _O()
+    errs = []
+    for N in (32, 64, 128):
+        wl = WL.as_ideal(WL.entropy_wave_1d(N))
+        g, cons, prims = initial_state(wl)
+        advance(g, cons, prims, O.dt(g, 0.5), t_end=2.0)
+        x = (np.arange(N) + 0.5) / N
+        errs.append(np.mean(np.abs(g.interior(prims)[0, 0] - (1 + 0.5 * np.sin(2 * np.pi * (x - 1.0))))))
+    assert np.log2(errs[0] / errs[-1]) / 2 > 1.8, errs
+    wl = WL.as_ideal(WL.kelvin_helmholtz_2d(24, 32, seed=7))
+    g, c, p = initial_state(wl)
+    tot0 = g.interior(c).sum(axis=(1, 2))
+    advance(g, c, p, O.dt(g, 0.5), steps=10, scheme="ssp3")
+    tot = g.interior(c).sum(axis=(1, 2))
+    scale = np.abs(g.interior(c)).sum(axis=(1, 2))
+    for v in range(8):
+        assert abs(tot[v] - tot0[v]) <= 1e-13 * max(scale[v], scale[0]), v
+
+
+def test_resistive_brio_wu_tends_to_the_ideal_run():
+    """As sigma grows the resistive single-fluid Brio-Wu tube approaches the ideal model's
+    (the trend the paper's resistive Brio-Wu figure shows): the L1 distance of B_y at t = 0.4
+    falls monotonically over sigma = 1e1, 1e2, 1e3, by more than 3x overall."""
+    O = _O()
+    wli = WL.as_ideal(WL.brio_wu_1d(200))
+    gi, ci, pi = initial_state(wli)
+    dt = O.dt(gi, 0.5)
+    advance(gi, ci, pi, dt, t_end=0.4)
+    dists = []
+    for sig in (1e1, 1e2, 1e3):
+        wl = WL.brio_wu_1d(200, sigma=sig)
+        g, c, p = initial_state(wl)
+        advance(g, c, p, dt, t_end=0.4)
+        dists.append(np.abs(g.interior(c)[6, 0] - gi.interior(ci)[6, 0]).mean())
+    assert dists[0] > dists[1] > dists[2] and dists[0] > 3 * dists[2], dists
