@@ -23,7 +23,9 @@
  *   two fluid     conserved (18): D, Sx, Sy, Sz, tau, Dbar, Sbx, Sby, Sbz, taubar,
  *                                 Bx, By, Bz, Ex, Ey, Ez, psi, phi
  *                 primitive (10): rho1, v1x, v1y, v1z, p1, rho2, v2x, v2y, v2z, p2
- *   fields EB (6, init only):     Bx, By, Bz, Ex, Ey, Ez
+ *   ideal         conserved  (9): D, Sx, Sy, Sz, tau, Bx, By, Bz, phi   (E = -v x B)
+ *                 primitive  (5): rho, vx, vy, vz, p
+ *   fields EB (6, init only):     Bx, By, Bz, Ex, Ey, Ez (the ideal model reads B only)
  *
  * Streams.  All work is enqueued on the HIP stream given to rmhd_create() and is ordered
  * with the caller's other work on that stream; calls return before the GPU finishes,
@@ -46,6 +48,7 @@ extern "C" {
 
 #define RMHD_SINGLE_FLUID 0
 #define RMHD_TWO_FLUID 1
+#define RMHD_IDEAL 2       /* ideal RMHD, advanced by explicit steps (see rmhd_imex_step) */
 #define RMHD_BC_OUTFLOW 0  /* zero-gradient copy of the nearest interior cell */
 #define RMHD_BC_PERIODIC 1
 
@@ -66,7 +69,7 @@ extern "C" {
 #define RMHD_SSP3_332 1
 
 typedef struct rmhd_params {
-    int32_t model;            /* RMHD_SINGLE_FLUID or RMHD_TWO_FLUID */
+    int32_t model;            /* RMHD_SINGLE_FLUID, RMHD_TWO_FLUID or RMHD_IDEAL */
     int32_t ndim;             /* 1, 2 or 3 */
     int32_t nx, ny;           /* interior cells (ny = 1 in 1-D); nz below */
     int32_t bc;               /* RMHD_BC_OUTFLOW or RMHD_BC_PERIODIC, all sides */
@@ -152,7 +155,7 @@ int rmhd_cons2prim(rmhd_ctx *ctx, const double *cons, double *prims, int8_t *sta
  * L: written on the interior only. */
 int rmhd_F(rmhd_ctx *ctx, double *cons, double *prims, double *L);
 
-/* Implicit stage (Sec. 2.2.1, Eq. 10): solve Q = R + a Psi(Q) per cell, a = a_ii dt, on every
+/* Implicit stage (Sec. 2.2.1, Eq. 10; resistive models only): solve Q = R + a Psi(Q) per cell, a = a_ii dt, on every
  * cell including ghosts (so Q's ghosts follow R's).  guess: optional array of conserved
  * variables whose source-carrying components start Newton (NULL = the plain guess R; two
  * fluid: Newton starts from whichever of guess and R has the smaller residual); a cell whose
@@ -164,6 +167,10 @@ int rmhd_implicit_stage(rmhd_ctx *ctx, double a, const double *R, const double *
 
 /* One IMEX step of size dt (Sec. 2.2.1, Eqs. 10-11) with the context's integrator: SSP2(222)
  * (Table 2, two implicit stages, gamma = 1 - 1/sqrt 2) or SSP3(332) (Table 3, three).
+ * RMHD_IDEAL contexts, which have no stiff source, take the explicit half of the same
+ * tableau (Heun's method, or the three-stage SSP Runge-Kutta method) with the divergence
+ * cleaning's damping explicit too; their recovery is the two-dimensional root-find of
+ * Sec. 2.1.3 (with a one-dimensional bracketed fallback unless c2p_primary_only).
  * cons (ghosts valid) is advanced in place; prims holds the primitives of cons on entry
  * (used as root-find starting points) and those of the new cons on exit, ghosts included.
  * Counters of the stage solves are accumulated into the context's statistics. */

@@ -53,13 +53,42 @@ template <>
 struct Model<1> {
     static constexpr int NC = 18, NP = 10, NX = 7;
 };
+template <>
+struct Model<2> {   // ideal: no implicit stage
+    static constexpr int NC = 9, NP = 5, NX = 0;
+};
+
+// Per-model recovery and fluxes (model 0 single fluid, 1 two fluid, 2 ideal).
+template <int M>
+__device__ __forceinline__ int cons2prim_m(const double *q, double *w, const Phys &P, int &it)
+{
+    if constexpr (M == 0) return sf_cons2prim(q, w, P, it);
+    else if constexpr (M == 1) return tf_cons2prim(q, w, P, it);
+    else return id_cons2prim(q, w, P, it);
+}
+template <int M>
+__device__ __forceinline__ void flux_source_m(const double *q, const double *w, double sig, const Phys &P, double *fx,
+                                              double *fy, double *src)
+{
+    if constexpr (M == 0) sf_flux_source(q, w, sig, P, fx, fy, src);
+    else if constexpr (M == 1) tf_flux_source(q, w, sig, P, fx, fy, src);
+    else id_flux_source(q, w, P, fx, fy, src);
+}
+template <int M>
+__device__ __forceinline__ void flux_z_m(const double *q, const double *w, double sig, const Phys &P, double *fz)
+{
+    if constexpr (M == 0) sf_flux_z(q, w, sig, P, fz);
+    else if constexpr (M == 1) tf_flux_z(q, w, P, fz);
+    else id_flux_z(q, w, P, fz);
+}
 
 // components that carry a source term
 __host__ __device__ constexpr bool has_source(int M, int v)
 {
-    return M == 0 ? (v == sf::EX || v == sf::EY || v == sf::EZ || v == sf::PSI || v == sf::PHI)
-                  : (v == tf::SBX || v == tf::SBY || v == tf::SBZ || v == tf::TAUB || v == tf::EX ||
-                     v == tf::EY || v == tf::EZ || v == tf::PSI || v == tf::PHI);
+    return M == 0   ? (v == sf::EX || v == sf::EY || v == sf::EZ || v == sf::PSI || v == sf::PHI)
+           : M == 1 ? (v == tf::SBX || v == tf::SBY || v == tf::SBZ || v == tf::TAUB || v == tf::EX ||
+                       v == tf::EY || v == tf::EZ || v == tf::PSI || v == tf::PHI)
+                    : v == id::PHI;
 }
 
 // Whether cell i of row r (= k * nyg + j) is an interior cell.
@@ -139,8 +168,10 @@ __global__ __launch_bounds__(256) void k_init(CPlanes prims, CPlanes EB, Planes 
             div += (EB.p[5][zp] - EB.p[5][zm]) * (0.5 * g.idz);
         }
         sf_prim2cons(w, eb, div, P, q);
-    } else {
+    } else if constexpr (M == 1) {
         tf_prim2cons(w, eb, P, q);
+    } else {
+        id_prim2cons(w, eb, P, q);
     }
 #pragma unroll
     for (int v = 0; v < NC; ++v) cons.p[v][idx] = q[v];
@@ -150,8 +181,9 @@ __global__ __launch_bounds__(256) void k_init(CPlanes prims, CPlanes EB, Planes 
 // primitive recovery
 // ---------------------------------------------------------------------------------------
 template <int M>
-__global__ __launch_bounds__(256) void k_c2p(CPlanes cons, Planes prims, int8_t *status, int32_t *iters, Geo g,
-                                             Phys P)
+// guess.p[0] == nullptr: the guesses are read from prims itself.
+__global__ __launch_bounds__(256) void k_c2p(CPlanes cons, CPlanes guess, Planes prims, int8_t *status,
+                                             int32_t *iters, Geo g, Phys P)
 {
     constexpr int NC = Model<M>::NC, NP = Model<M>::NP;
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -162,9 +194,9 @@ __global__ __launch_bounds__(256) void k_c2p(CPlanes cons, Planes prims, int8_t 
 #pragma unroll
     for (int v = 0; v < NC; ++v) q[v] = cons.p[v][idx];
 #pragma unroll
-    for (int v = 0; v < NP; ++v) w[v] = prims.p[v][idx];
+    for (int v = 0; v < NP; ++v) w[v] = guess.p[0] ? guess.p[v][idx] : prims.p[v][idx];
     int it = 0;
-    const int st = M == 0 ? sf_cons2prim(q, w, P, it) : tf_cons2prim(q, w, P, it);
+    const int st = cons2prim_m<M>(q, w, P, it);
 #pragma unroll
     for (int v = 0; v < NP; ++v) prims.p[v][idx] = w[v];
     if (status) status[idx] = (int8_t)st;
@@ -524,7 +556,7 @@ struct FluxArgs {
     Geo g;
     Phys P;
     int fuse_bc;          // also write the ghost images of output 0
-    // wnew.p[0] != nullptr (single fluid only): also recover the primitives of output 0
+    // wnew.p[0] != nullptr (single fluid and ideal): also recover the primitives of output 0
     // (guess: w) and write them, with their ghost images, to wnew, which must not alias w
     // (halo cells of other tiles still read w)
     Planes wnew;
@@ -540,8 +572,7 @@ __device__ __forceinline__ void flux_recover(const FluxArgs &A, const double *q,
 #pragma unroll
     for (int v = 0; v < NP; ++v) wn[v] = w[v];
     int it = 0;
-    if constexpr (M == 0) sf_cons2prim(q, wn, A.P, it);
-    else tf_cons2prim(q, wn, A.P, it);
+    cons2prim_m<M>(q, wn, A.P, it);
 #pragma unroll
     for (int v = 0; v < NP; ++v)
 #pragma unroll
@@ -600,8 +631,7 @@ __device__ __forceinline__ void flux_tile_lds(const FluxArgs &A, int bx, int by,
 #pragma unroll
     for (int v = 0; v < NP; ++v) w[v] = A.w.p[v][idx];
     const double sig = cell_sigma(A.P, idx);
-    if constexpr (M == 0) sf_flux_source(q, w, sig, A.P, fx, fy, src);
-    else tf_flux_source(q, w, sig, A.P, fx, fy, src);
+    flux_source_m<M>(q, w, sig, A.P, fx, fy, src);
 
     const bool interior = tx >= 2 && tx < BX - 2 && ii < g.nx &&
                           (NDIM == 1 || (ty >= 2 && ty < BY - 2 && jj < g.ny));
@@ -681,7 +711,7 @@ __device__ __forceinline__ void flux_tile_lds(const FluxArgs &A, int bx, int by,
         }
     }
     // the two-fluid step recovers in a separate kernel, so its flux pass does not carry the code
-    if constexpr (M == 0)
+    if constexpr (M != 1)
         if (A.wnew.p[0] && interior) flux_recover<M>(A, q, w, xi, yj, NDIM == 2 ? 3 : 1, zoff);
 }
 
@@ -715,8 +745,7 @@ __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by
 #pragma unroll
     for (int v = 0; v < NP; ++v) w[v] = A.w.p[v][idx];
     const double sig = cell_sigma(A.P, idx);
-    if constexpr (M == 0) sf_flux_source(q, w, sig, A.P, fx, fy, src);
-    else tf_flux_source(q, w, sig, A.P, fx, fy, src);
+    flux_source_m<M>(q, w, sig, A.P, fx, fy, src);
 
     const bool interior = tx >= 2 && tx < BX - 2 && ii < g.nx && ty >= 2 && ty < BY - 2 && jj < g.ny;
     const bool do_y = ty >= 1 && ty <= BY - 2 && tx >= 2 && tx <= BX - 3;
@@ -798,19 +827,19 @@ __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by
         // the next round rewrites sfp/sfm only after every thread has passed the barrier
         // above, and shp/shm only after the next round's first barrier
     }
-    if constexpr (M == 0)
+    if constexpr (M != 1)
         if (A.wnew.p[0] && interior) flux_recover<M>(A, q, w, xi, yj, 3, zoff);
 }
 
-// One tile of the flux pass: single-fluid 2-D tiles with 64-wide rows use the wavefront-row
-// form, everything else the LDS form (measured: for the two-fluid model the row form's
-// extra live registers cost more than its saved LDS traffic).
+// One tile of the flux pass: single-fluid and ideal 2-D tiles with 64-wide rows use the
+// wavefront-row form, everything else the LDS form (measured: for the two-fluid model the
+// row form's extra live registers cost more than its saved LDS traffic).
 // NO: outputs used (o[0..NO-1]), fixed at compile time so unused ones cost no registers.
 template <int M, int NDIM, int BX, int BY, int NO>
 __device__ __forceinline__ void flux_tile(const FluxArgs &A, int bx, int by, long zoff = 0)
 {
     static_assert(NO >= 1 && NO <= FLUX_MAXOUT, "outputs");
-    if constexpr (M == 0 && NDIM == 2 && BX == 64) flux_tile_rows<M, BY, NO>(A, bx, by, zoff);
+    if constexpr (M != 1 && NDIM == 2 && BX == 64) flux_tile_rows<M, BY, NO>(A, bx, by, zoff);
     else flux_tile_lds<M, NDIM, BX, BY, NO>(A, bx, by, zoff);
 }
 
@@ -881,8 +910,7 @@ __global__ __launch_bounds__(1024) void k_flux_z(FluxArgs A)
     for (int v = 0; v < NC; ++v) q[v] = A.q.p[v][idx];
 #pragma unroll
     for (int v = 0; v < NP; ++v) w[v] = A.w.p[v][idx];
-    if constexpr (M == 0) sf_flux_z(q, w, cell_sigma(A.P, idx), A.P, fz);
-    else tf_flux_z(q, w, A.P, fz);
+    flux_z_m<M>(q, w, cell_sigma(A.P, idx), A.P, fz);
 
     const bool interior = ii < g.nx && tz >= 2 && tz < BZ - 2 && kk < g.nz;
     const bool do_z = tz >= 1 && tz <= BZ - 2;
@@ -958,8 +986,8 @@ static inline void layout_from(const rmhd_params *p, rmhd_layout *out)
     out->pitch = (out->nxg + 7) / 8 * 8;
     out->slab = out->pitch * out->nyg;
     out->plane = out->slab * out->nzg;
-    out->ncons = p->model == RMHD_SINGLE_FLUID ? 14 : 18;
-    out->nprim = p->model == RMHD_SINGLE_FLUID ? 5 : 10;
+    out->ncons = p->model == RMHD_SINGLE_FLUID ? 14 : p->model == RMHD_TWO_FLUID ? 18 : 9;
+    out->nprim = p->model == RMHD_TWO_FLUID ? 10 : 5;
 }
 
 static inline Geo geo_from(const rmhd_params *p, const rmhd_layout &L)

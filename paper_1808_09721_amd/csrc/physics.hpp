@@ -21,6 +21,10 @@ namespace tf {
 enum { D, SX, SY, SZ, TAU, DB, SBX, SBY, SBZ, TAUB, BX, BY, BZ, EX, EY, EZ, PSI, PHI, NC };
 constexpr int NP = 10;
 }  // namespace tf
+namespace id {   // ideal RMHD (E = -v x B), the explicit comparison model
+enum { D, SX, SY, SZ, TAU, BX, BY, BZ, PHI, NC };
+constexpr int NP = 5;
+}  // namespace id
 
 enum CellStatus { CELL_OK = 0, CELL_C2P_NOCONV = 1, CELL_C2P_UNPHYS = 2, CELL_NEWTON_NOCONV = 3,
                   CELL_LINESEARCH = 4,
@@ -595,6 +599,196 @@ __device__ inline void tf_flux_z(const double *q, const double *w, const Phys &P
     fz[tf::BX] = -E.y; fz[tf::BY] = E.x; fz[tf::BZ] = q[tf::PHI];
     fz[tf::EX] = B.y; fz[tf::EY] = -B.x; fz[tf::EZ] = q[tf::PSI];
     fz[tf::PSI] = E.z; fz[tf::PHI] = B.z;
+}
+
+// ---------------------------------------------------------------------------------------
+// Ideal RMHD (Sec. 2.1 lists it; recovery by a two-dimensional root-find, Sec. 2.1.3): the
+// conserved state (D, S, tau, B, phi) of a perfectly conducting fluid, E = -v x B, with the
+// resistive models' cleaning of B (flux of B^i gains phi along i; d_t phi + div B = -kappa phi).
+// ---------------------------------------------------------------------------------------
+__device__ inline void id_prim2cons(const double *w, const double *EB, const Phys &P, double *q)
+{
+    const vec3<double> v = v3(w[1], w[2], w[3]), B = v3(EB[0], EB[1], EB[2]);
+    const double W = frsqrt(1.0 - dot(v, v));
+    const double Z = (w[0] + P.hk * w[4]) * (W * W);   // rho h W^2
+    const double vB = dot(v, B), B2 = dot(B, B);
+    q[id::D] = w[0] * W;
+    q[id::SX] = (Z + B2) * v.x - vB * B.x;
+    q[id::SY] = (Z + B2) * v.y - vB * B.y;
+    q[id::SZ] = (Z + B2) * v.z - vB * B.z;
+    // E^2 = v^2 B^2 - (v.B)^2 for E = -v x B
+    q[id::TAU] = Z - w[4] + 0.5 * (B2 + dot(v, v) * B2 - vB * vB) - q[id::D];
+    q[id::BX] = B.x; q[id::BY] = B.y; q[id::BZ] = B.z;
+    q[id::PHI] = 0.0;
+}
+
+// The two equations of the recovery in the unknowns (Z = rho h W^2, y = v^2):
+//   F1 = y (Z + B^2)^2 - (S.B)^2 (B^2 + 2 Z) / Z^2 - S^2                 (momentum)
+//   F2 = Z + B^2 - p - B^2 (1 - y) / 2 - (S.B)^2 / (2 Z^2) - (tau + D)    (energy)
+// with p = (Gamma-1)/Gamma (Z (1 - y) - D sqrt(1 - y)) for the Gamma law.
+struct IdealSys {
+    double D, S2, SB2, B2, Et, gk;
+};
+__device__ __forceinline__ void id_residual(const IdealSys &s, double Z, double y, double &F1, double &F2,
+                                            double J[4])
+{
+    const double iZ = frcp(Z), u = 1.0 - y, su = sqrt(u);
+    const double ZB = Z + s.B2;
+    const double p = s.gk * (Z * u - s.D * su);
+    F1 = y * ZB * ZB - s.SB2 * (s.B2 + 2.0 * Z) * iZ * iZ - s.S2;
+    F2 = ZB - p - 0.5 * s.B2 * u - 0.5 * s.SB2 * iZ * iZ - s.Et;
+    J[0] = 2.0 * y * ZB + 2.0 * s.SB2 * ZB * iZ * iZ * iZ;   // dF1/dZ
+    J[1] = ZB * ZB;                                          // dF1/dy
+    J[2] = 1.0 - s.gk * u + s.SB2 * iZ * iZ * iZ;            // dF2/dZ
+    J[3] = s.gk * (Z - 0.5 * s.D * frcp(su)) + 0.5 * s.B2;   // dF2/dy
+}
+
+// Second route, where the two-dimensional iteration does not converge: y from F1 = 0 in
+// closed form, y(Z) = (S^2 Z^2 + (S.B)^2 (2 Z + B^2)) / (Z^2 (Z + B^2)^2), and F2(Z, y(Z))
+// bracketed on Z (y >= 1 or F2 < 0 below the root, F2 > 0 above) and bisected to rounding.
+__device__ inline bool id_root_1d(const IdealSys &s, double &Z, double &y, int &iters)
+{
+    auto eval = [&](double z, double &yy, double &f) -> bool {
+        const double iz = frcp(z), zb = z + s.B2;
+        yy = (s.S2 * z * z + s.SB2 * (2.0 * z + s.B2)) * iz * iz * frcp(zb * zb);
+        if (!(yy < 1.0)) return false;
+        const double u = 1.0 - yy;
+        f = zb - s.gk * (z * u - s.D * sqrt(u)) - 0.5 * s.B2 * u - 0.5 * s.SB2 * iz * iz - s.Et;
+        return true;
+    };
+    double lo = 0.0, hi = 2.0 * s.Et + 1.0, yy = 0.0, f = 0.0;
+    int k = 0;
+    while (k < 64 && !(eval(hi, yy, f) && f > 0.0)) {
+        lo = hi;
+        hi *= 2.0;
+        ++k;
+    }
+    if (k == 64) return false;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (!(mid > lo && mid < hi)) break;
+        if (eval(mid, yy, f) && f > 0.0) hi = mid; else lo = mid;
+        ++iters;
+    }
+    Z = hi;
+    return eval(Z, y, f);
+}
+
+// 9 conserved -> (rho, v, p).  Newton on (Z, y) from the guess w (rho h W^2 and v^2 of w;
+// a start outside Z > 0, 0 <= y < 1 is replaced by Z = tau + D, y = 0), steps halved until
+// they stay inside; stop at |F1| <= tol max(1, S^2 + B^4) and |F2| <= tol max(1, tau + D) and
+// take one more step.  Where it does not converge (unless P.c2p_fallback is 0) the
+// one-dimensional route takes over.
+__device__ inline int id_cons2prim(const double *q, double *w, const Phys &P, int &iters)
+{
+    const vec3<double> S = v3(q[id::SX], q[id::SY], q[id::SZ]), B = v3(q[id::BX], q[id::BY], q[id::BZ]);
+    IdealSys s;
+    s.D = q[id::D];
+    s.S2 = dot(S, S);
+    const double SB = dot(S, B);
+    s.SB2 = SB * SB;
+    s.B2 = dot(B, B);
+    s.Et = q[id::TAU] + q[id::D];
+    s.gk = P.gk;
+    iters = 0;
+    if (!(s.D > 0.0) || !(s.Et > 0.0) || !isfinite(s.S2 + s.B2)) return CELL_C2P_UNPHYS;
+    double y = w[1] * w[1] + w[2] * w[2] + w[3] * w[3];
+    double Z = (w[0] + P.hk * w[4]) * frcp(1.0 - y);
+    if (!(Z > 0.0) || !(y >= 0.0 && y < 1.0) || !(w[0] > 0.0) || !(w[4] > 0.0)) {
+        Z = s.Et;
+        y = 0.0;
+    }
+    const double t1 = P.c2p_tol * fmax(1.0, s.S2 + s.B2 * s.B2), t2 = P.c2p_tol * fmax(1.0, s.Et);
+    int st = CELL_C2P_NOCONV;
+    for (int it = 1; it <= P.max_c2p; ++it) {
+        double F1, F2, J[4];
+        id_residual(s, Z, y, F1, F2, J);
+        const double idet = frcp(J[0] * J[3] - J[1] * J[2]);
+        const double dZ = -(J[3] * F1 - J[1] * F2) * idet, dy = -(J[0] * F2 - J[2] * F1) * idet;
+        const bool done = fabs(F1) <= t1 && fabs(F2) <= t2;
+        double lam = 1.0;
+        for (int h = 0; h < 30 && !(Z + lam * dZ > 0.0 && y + lam * dy >= 0.0 && y + lam * dy < 1.0); ++h)
+            lam *= 0.5;
+        iters = it;
+        if (!(Z + lam * dZ > 0.0 && y + lam * dy >= 0.0 && y + lam * dy < 1.0)) break;
+        Z += lam * dZ;
+        y += lam * dy;
+        if (done) {
+            st = CELL_OK;
+            break;
+        }
+    }
+    if (st != CELL_OK && P.c2p_fallback) {
+        if (id_root_1d(s, Z, y, iters)) st = CELL_OK;
+    }
+    if (st != CELL_OK) return st;
+    const double u = 1.0 - y, iZB = frcp(Z + s.B2), sZ = SB * frcp(Z);
+    w[1] = (S.x + sZ * B.x) * iZB;
+    w[2] = (S.y + sZ * B.y) * iZB;
+    w[3] = (S.z + sZ * B.z) * iZB;
+    // rho and p from the velocity actually returned, so that (rho, v, p) are consistent
+    const double uw = 1.0 - (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]);
+    w[0] = s.D * sqrt(uw);
+    w[4] = P.gk * (Z * uw - w[0]);
+    (void)u;
+    if (!(w[0] > 0.0) || !(w[4] > 0.0) || !(uw > 0.0)) return CELL_C2P_UNPHYS;
+    return CELL_OK;
+}
+
+// Flux of one cell along direction K (0, 1, 2) from (q, w), and the cleaning source.
+template <int K>
+__device__ __forceinline__ void id_flux_dir(const double *q, const double *w, const vec3<double> &v, double W,
+                                           double pstar, const double *b, const vec3<double> &B, double *f)
+{
+    const double vk = K == 0 ? v.x : K == 1 ? v.y : v.z;
+    const double Bk = K == 0 ? B.x : K == 1 ? B.y : B.z;
+    const double iW = frcp(W);
+    f[id::D] = q[id::D] * vk;
+    f[id::SX] = q[id::SX] * vk + (K == 0 ? pstar : 0.0) - b[0] * Bk * iW;
+    f[id::SY] = q[id::SY] * vk + (K == 1 ? pstar : 0.0) - b[1] * Bk * iW;
+    f[id::SZ] = q[id::SZ] * vk + (K == 2 ? pstar : 0.0) - b[2] * Bk * iW;
+    f[id::TAU] = q[id::SX + K] - q[id::D] * vk;
+    f[id::BX] = vk * B.x - v.x * Bk + (K == 0 ? q[id::PHI] : 0.0);
+    f[id::BY] = vk * B.y - v.y * Bk + (K == 1 ? q[id::PHI] : 0.0);
+    f[id::BZ] = vk * B.z - v.z * Bk + (K == 2 ? q[id::PHI] : 0.0);
+    f[id::PHI] = Bk;
+    (void)w;
+}
+
+// Comoving-field quantities of the fluxes: b^i = B^i / W + b^0 v^i, b^0 = W (v.B),
+// p* = p + b^2 / 2, b^2 = B^2 / W^2 + (v.B)^2.
+__device__ __forceinline__ void id_fields(const double *q, const double *w, vec3<double> &v, vec3<double> &B,
+                                         double &W, double &pstar, double b[3])
+{
+    v = v3(w[1], w[2], w[3]);
+    B = v3(q[id::BX], q[id::BY], q[id::BZ]);
+    W = frsqrt(1.0 - dot(v, v));
+    const double vB = dot(v, B), iW = frcp(W), b0 = W * vB;
+    b[0] = B.x * iW + b0 * v.x;
+    b[1] = B.y * iW + b0 * v.y;
+    b[2] = B.z * iW + b0 * v.z;
+    pstar = w[4] + 0.5 * (dot(B, B) * (iW * iW) + vB * vB);
+}
+
+__device__ inline void id_flux_source(const double *q, const double *w, const Phys &P, double *fx, double *fy,
+                                      double *src)
+{
+    vec3<double> v, B;
+    double W, pstar, b[3];
+    id_fields(q, w, v, B, W, pstar, b);
+    id_flux_dir<0>(q, w, v, W, pstar, b, B, fx);
+    id_flux_dir<1>(q, w, v, W, pstar, b, B, fy);
+    for (int k = 0; k < id::NC; ++k) src[k] = 0.0;
+    src[id::PHI] = -P.kappa * q[id::PHI];
+}
+
+__device__ inline void id_flux_z(const double *q, const double *w, const Phys &P, double *fz)
+{
+    vec3<double> v, B;
+    double W, pstar, b[3];
+    id_fields(q, w, v, B, W, pstar, b);
+    id_flux_dir<2>(q, w, v, W, pstar, b, B, fz);
+    (void)P;
 }
 
 }  // namespace rmhd

@@ -77,7 +77,8 @@ static int hip_check(rmhd_ctx *c, hipError_t e, const char *what)
 static int check_params_impl(const rmhd_params *p, rmhd_ctx *c)
 {
     if (!p) return fail(c, RMHD_EINVAL, "params is NULL");
-    if (p->model != RMHD_SINGLE_FLUID && p->model != RMHD_TWO_FLUID) return fail(c, RMHD_EINVAL, "model must be 0 or 1");
+    if (p->model != RMHD_SINGLE_FLUID && p->model != RMHD_TWO_FLUID && p->model != RMHD_IDEAL)
+        return fail(c, RMHD_EINVAL, "model must be 0, 1 or 2");
     if (p->ndim < 1 || p->ndim > 3) return fail(c, RMHD_EINVAL, "ndim must be 1, 2 or 3");
     if (p->nx < 4 || (p->ndim >= 2 && p->ny < 4) || (p->ndim == 1 && p->ny != 1))
         return fail(c, RMHD_EINVAL, "need nx >= 4 (and ny >= 4 in 2-D and 3-D, ny == 1 in 1-D)");
@@ -160,7 +161,7 @@ extern "C" int rmhd_create(const rmhd_params *p, void *stream, rmhd_ctx **out)
     c->geo = geo_from(p, L);
     c->phys = phys_from(p);
     const size_t pl = (size_t)L.plane * sizeof(double);
-    const int nsrc = p->model == RMHD_SINGLE_FLUID ? 5 : 9;
+    const int nsrc = p->model == RMHD_SINGLE_FLUID ? 5 : p->model == RMHD_TWO_FLUID ? 9 : 1;
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipMalloc((void **)&c->q1src, pl * nsrc);
     if (e == hipSuccess) e = hipMalloc((void **)&c->w1, pl * L.nprim);
@@ -170,7 +171,7 @@ extern "C" int rmhd_create(const rmhd_params *p, void *stream, rmhd_ctx **out)
     if (e == hipSuccess && p->integrator == RMHD_SSP3_332) e = hipMalloc((void **)&c->w2, pl * L.nprim);
     if (e == hipSuccess) e = hipMalloc((void **)&c->status, (size_t)L.plane);
     if (e == hipSuccess) e = hipMalloc((void **)&c->iters, (size_t)L.plane * sizeof(int32_t));
-    const int nx_unk = p->model == RMHD_SINGLE_FLUID ? 3 : 7;
+    const int nx_unk = p->model == RMHD_TWO_FLUID ? 7 : 3;
     // stage queue by default for the two-fluid stage only: its 7-unknown Newton step is
     // costly enough to repay the second launch; the single-fluid one is not
     c->cap = p->model == RMHD_TWO_FLUID ? 1 : 1 << 30;
@@ -324,7 +325,8 @@ static int launch_flux(rmhd_ctx *c, const FluxArgs &A)
         B.fuse_bc = 0;
     }
     if (c->prm.model == RMHD_SINGLE_FLUID) launch_flux_m<0>(c, B);
-    else launch_flux_m<1>(c, B);
+    else if (c->prm.model == RMHD_TWO_FLUID) launch_flux_m<1>(c, B);
+    else launch_flux_m<2>(c, B);
     int rc = hip_check(c, hipGetLastError(), "k_flux launch");
     if (!rc && c->prm.ndim == 3 && A.fuse_bc) {
         hipLaunchKernelGGL(k_bc, cells_grid(c), dim3(256), 0, c->stream, A.o[0].out, (int)c->lay.ncons, c->geo);
@@ -337,28 +339,40 @@ extern "C" int rmhd_init_state(rmhd_ctx *c, const double *prims, const double *E
 {
     if (!c || !prims || !EB || !cons) return fail(c, RMHD_EINVAL, "rmhd_init_state: NULL argument");
     const rmhd_layout &L = c->lay;
+    const CPlanes P = cplanes_of(prims, L, L.nprim), F = cplanes_of(EB, L, 6);
+    const Planes Q = planes_of(cons, L, L.ncons);
     if (c->prm.model == RMHD_SINGLE_FLUID)
-        hipLaunchKernelGGL(k_init<0>, cells_grid(c), dim3(256), 0, c->stream, cplanes_of(prims, L, L.nprim),
-                           cplanes_of(EB, L, 6), planes_of(cons, L, L.ncons), c->geo, c->phys);
+        hipLaunchKernelGGL(k_init<0>, cells_grid(c), dim3(256), 0, c->stream, P, F, Q, c->geo, c->phys);
+    else if (c->prm.model == RMHD_TWO_FLUID)
+        hipLaunchKernelGGL(k_init<1>, cells_grid(c), dim3(256), 0, c->stream, P, F, Q, c->geo, c->phys);
     else
-        hipLaunchKernelGGL(k_init<1>, cells_grid(c), dim3(256), 0, c->stream, cplanes_of(prims, L, L.nprim),
-                           cplanes_of(EB, L, 6), planes_of(cons, L, L.ncons), c->geo, c->phys);
+        hipLaunchKernelGGL(k_init<2>, cells_grid(c), dim3(256), 0, c->stream, P, F, Q, c->geo, c->phys);
     int rc = hip_check(c, hipGetLastError(), "k_init launch");
     if (rc) return rc;
     return launch_bc(c, cons, L.ncons);
 }
 
+// Recovery on every cell; guess == nullptr: the guesses are prims' own values.
+static int launch_c2p(rmhd_ctx *c, const double *cons, const double *guess, double *prims, int8_t *status,
+                      int32_t *iters)
+{
+    const rmhd_layout &L = c->lay;
+    const CPlanes Q = cplanes_of(cons, L, L.ncons);
+    const CPlanes G = guess ? cplanes_of(guess, L, L.nprim) : CPlanes{};
+    const Planes W = planes_of(prims, L, L.nprim);
+    if (c->prm.model == RMHD_SINGLE_FLUID)
+        hipLaunchKernelGGL(k_c2p<0>, cells_grid(c), dim3(256), 0, c->stream, Q, G, W, status, iters, c->geo, c->phys);
+    else if (c->prm.model == RMHD_TWO_FLUID)
+        hipLaunchKernelGGL(k_c2p<1>, cells_grid(c), dim3(256), 0, c->stream, Q, G, W, status, iters, c->geo, c->phys);
+    else
+        hipLaunchKernelGGL(k_c2p<2>, cells_grid(c), dim3(256), 0, c->stream, Q, G, W, status, iters, c->geo, c->phys);
+    return hip_check(c, hipGetLastError(), "k_c2p launch");
+}
+
 extern "C" int rmhd_cons2prim(rmhd_ctx *c, const double *cons, double *prims, int8_t *status, int32_t *iters)
 {
     if (!c || !cons || !prims) return fail(c, RMHD_EINVAL, "rmhd_cons2prim: NULL argument");
-    const rmhd_layout &L = c->lay;
-    if (c->prm.model == RMHD_SINGLE_FLUID)
-        hipLaunchKernelGGL(k_c2p<0>, cells_grid(c), dim3(256), 0, c->stream, cplanes_of(cons, L, L.ncons),
-                           planes_of(prims, L, L.nprim), status, iters, c->geo, c->phys);
-    else
-        hipLaunchKernelGGL(k_c2p<1>, cells_grid(c), dim3(256), 0, c->stream, cplanes_of(cons, L, L.ncons),
-                           planes_of(prims, L, L.nprim), status, iters, c->geo, c->phys);
-    return hip_check(c, hipGetLastError(), "k_c2p launch");
+    return launch_c2p(c, cons, nullptr, prims, status, iters);
 }
 
 extern "C" int rmhd_F(rmhd_ctx *c, double *cons, double *prims, double *Lout)
@@ -382,6 +396,7 @@ extern "C" int rmhd_implicit_stage(rmhd_ctx *c, double a, const double *R, const
                                    double *prims, int8_t *status, int32_t *iters)
 {
     if (!c || !R || !Q || !prims) return fail(c, RMHD_EINVAL, "rmhd_implicit_stage: NULL argument");
+    if (c->prm.model == RMHD_IDEAL) return fail(c, RMHD_EINVAL, "rmhd_implicit_stage: the ideal model has no implicit stage");
     if (!(a >= 0.0)) return fail(c, RMHD_EINVAL, "rmhd_implicit_stage: a must be >= 0");
     const rmhd_layout &L = c->lay;
     StageArgs A{};
@@ -466,8 +481,94 @@ static FluxOut flux_out(const double *base, double *out, const rmhd_layout &L, d
 //              flux 3:  q^{n+1} = ACC + 2 dt/3 (L3 + Psi3)
 // Every flux pass writes the ghost images of its first output; the last one also recovers the
 // primitives (single fluid; two fluid: a separate recovery kernel), from the last stage's.
+static int enqueue_explicit(rmhd_ctx *c, double dt, double *cons, double *prims);
+
+// Wait for a timed step's last event and add its event pairs to the per-kind totals
+// (0 stage, 1 flux pass, 2 recovery).
+static int record_timing(rmhd_ctx *c, int nev, const int *kinds)
+{
+    int rc = hip_check(c, hipEventSynchronize(c->ev[nev - 1]), "timing sync");
+    if (rc) return rc;
+    for (int k = 0; 2 * k < nev; ++k) {
+        float ms = 0.0f;
+        hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]);
+        if (kinds[k] == 0) { c->times.stage_ms += ms; c->times.stage_launches += 1; }
+        if (kinds[k] == 1) { c->times.flux_ms += ms; c->times.flux_launches += 1; }
+        if (kinds[k] == 2) { c->times.c2p_ms += ms; c->times.c2p_launches += 1; }
+    }
+    c->times.steps += 1;
+    return RMHD_OK;
+}
+
+// The ideal model's step: the explicit halves of the tableaux, with the cleaning source
+// (the model's only one) explicit as well, K = L + Psi:
+//   SSP2(222)  flux 1: R2 = q^n + dt K1,  ACC = q^n + dt/2 K1
+//              flux 2: q^{n+1} = ACC + dt/2 K(R2)
+//   SSP3(332)  flux 1: R2 = q^n + dt K1,  R3 = q^n + dt/4 K1,  ACC = q^n + dt/6 K1
+//              flux 2: R3 += dt/4 K(R2),  ACC += dt/6 K(R2)
+//              flux 3: q^{n+1} = ACC + 2 dt/3 K(R3)
+// Each pass writes the ghost images of its first output and recovers its primitives
+// (in the same kernel on 1-D and 2-D grids, in the recovery kernel on 3-D ones), each
+// recovery starting from the primitives of the state the pass read.
+static int enqueue_explicit(rmhd_ctx *c, double dt, double *cons, double *prims)
+{
+    const rmhd_layout &L = c->lay;
+    const bool ssp3 = c->prm.integrator == RMHD_SSP3_332;
+    const bool fused = c->prm.ndim < 3;
+    int nev = 0, kinds[7];
+    auto begin = [&]() {
+        if (c->timing) hipEventRecord(c->ev[nev], c->stream);
+    };
+    auto end = [&](int kind) {
+        if (c->timing) hipEventRecord(c->ev[nev + 1], c->stream);
+        kinds[nev / 2] = kind;
+        nev += 2;
+    };
+    // one pass reading (q, w), writing outputs with the recovered primitives of output 0 in wout
+    auto pass = [&](const double *q, const double *w, double *out0, double *wout, const FluxOut *o, int n) {
+        FluxArgs F{};
+        F.q = cplanes_of(q, L, L.ncons);
+        F.w = cplanes_of(w, L, L.nprim);
+        F.g = c->geo;
+        F.P = c->phys;
+        F.fuse_bc = 1;
+        for (int k = 0; k < n; ++k) F.o[k] = o[k];
+        if (fused) F.wnew = planes_of(wout, L, L.nprim);
+        begin();
+        int rc = launch_flux(c, F);
+        end(1);
+        if (rc || fused) return rc;
+        begin();
+        rc = launch_c2p(c, out0, w, wout, nullptr, nullptr);
+        end(2);
+        return rc;
+    };
+    int rc;
+    if (!ssp3) {
+        const FluxOut o1[2] = {flux_out(cons, c->r2, L, dt, dt), flux_out(cons, c->acc, L, 0.5 * dt, 0.5 * dt)};
+        rc = pass(cons, prims, c->r2, c->w1, o1, 2);
+        if (rc) return rc;
+        const FluxOut o2[1] = {flux_out(c->acc, cons, L, 0.5 * dt, 0.5 * dt)};
+        rc = pass(c->r2, c->w1, cons, prims, o2, 1);
+    } else {
+        const FluxOut o1[3] = {flux_out(cons, c->r2, L, dt, dt), flux_out(cons, c->r3, L, 0.25 * dt, 0.25 * dt),
+                               flux_out(cons, c->acc, L, dt / 6.0, dt / 6.0)};
+        rc = pass(cons, prims, c->r2, c->w1, o1, 3);
+        if (rc) return rc;
+        const FluxOut o2[2] = {flux_out(c->r3, c->r3, L, 0.25 * dt, 0.25 * dt),
+                               flux_out(c->acc, c->acc, L, dt / 6.0, dt / 6.0)};
+        rc = pass(c->r2, c->w1, c->r3, c->w2, o2, 2);
+        if (rc) return rc;
+        const FluxOut o3[1] = {flux_out(c->acc, cons, L, 2.0 * dt / 3.0, 2.0 * dt / 3.0)};
+        rc = pass(c->r3, c->w2, cons, prims, o3, 1);
+    }
+    if (rc || !c->timing) return rc;
+    return record_timing(c, nev, kinds);
+}
+
 static int enqueue_imex(rmhd_ctx *c, double dt, double *cons, double *prims)
 {
+    if (c->prm.model == RMHD_IDEAL) return enqueue_explicit(c, dt, cons, prims);
     const rmhd_layout &L = c->lay;
     const double gm = SSP2_GAMMA;
     const int M = c->prm.model;
@@ -586,17 +687,7 @@ static int enqueue_imex(rmhd_ctx *c, double dt, double *cons, double *prims)
         if (rc) return rc;
     }
     if (!c->timing) return RMHD_OK;
-    rc = hip_check(c, hipEventSynchronize(c->ev[nev - 1]), "timing sync");
-    if (rc) return rc;
-    for (int k = 0; 2 * k < nev; ++k) {
-        float ms = 0.0f;
-        hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]);
-        if (kinds[k] == 0) { c->times.stage_ms += ms; c->times.stage_launches += 1; }
-        if (kinds[k] == 1) { c->times.flux_ms += ms; c->times.flux_launches += 1; }
-        if (kinds[k] == 2) { c->times.c2p_ms += ms; c->times.c2p_launches += 1; }
-    }
-    c->times.steps += 1;
-    return RMHD_OK;
+    return record_timing(c, nev, kinds);
 }
 
 extern "C" int rmhd_set_timing(rmhd_ctx *c, int enable)

@@ -14,7 +14,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librmhd.so")
 
-SINGLE_FLUID, TWO_FLUID = 0, 1
+SINGLE_FLUID, TWO_FLUID, IDEAL = 0, 1, 2
 BC_OUTFLOW, BC_PERIODIC = 0, 1
 CELL_STATUS = {0: "ok", 1: "c2p_noconv", 2: "c2p_unphysical", 3: "newton_noconv", 4: "linesearch"}
 
