@@ -306,6 +306,50 @@ def grid3d_measure(steps: int, warmup: int) -> dict:
     return out
 
 
+def ideal_measure(steps: int, warmup: int, resistive_ms: float) -> dict:
+    """The ideal model (explicit steps) on the headline Kelvin-Helmholtz grid with both
+    tableaux, and on the 3-D grid, against the resistive single-fluid IMEX step on the same
+    2-D grid (the paper reports resistive IMEX runs often taking over ten times longer than
+    ideal explicit ones)."""
+    import torch
+
+    from paper_1808_09721_amd import rmhd as R
+    from paper_1808_09721_amd import workloads as WL
+    out = {}
+    for name, wl, integ in (("kelvin_helmholtz_2d 256x512 ideal, SSP2 explicit", WL.kelvin_helmholtz_2d(), R.SSP2_222),
+                            ("kelvin_helmholtz_2d 256x512 ideal, SSP3 explicit", WL.kelvin_helmholtz_2d(), R.SSP3_332),
+                            ("kelvin_helmholtz_3d 128x256x128 ideal, SSP2 explicit", WL.kelvin_helmholtz_3d(),
+                             R.SSP2_222)):
+        wl = WL.as_ideal(wl)
+        s = R.Solver.for_workload(wl, integrator=integ)
+        c, w = s.initial_state(wl.prims, wl.EB)
+        dt = s.dt()
+        n = steps if wl.cells < 500000 else max(3, steps // 20)
+        for _ in range(warmup):
+            s.step(dt, c, w)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(n):
+            s.step(dt, c, w)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / n
+        R.rmhd_set_timing(s.ctx, True)
+        R.rmhd_get_timing(s.ctx, reset=True)
+        for _ in range(3):
+            s.step(dt, c, w)
+        tm = R.rmhd_get_timing(s.ctx, reset=True)
+        R.rmhd_set_timing(s.ctx, False)
+        out[name] = {"cells": wl.cells, "steps": n, "ms_per_step": ms, "value": wl.cells / (ms / 1e3),
+                     "unit": "cell-updates/s", "flux_ms_per_pass": tm["flux_ms"] / max(1, tm["flux_launches"]),
+                     "c2p_ms_per_launch": tm["c2p_ms"] / tm["c2p_launches"] if tm["c2p_launches"] else None}
+        s.close()
+    out["resistive_over_ideal_step_time_2d_ssp2"] = resistive_ms / out[
+        "kelvin_helmholtz_2d 256x512 ideal, SSP2 explicit"]["ms_per_step"]
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -317,6 +361,7 @@ def main() -> int:
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-ssp3", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
+    ap.add_argument("--no-ideal", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (traffic calibration)")
     args = ap.parse_args()
@@ -442,6 +487,8 @@ def main() -> int:
         out["ssp3"] = ssp3_measure(max(10, args.steps // 2), args.warmup)
     if not args.no_3d:
         out["grid3d"] = grid3d_measure(max(3, args.steps // 20), args.warmup)
+    if not args.no_ideal:
+        out["ideal"] = ideal_measure(max(10, args.steps // 2), args.warmup, ms / args.steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
         out["cpu_baseline"]["gpu_speedup"] = value / out["cpu_baseline"]["value"]
