@@ -660,6 +660,10 @@ __device__ __forceinline__ void flux_tile_lds(const FluxArgs &A, int bx, int by,
 
 #pragma unroll
     for (int v = 0; v < NC; ++v) {
+        // base terms first, so that their loads overlap the reconstruction
+        double bv[NO];
+#pragma unroll
+        for (int k = 0; k < NO; ++k) bv[k] = (interior && A.o[k].base.p[0]) ? A.o[k].base.p[v][idx] : 0.0;
         sfp[0][ty][tx] = 0.5 * (fx[v] + q[v]);
         sfm[0][ty][tx] = 0.5 * (fx[v] - q[v]);
         if constexpr (NDIM == 2) {
@@ -694,8 +698,7 @@ __device__ __forceinline__ void flux_tile_lds(const FluxArgs &A, int bx, int by,
 #pragma unroll
             for (int k = 0; k < NO; ++k) {
                 const FluxOut &F = A.o[k];
-                const double b = F.base.p[0] ? F.base.p[v][idx] : 0.0;
-                const double o = b + F.cL * L + F.cS * S;
+                const double o = bv[k] + F.cL * L + F.cS * S;
                 if (k == 0) {
                     o0 = o;
 #pragma unroll
@@ -713,6 +716,27 @@ __device__ __forceinline__ void flux_tile_lds(const FluxArgs &A, int bx, int by,
     // the two-fluid step recovers in a separate kernel, so its flux pass does not carry the code
     if constexpr (M != 1)
         if (A.wnew.p[0] && interior) flux_recover<M>(A, q, w, xi, yj, NDIM == 2 ? 3 : 1, zoff);
+}
+
+// Row-form flux components per model (single fluid and ideal; the two-fluid model uses the
+// LDS form).
+template <int M>
+__device__ __forceinline__ auto row_quantities(const double *q, const double *w, double sig, const Phys &P)
+{
+    if constexpr (M == 0) return sf_row(q, w, sig, P);
+    else return id_row(q, w);
+}
+template <int M, int K, typename T>
+__device__ __forceinline__ double row_flux(int c, const double *q, const T &I)
+{
+    if constexpr (M == 0) return sf_row_flux<K>(c, q, I);
+    else return id_row_flux<K>(c, q, I);
+}
+template <int M, typename T>
+__device__ __forceinline__ double row_source(int c, const double *q, const T &I, const Phys &P)
+{
+    if constexpr (M == 0) return sf_row_src(c, q, I, P);
+    else return c == id::PHI ? -P.kappa * q[id::PHI] : 0.0;
 }
 
 // Values of the lanes to the left and right in the same wavefront (a lane at the edge gets
@@ -739,13 +763,13 @@ __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by
     const int j = min(max(jj + 2, 0), g.nyg - 1);
     const long idx = zoff + (long)j * g.pitch + i;
 
-    double q[NC], w[NP], fx[NC], fy[NC], src[NC];
+    double q[NC], w[NP];
 #pragma unroll
     for (int v = 0; v < NC; ++v) q[v] = A.q.p[v][idx];
 #pragma unroll
     for (int v = 0; v < NP; ++v) w[v] = A.w.p[v][idx];
-    const double sig = cell_sigma(A.P, idx);
-    flux_source_m<M>(q, w, sig, A.P, fx, fy, src);
+    // quantities shared by the flux components; each round forms only its own components
+    const auto I = row_quantities<M>(q, w, cell_sigma(A.P, idx), A.P);
 
     const bool interior = tx >= 2 && tx < BX - 2 && ii < g.nx && ty >= 2 && ty < BY - 2 && jj < g.ny;
     const bool do_y = ty >= 1 && ty <= BY - 2 && tx >= 2 && tx <= BX - 3;
@@ -768,19 +792,30 @@ __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by
 
 #pragma unroll
     for (int v0 = 0; v0 < NC; v0 += G) {
+        // the base terms of this round's outputs, loaded first so that their latency is
+        // spent on the x reconstructions below (base is read only at interior cells, ghost
+        // images are written only at ghost cells, so no store of this pass can change them)
+        double bv[G][NO];
+#pragma unroll
+        for (int k = 0; k < G; ++k)
+#pragma unroll
+            for (int kk = 0; kk < NO; ++kk)
+                bv[k][kk] = (v0 + k < NC && interior && A.o[kk].base.p[0]) ? A.o[kk].base.p[v0 + k][idx] : 0.0;
         double Lx[G];
 #pragma unroll
         for (int k = 0; k < G; ++k) {
             const int v = v0 + k;
             if (v >= NC) break;
             // x: split fluxes and both half reconstructions from the neighbouring lanes
-            const double fp = 0.5 * (fx[v] + q[v]), fm = 0.5 * (fx[v] - q[v]);
+            const double fxv = row_flux<M, 0>(v, q, I);
+            const double fp = 0.5 * (fxv + q[v]), fm = 0.5 * (fxv - q[v]);
             double vp, vm;
             weno3_pair(from_left(fp), fp, from_right(fp), from_right(fm), fm, from_left(fm), vp, vm);
             Lx[k] = -((vp + from_right(vm)) - (from_left(vp) + vm)) * g.idx;
             // y: split fluxes to LDS
-            sfp[k][ty][tx] = 0.5 * (fy[v] + q[v]);
-            sfm[k][ty][tx] = 0.5 * (fy[v] - q[v]);
+            const double fyv = row_flux<M, 1>(v, q, I);
+            sfp[k][ty][tx] = 0.5 * (fyv + q[v]);
+            sfm[k][ty][tx] = 0.5 * (fyv - q[v]);
         }
         __syncthreads();
         if (do_y) {
@@ -802,15 +837,12 @@ __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by
                 if (v >= NC) break;
                 double L = Lx[k];
                 L -= ((shp[k][ty][tx] + shm[k][ty + 1][tx]) - (shp[k][ty - 1][tx] + shm[k][ty][tx])) * g.idy;
-                const double S = has_source(M, v) ? src[v] : 0.0;
-                double o0 = 0.0;
+                const double S = row_source<M>(v, q, I, A.P);
 #pragma unroll
                 for (int kk = 0; kk < NO; ++kk) {
                     const FluxOut &F = A.o[kk];
-                    const double b = F.base.p[0] ? F.base.p[v][idx] : 0.0;
-                    const double o = b + F.cL * L + F.cS * S;
+                    const double o = bv[k][kk] + F.cL * L + F.cS * S;
                     if (kk == 0) {
-                        o0 = o;
 #pragma unroll
                         for (int aa = 0; aa < 3; ++aa)
 #pragma unroll
@@ -821,14 +853,19 @@ __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by
                         F.out.p[v][idx] = o;
                     }
                 }
-                q[v] = o0;   // this thread's own q[v] is not read again
             }
         }
         // the next round rewrites sfp/sfm only after every thread has passed the barrier
         // above, and shp/shm only after the next round's first barrier
     }
     if constexpr (M != 1)
-        if (A.wnew.p[0] && interior) flux_recover<M>(A, q, w, xi, yj, 3, zoff);
+        if (A.wnew.p[0] && interior) {
+            // the new state, read back from output 0 (written above by this thread)
+            double qn[NC];
+#pragma unroll
+            for (int v = 0; v < NC; ++v) qn[v] = A.o[0].out.p[v][idx];
+            flux_recover<M>(A, qn, w, xi, yj, 3, zoff);
+        }
 }
 
 // One tile of the flux pass: single-fluid and ideal 2-D tiles with 64-wide rows use the
@@ -916,6 +953,12 @@ __global__ __launch_bounds__(1024) void k_flux_z(FluxArgs A)
     const bool do_z = tz >= 1 && tz <= BZ - 2;
 #pragma unroll
     for (int v0 = 0; v0 < NC; v0 += G) {
+        // this round's outputs, read first so that the loads overlap the reconstruction
+        double ov[G][NO];
+#pragma unroll
+        for (int c = 0; c < G; ++c)
+#pragma unroll
+            for (int o = 0; o < NO; ++o) ov[c][o] = (v0 + c < NC && interior) ? A.o[o].out.p[v0 + c][idx] : 0.0;
 #pragma unroll
         for (int c = 0; c < G; ++c) {
             const int v = v0 + c;
@@ -944,10 +987,7 @@ __global__ __launch_bounds__(1024) void k_flux_z(FluxArgs A)
                 const double Lz =
                     -((shp[c][tz][tx] + shm[c][tz + 1][tx]) - (shp[c][tz - 1][tx] + shm[c][tz][tx])) * g.idz;
 #pragma unroll
-                for (int o = 0; o < NO; ++o) {
-                    const FluxOut &F = A.o[o];
-                    F.out.p[v][idx] += F.cL * Lz;
-                }
+                for (int o = 0; o < NO; ++o) A.o[o].out.p[v][idx] = ov[c][o] + A.o[o].cL * Lz;
             }
         }
         // sfp/sfm are rewritten only after every thread has passed the second barrier above,

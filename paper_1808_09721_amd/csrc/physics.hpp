@@ -791,4 +791,82 @@ __device__ inline void id_flux_z(const double *q, const double *w, const Phys &P
     (void)P;
 }
 
+// ---------------------------------------------------------------------------------------
+// Flux components one at a time (for the row-form flux tile, which works through the
+// conserved variables in rounds): the per-cell quantities shared by the components are
+// formed once, and each component of f^x (K = 0) or f^y (K = 1) and of the source is an
+// expression in them and in q, so only the current round's values are live.  Same values as
+// sf_flux_source / id_flux_source.
+// ---------------------------------------------------------------------------------------
+struct SFRow {
+    double vx, vy, vz, A, pt, Jx, Jy, Jz;
+};
+__device__ __forceinline__ SFRow sf_row(const double *q, const double *w, double sig, const Phys &P)
+{
+    const vec3<double> v = v3(w[1], w[2], w[3]);
+    const vec3<double> B = v3(q[sf::BX], q[sf::BY], q[sf::BZ]), E = v3(q[sf::EX], q[sf::EY], q[sf::EZ]);
+    const double W = frsqrt(1.0 - dot(v, v));
+    const vec3<double> J = sf_current(v, W, E, B, q[sf::RHOE], sig);
+    return SFRow{v.x, v.y, v.z, (w[0] + P.hk * w[4]) * (W * W), w[4] + 0.5 * (dot(E, E) + dot(B, B)), J.x, J.y, J.z};
+}
+template <int K>
+__device__ __forceinline__ double sf_row_flux(int c, const double *q, const SFRow &I)
+{
+    const double vk = K == 0 ? I.vx : I.vy, Ek = q[sf::EX + K], Bk = q[sf::BX + K];
+    switch (c) {
+    case sf::D: return q[sf::D] * vk;
+    case sf::SX: return I.A * I.vx * vk + (K == 0 ? I.pt : 0.0) - q[sf::EX] * Ek - q[sf::BX] * Bk;
+    case sf::SY: return I.A * I.vy * vk + (K == 1 ? I.pt : 0.0) - q[sf::EY] * Ek - q[sf::BY] * Bk;
+    case sf::SZ: return I.A * I.vz * vk - q[sf::EZ] * Ek - q[sf::BZ] * Bk;
+    case sf::TAU: return q[sf::SX + K] - q[sf::D] * vk;
+    case sf::BX: return K == 0 ? q[sf::PHI] : q[sf::EZ];
+    case sf::BY: return K == 0 ? -q[sf::EZ] : q[sf::PHI];
+    case sf::BZ: return K == 0 ? q[sf::EY] : -q[sf::EX];
+    case sf::EX: return K == 0 ? q[sf::PSI] : -q[sf::BZ];
+    case sf::EY: return K == 0 ? q[sf::BZ] : q[sf::PSI];
+    case sf::EZ: return K == 0 ? -q[sf::BY] : q[sf::BX];
+    case sf::RHOE: return K == 0 ? I.Jx : I.Jy;
+    case sf::PSI: return Ek;
+    default: return Bk;   // PHI
+    }
+}
+__device__ __forceinline__ double sf_row_src(int c, const double *q, const SFRow &I, const Phys &P)
+{
+    switch (c) {
+    case sf::EX: return -I.Jx;
+    case sf::EY: return -I.Jy;
+    case sf::EZ: return -I.Jz;
+    case sf::PSI: return q[sf::RHOE] - P.kappa * q[sf::PSI];
+    case sf::PHI: return -P.kappa * q[sf::PHI];
+    default: return 0.0;
+    }
+}
+
+struct IdRow {
+    double vx, vy, vz, iW, pstar, bx, by, bz;
+};
+__device__ __forceinline__ IdRow id_row(const double *q, const double *w)
+{
+    vec3<double> v, B;
+    double W, pstar, b[3];
+    id_fields(q, w, v, B, W, pstar, b);
+    return IdRow{v.x, v.y, v.z, frcp(W), pstar, b[0], b[1], b[2]};
+}
+template <int K>
+__device__ __forceinline__ double id_row_flux(int c, const double *q, const IdRow &I)
+{
+    const double vk = K == 0 ? I.vx : I.vy, Bk = q[id::BX + K];
+    switch (c) {
+    case id::D: return q[id::D] * vk;
+    case id::SX: return q[id::SX] * vk + (K == 0 ? I.pstar : 0.0) - I.bx * Bk * I.iW;
+    case id::SY: return q[id::SY] * vk + (K == 1 ? I.pstar : 0.0) - I.by * Bk * I.iW;
+    case id::SZ: return q[id::SZ] * vk - I.bz * Bk * I.iW;
+    case id::TAU: return q[id::SX + K] - q[id::D] * vk;
+    case id::BX: return vk * q[id::BX] - I.vx * Bk + (K == 0 ? q[id::PHI] : 0.0);
+    case id::BY: return vk * q[id::BY] - I.vy * Bk + (K == 1 ? q[id::PHI] : 0.0);
+    case id::BZ: return vk * q[id::BZ] - I.vz * Bk;
+    default: return Bk;   // PHI
+    }
+}
+
 }  // namespace rmhd
