@@ -562,6 +562,22 @@ struct FluxArgs {
     Planes wnew;
 };
 
+// Store a cell's value and, where the cell has ghost images (img), the images too: the
+// image loop sits behind one branch, which whole wavefronts away from the boundary skip.
+__device__ __forceinline__ void store_with_images(double *plane, long zoff, int pitch, const int (&xi)[3],
+                                                  const int (&yj)[3], int ny_img, bool img, double val)
+{
+    plane[zoff + (long)yj[0] * pitch + xi[0]] = val;
+    if (img) {
+#pragma unroll
+        for (int aa = 0; aa < 3; ++aa)
+#pragma unroll
+            for (int bb = 0; bb < 3; ++bb)
+                if ((aa || bb) && bb < ny_img && xi[aa] >= 0 && yj[bb] >= 0)
+                    plane[zoff + (long)yj[bb] * pitch + xi[aa]] = val;
+    }
+}
+
 // Primitives of a cell's new state q (guess w), written with the ghost images of the cell.
 template <int M>
 __device__ __forceinline__ void flux_recover(const FluxArgs &A, const double *q, const double *w,
@@ -573,14 +589,9 @@ __device__ __forceinline__ void flux_recover(const FluxArgs &A, const double *q,
     for (int v = 0; v < NP; ++v) wn[v] = w[v];
     int it = 0;
     cons2prim_m<M>(q, wn, A.P, it);
+    const bool img = xi[1] >= 0 || xi[2] >= 0 || yj[1] >= 0 || yj[2] >= 0;
 #pragma unroll
-    for (int v = 0; v < NP; ++v)
-#pragma unroll
-        for (int aa = 0; aa < 3; ++aa)
-#pragma unroll
-            for (int bb = 0; bb < 3; ++bb)
-                if (bb < ny_img && xi[aa] >= 0 && yj[bb] >= 0)
-                    A.wnew.p[v][zoff + (long)yj[bb] * A.g.pitch + xi[aa]] = wn[v];
+    for (int v = 0; v < NP; ++v) store_with_images(A.wnew.p[v], zoff, A.g.pitch, xi, yj, ny_img, img, wn[v]);
 }
 
 // WENO3 value at the downwind face of b from the upwind-ordered stencil (a, b, c):
@@ -657,6 +668,7 @@ __device__ __forceinline__ void flux_tile_lds(const FluxArgs &A, int bx, int by,
             }
         }
     }
+    const bool img = xi[1] >= 0 || xi[2] >= 0 || yj[1] >= 0 || yj[2] >= 0;
 
 #pragma unroll
     for (int v = 0; v < NC; ++v) {
@@ -701,11 +713,7 @@ __device__ __forceinline__ void flux_tile_lds(const FluxArgs &A, int bx, int by,
                 const double o = bv[k] + F.cL * L + F.cS * S;
                 if (k == 0) {
                     o0 = o;
-#pragma unroll
-                    for (int aa = 0; aa < 3; ++aa)
-#pragma unroll
-                        for (int bb = 0; bb < (NDIM == 2 ? 3 : 1); ++bb)
-                            if (xi[aa] >= 0 && yj[bb] >= 0) F.out.p[v][zoff + (long)yj[bb] * g.pitch + xi[aa]] = o;
+                    store_with_images(F.out.p[v], zoff, g.pitch, xi, yj, NDIM == 2 ? 3 : 1, img, o);
                 } else {
                     F.out.p[v][idx] = o;
                 }
@@ -789,6 +797,7 @@ __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by
             if (jj == g.ny - 1) { yj[1] = g.ny + 2; yj[2] = g.ny + 3; }
         }
     }
+    const bool img = xi[1] >= 0 || xi[2] >= 0 || yj[1] >= 0 || yj[2] >= 0;
 
 #pragma unroll
     for (int v0 = 0; v0 < NC; v0 += G) {
@@ -843,12 +852,7 @@ __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by
                     const FluxOut &F = A.o[kk];
                     const double o = bv[k][kk] + F.cL * L + F.cS * S;
                     if (kk == 0) {
-#pragma unroll
-                        for (int aa = 0; aa < 3; ++aa)
-#pragma unroll
-                            for (int bb = 0; bb < 3; ++bb)
-                                if (xi[aa] >= 0 && yj[bb] >= 0)
-                                    F.out.p[v][zoff + (long)yj[bb] * g.pitch + xi[aa]] = o;
+                        store_with_images(F.out.p[v], zoff, g.pitch, xi, yj, 3, img, o);
                     } else {
                         F.out.p[v][idx] = o;
                     }
