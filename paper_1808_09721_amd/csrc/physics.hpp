@@ -722,7 +722,7 @@ __device__ inline int id_cons2prim(const double *q, double *w, const Phys &P, in
         if (id_root_1d(s, Z, y, iters)) st = CELL_OK;
     }
     if (st != CELL_OK) return st;
-    const double u = 1.0 - y, iZB = frcp(Z + s.B2), sZ = SB * frcp(Z);
+    const double iZB = frcp(Z + s.B2), sZ = SB * frcp(Z);
     w[1] = (S.x + sZ * B.x) * iZB;
     w[2] = (S.y + sZ * B.y) * iZB;
     w[3] = (S.z + sZ * B.z) * iZB;
@@ -730,15 +730,14 @@ __device__ inline int id_cons2prim(const double *q, double *w, const Phys &P, in
     const double uw = 1.0 - (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]);
     w[0] = s.D * sqrt(uw);
     w[4] = P.gk * (Z * uw - w[0]);
-    (void)u;
     if (!(w[0] > 0.0) || !(w[4] > 0.0) || !(uw > 0.0)) return CELL_C2P_UNPHYS;
     return CELL_OK;
 }
 
 // Flux of one cell along direction K (0, 1, 2) from (q, w), and the cleaning source.
 template <int K>
-__device__ __forceinline__ void id_flux_dir(const double *q, const double *w, const vec3<double> &v, double W,
-                                           double pstar, const double *b, const vec3<double> &B, double *f)
+__device__ __forceinline__ void id_flux_dir(const double *q, const vec3<double> &v, double W, double pstar,
+                                           const double *b, const vec3<double> &B, double *f)
 {
     const double vk = K == 0 ? v.x : K == 1 ? v.y : v.z;
     const double Bk = K == 0 ? B.x : K == 1 ? B.y : B.z;
@@ -752,7 +751,6 @@ __device__ __forceinline__ void id_flux_dir(const double *q, const double *w, co
     f[id::BY] = vk * B.y - v.y * Bk + (K == 1 ? q[id::PHI] : 0.0);
     f[id::BZ] = vk * B.z - v.z * Bk + (K == 2 ? q[id::PHI] : 0.0);
     f[id::PHI] = Bk;
-    (void)w;
 }
 
 // Comoving-field quantities of the fluxes: b^i = B^i / W + b^0 v^i, b^0 = W (v.B),
@@ -776,8 +774,8 @@ __device__ inline void id_flux_source(const double *q, const double *w, const Ph
     vec3<double> v, B;
     double W, pstar, b[3];
     id_fields(q, w, v, B, W, pstar, b);
-    id_flux_dir<0>(q, w, v, W, pstar, b, B, fx);
-    id_flux_dir<1>(q, w, v, W, pstar, b, B, fy);
+    id_flux_dir<0>(q, v, W, pstar, b, B, fx);
+    id_flux_dir<1>(q, v, W, pstar, b, B, fy);
     for (int k = 0; k < id::NC; ++k) src[k] = 0.0;
     src[id::PHI] = -P.kappa * q[id::PHI];
 }
@@ -787,8 +785,8 @@ __device__ inline void id_flux_z(const double *q, const double *w, const Phys &P
     vec3<double> v, B;
     double W, pstar, b[3];
     id_fields(q, w, v, B, W, pstar, b);
-    id_flux_dir<2>(q, w, v, W, pstar, b, B, fz);
-    (void)P;
+    id_flux_dir<2>(q, v, W, pstar, b, B, fz);
+    (void)P;   // the ideal fluxes need no physics constants beyond the state
 }
 
 // ---------------------------------------------------------------------------------------

@@ -195,3 +195,21 @@ def test_3d_full_size_sampled_flux_divergence(R, O):
     print("worst sampled relative error", worst)
     assert worst < 1e-12
     s.close()
+
+
+@pytest.mark.parametrize("model", [0, 2])
+def test_3d_outflow_shock_tube_along_z_matches_oracle(R, O, model):
+    """The Brio-Wu tube laid along z on a 4 x 4 x 400 grid (outflow on every side, vectors
+    turned twice): 100 steps against the oracle's run of the same 3-D set-up (1e-9), both
+    resistive (sigma = 100) and ideal."""
+    banner(f"3-D Brio-Wu along z model={model}")
+    wl1 = WL.brio_wu_1d()
+    if model == 2:
+        wl1 = WL.as_ideal(wl1)
+    wl = WL.rotate_axes(WL.rotate_axes(wl1))
+    assert (wl.nx, wl.ny, wl.nz) == (4, 4, 400) and wl.bc == WL.BC_OUTFLOW
+    g, oc, op, gc, gp, st = run_both(R, O, wl, 100)
+    assert st["failures"] == 0
+    err = rel_linf(g.interior(gc), g.interior(oc))
+    print("rel Linf per variable", err)
+    assert np.all(err < 1e-9)
