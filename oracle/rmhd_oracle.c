@@ -691,7 +691,11 @@ static int ideal_c2p(const orc_params *p, const double *q, double *w, int *iters
         }
     }
     *iters = it;
-    if (!conv || !ideal_residual(p->gamma, D, S2, SB2, B2, Et, Z, &f, &df)) return ORC_C2P_NOCONV;
+    if (!conv) return ORC_C2P_NOCONV;
+    /* a bracket that closed on the edge v^2 = 1 rather than on a sign change of f holds no
+     * root: the state has no physical primitives */
+    if (!ideal_residual(p->gamma, D, S2, SB2, B2, Et, Z, &f, &df) || fabs(f) > 1e-8 * (Et > 1.0 ? Et : 1.0))
+        return ORC_C2P_UNPHYS;
     for (int i = 0; i < 3; ++i) w[P_VX + i] = (S[i] + SB * B[i] / Z) / (Z + B2);
     const double u = 1.0 - dot3(w + P_VX, w + P_VX);
     w[P_RHO] = D * sqrt(u);

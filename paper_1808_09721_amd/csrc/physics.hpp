@@ -646,7 +646,9 @@ __device__ __forceinline__ void id_residual(const IdealSys &s, double Z, double 
 // Second route, where the two-dimensional iteration does not converge: y from F1 = 0 in
 // closed form, y(Z) = (S^2 Z^2 + (S.B)^2 (2 Z + B^2)) / (Z^2 (Z + B^2)^2), and F2(Z, y(Z))
 // bracketed on Z (y >= 1 or F2 < 0 below the root, F2 > 0 above) and bisected to rounding.
-__device__ inline bool id_root_1d(const IdealSys &s, double &Z, double &y, int &iters)
+// A bracket that closes on the edge y = 1 instead of a sign change of F2 holds no root: the
+// state has no physical primitives (status CELL_C2P_UNPHYS).
+__device__ inline int id_root_1d(const IdealSys &s, double &Z, double &y, int &iters)
 {
     auto eval = [&](double z, double &yy, double &f) -> bool {
         const double iz = frcp(z), zb = z + s.B2;
@@ -663,7 +665,7 @@ __device__ inline bool id_root_1d(const IdealSys &s, double &Z, double &y, int &
         hi *= 2.0;
         ++k;
     }
-    if (k == 64) return false;
+    if (k == 64) return CELL_C2P_UNPHYS;
     for (int it = 0; it < 200; ++it) {
         const double mid = 0.5 * (lo + hi);
         if (!(mid > lo && mid < hi)) break;
@@ -671,7 +673,8 @@ __device__ inline bool id_root_1d(const IdealSys &s, double &Z, double &y, int &
         ++iters;
     }
     Z = hi;
-    return eval(Z, y, f);
+    if (!eval(Z, y, f) || fabs(f) > 1e-8 * fmax(1.0, s.Et)) return CELL_C2P_UNPHYS;
+    return CELL_OK;
 }
 
 // 9 conserved -> (rho, v, p).  Newton on (Z, y) from the guess w (rho h W^2 and v^2 of w;
@@ -718,9 +721,7 @@ __device__ inline int id_cons2prim(const double *q, double *w, const Phys &P, in
             break;
         }
     }
-    if (st != CELL_OK && P.c2p_fallback) {
-        if (id_root_1d(s, Z, y, iters)) st = CELL_OK;
-    }
+    if (st != CELL_OK && P.c2p_fallback) st = id_root_1d(s, Z, y, iters);
     if (st != CELL_OK) return st;
     const double iZB = frcp(Z + s.B2), sZ = SB * frcp(Z);
     w[1] = (S.x + sZ * B.x) * iZB;

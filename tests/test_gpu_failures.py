@@ -136,3 +136,34 @@ def test_nan_cell_in_a_stage_stays_local(R, O, model):
     assert (st1[mask] == 0).all()
     np.testing.assert_array_equal(q1[:, mask], q0[:, mask])
     s.close()
+
+
+def test_ideal_recovery_flags_unphysical_and_nan_cells(R, O):
+    """Ideal model: a cell whose energy cannot carry its momentum, a negative density and a
+    NaN density come back with status 2 (no physical primitives), as the oracle flags them;
+    every other cell recovers as the oracle does."""
+    banner("ideal recovery failures")
+    import torch
+    wl = WL.as_ideal(WL.kelvin_helmholtz_2d(40, 24, steps=1))
+    s = gpu_solver(R, wl)
+    g, ocons, oprims = initial_state(wl)
+    bad = ocons.copy()
+    bad[4, 10, 10] = -bad[0, 10, 10] + 1e-3              # tau + D tiny against |S|
+    bad[1, 10, 10] = 5.0
+    bad[0, 12, 20] = -1.0                                 # negative density
+    bad[0, 15, 30] = float("nan")                         # NaN density
+    cons = upload_all(R, s.grid, bad)
+    prims = upload_all(R, s.grid, oprims)
+    st = status_plane(R, s)
+    R.rmhd_cons2prim(s.ctx, cons, prims, st)
+    torch.cuda.synchronize()
+    stv = s.grid.all_view(st).cpu().numpy()[0]
+    for (j, i) in ((10, 10), (12, 20), (15, 30)):
+        assert stv[j, i] == 2, (j, i, stv[j, i])
+        assert O.cons2prim_cell(g, bad[:, j, i], oprims[:, j, i].copy())[1] == 2
+    mask = np.ones_like(stv, dtype=bool)
+    mask[10, 10] = mask[12, 20] = mask[15, 30] = False
+    assert (stv[mask] == 0).all()
+    gp = s.grid.download_all(prims)
+    assert np.all(np.abs(gp[:, mask] - oprims[:, mask]) <= 1e-12 * np.abs(oprims).max(axis=(1, 2))[:, None])
+    s.close()

@@ -285,3 +285,34 @@ def test_learned_guess_gain(R, trained):
     assert 0.0 < sp["residual_max"] <= 1e-12 and 0.0 < sl["residual_max"] <= 1e-12
     assert rel_linf(learned, plain).max() < 1e-9
     assert il <= ip + 0.05
+
+
+def test_learned_guess_and_harvest_on_a_3d_grid(R, O, trained):
+    """3-D two-fluid grid: the learned guess (trained on 2-D sheets) leaves whole steps equal
+    to the oracle's to 1e-9, and harvesting writes one row per interior cell and stage."""
+    banner("learned guess on a 3-D grid")
+    import torch
+    wl = WL.two_fluid_sheet_3d(16, 12, 10, steps=3)
+    s = gpu_solver(R, wl)
+    cons, prims = s.initial_state(wl.prims, wl.EB)
+    n = wl.cells
+    X = torch.zeros((2 * n + 3, 19), dtype=torch.float32, device="cuda")
+    T = torch.zeros((2 * n + 3, 7), dtype=torch.float32, device="cuda")
+    s.set_harvest(X, T)
+    s.step(s.dt(), cons, prims)
+    assert s.harvest_count() == 2 * n
+    s.set_harvest(None, None)
+    s.set_guess_model(trained)
+    for _ in range(wl.steps - 1):
+        s.step(s.dt(), cons, prims)
+    st = s.stats()
+    gc = s.grid.download_all(cons)
+    s.close()
+    assert st["failures"] == 0
+    g, oc, op = initial_state(wl)
+    advance(g, oc, op, O.dt(g, wl.cfl), steps=wl.steps)
+    assert rel_linf(gc, oc).max() < 1e-9
+    # the harvested features of the first stage: f_k = R_k / D of the initial state
+    x = X[:n].cpu().numpy()
+    qi = g.interior(initial_state(wl)[1]).reshape(18, -1)
+    np.testing.assert_allclose(x[:, 1], (qi[1] / qi[0]).astype(np.float32), rtol=1e-5, atol=1e-7)
