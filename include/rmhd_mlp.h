@@ -107,6 +107,15 @@ int rmhd_set_harvest(rmhd_ctx *ctx, float *X, float *T, long capacity);
 long rmhd_harvest_count(const rmhd_ctx *ctx);
 int rmhd_set_guess_model(rmhd_ctx *ctx, const rmhd_mlp *m);
 
+/* The learned starting point that rmhd_set_guess_model feeds to an implicit stage (the same
+ * kernel), written on its own: for every cell of the padded grid (ghosts included, row
+ * padding excluded) the seven source-carrying planes of guess (Sbar, taubar, E; conserved
+ * layout, ncons planes) receive x0 = R_x + D y, y the network's output on the cell's features
+ * of R (f_0 = log10(a mu1^2 D), f_k = R_k / D, f_18 = log10(a sigma)), momentum and energy in
+ * conserved units.  The other planes are not touched.  R and guess: device arrays of the
+ * context's layout, not aliased.  Two-fluid contexts, a > 0. */
+int rmhd_learned_guess(rmhd_ctx *ctx, const rmhd_mlp *m, double a, const double *R, double *guess);
+
 #ifdef __cplusplus
 }
 #endif

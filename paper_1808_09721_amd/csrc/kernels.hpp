@@ -118,6 +118,29 @@ __device__ __forceinline__ int bc_src(int i, int n, int bc)
     return i < 2 ? 2 : n + 1;
 }
 
+// Ghost images of interior cell (ii, jj) (interior coordinates) of a 1-D or 2-D grid under
+// the boundary condition: xi[0] and yj[0] stay the cell's own padded column and row, xi[1..2]
+// and yj[1..2] become the ghost columns and rows that copy it (-1: none).  With ydir false
+// only x images are formed.
+__device__ __forceinline__ void ghost_images(const Geo &g, int ii, int jj, bool ydir, int (&xi)[3], int (&yj)[3])
+{
+    if (g.bc == RMHD_BC_PERIODIC) {
+        if (ii < 2) xi[1] = xi[0] + g.nx;
+        if (ii >= g.nx - 2) xi[2] = xi[0] - g.nx;
+        if (ydir) {
+            if (jj < 2) yj[1] = yj[0] + g.ny;
+            if (jj >= g.ny - 2) yj[2] = yj[0] - g.ny;
+        }
+    } else {
+        if (ii == 0) { xi[1] = 0; xi[2] = 1; }
+        if (ii == g.nx - 1) { xi[1] = g.nx + 2; xi[2] = g.nx + 3; }
+        if (ydir) {
+            if (jj == 0) { yj[1] = 0; yj[2] = 1; }
+            if (jj == g.ny - 1) { yj[1] = g.ny + 2; yj[2] = g.ny + 3; }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------------------
 // ghost fill
 // ---------------------------------------------------------------------------------------
@@ -651,23 +674,7 @@ __device__ __forceinline__ void flux_tile_lds(const FluxArgs &A, int bx, int by,
 
     // ghost images of this interior cell (fused boundary fill of output 0)
     int xi[3] = {i, -1, -1}, yj[3] = {j, -1, -1};
-    if (A.fuse_bc && interior) {
-        if (g.bc == RMHD_BC_PERIODIC) {
-            if (ii < 2) xi[1] = i + g.nx;
-            if (ii >= g.nx - 2) xi[2] = i - g.nx;
-            if (NDIM == 2) {
-                if (jj < 2) yj[1] = j + g.ny;
-                if (jj >= g.ny - 2) yj[2] = j - g.ny;
-            }
-        } else {
-            if (ii == 0) { xi[1] = 0; xi[2] = 1; }
-            if (ii == g.nx - 1) { xi[1] = g.nx + 2; xi[2] = g.nx + 3; }
-            if (NDIM == 2) {
-                if (jj == 0) { yj[1] = 0; yj[2] = 1; }
-                if (jj == g.ny - 1) { yj[1] = g.ny + 2; yj[2] = g.ny + 3; }
-            }
-        }
-    }
+    if (A.fuse_bc && interior) ghost_images(g, ii, jj, NDIM == 2, xi, yj);
     const bool img = xi[1] >= 0 || xi[2] >= 0 || yj[1] >= 0 || yj[2] >= 0;
 
 #pragma unroll
@@ -784,19 +791,7 @@ __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by
 
     // ghost images of this interior cell (fused boundary fill of output 0)
     int xi[3] = {i, -1, -1}, yj[3] = {j, -1, -1};
-    if (A.fuse_bc && interior) {
-        if (g.bc == RMHD_BC_PERIODIC) {
-            if (ii < 2) xi[1] = i + g.nx;
-            if (ii >= g.nx - 2) xi[2] = i - g.nx;
-            if (jj < 2) yj[1] = j + g.ny;
-            if (jj >= g.ny - 2) yj[2] = j - g.ny;
-        } else {
-            if (ii == 0) { xi[1] = 0; xi[2] = 1; }
-            if (ii == g.nx - 1) { xi[1] = g.nx + 2; xi[2] = g.nx + 3; }
-            if (jj == 0) { yj[1] = 0; yj[2] = 1; }
-            if (jj == g.ny - 1) { yj[1] = g.ny + 2; yj[2] = g.ny + 3; }
-        }
-    }
+    if (A.fuse_bc && interior) ghost_images(g, ii, jj, true, xi, yj);
     const bool img = xi[1] >= 0 || xi[2] >= 0 || yj[1] >= 0 || yj[2] >= 0;
 
 #pragma unroll

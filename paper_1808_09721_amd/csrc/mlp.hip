@@ -2,9 +2,10 @@
 // a 19-64-64-7 tanh network with FP32 master weights used in bfloat16.
 //
 //   k_quantize   master weights -> bfloat16-rounded FP32 copy and matrix-core operand tiles
-//   k_infer<S>   inference on the matrix cores (v_mfma_f32_16x16x16_bf16, FP32 accumulate):
-//                S = 0 reads raw feature rows, S = 1 computes the features from a stage's
-//                right-hand side R and writes the starting point x0 = R_x + D y
+//   k_infer      inference on the matrix cores (v_mfma_f32_16x16x16_bf16, FP32 accumulate)
+//                of raw feature rows
+//   k_guess      the same network on the features of a stage's right-hand side R, writing
+//                the starting point x0 = R_x + D y (coalesced: one cell per lane)
 //   k_fwd32      FP32-activation forward, one sample per thread
 //   k_grad       forward + backward of 64 samples per block through LDS, per-block gradient
 //   k_adam       ordered sum of the block gradients, Adam update, re-rounding
@@ -85,205 +86,247 @@ __global__ void k_quantize(const float *master, float *wq, unsigned short *packe
 // The network is evaluated transposed, H^T = W U^T, on tiles of 16 samples per wave: the
 // accumulator layout of one product (lane l: rows 4 (l / 16) + e, column l % 16) is the
 // B-operand layout of the next, so activations never leave registers.
+__device__ inline float fast_tanh(float z)
+{
+    // 1 - 2 / (1 + e^{2z}) = 1 - 2 / (1 + 2^{2 z log2 e}) with the hardware base-2 exponential
+    // and reciprocal (about 1 ulp each, far below the bfloat16 rounding that follows);
+    // saturates to +-1.  The constant is 2 log2 e, so the product is twice z log2 e exactly.
+    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z * 2.8853900817779268f));
+}
+
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Four values rounded to bfloat16 (nearest, ties to even: gfx950's packed conversion, two
+// values per instruction, the same rounding as bf16_bits for finite values) as an MFMA
+// operand.
+__device__ inline v4s pack4(float a, float b, float c, float d)
+{
+    const f4 x = {a, b, c, d};
+    const bf4 h = __builtin_convertvector(x, bf4);
+    v4s r;
+    memcpy(&r, &h, sizeof(r));
+    return r;
+}
+
+// The network as one wavefront holds it: the 28 weight tiles in the A-operand layout and the
+// biases of the accumulator rows of this lane (rows 4q + e, q = lane / 16).
+struct NetRegs {
+    v4s w1[4][2], w2[4][4], w3[4];
+    float b1[4][4], b2[4][4], b3[4];
+};
+
+__device__ inline void load_net(const v4s *packed, const float *wq, int lane, NetRegs &N)
+{
+    const int q = lane >> 4;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) N.w1[m][kb] = packed[(m * 2 + kb) * 64 + lane];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) N.w2[m][kb] = packed[(8 + m * 4 + kb) * 64 + lane];
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) N.w3[kb] = packed[(24 + kb) * 64 + lane];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            N.b1[m][e] = wq[OB1 + 16 * m + 4 * q + e];
+            N.b2[m][e] = wq[OB2 + 16 * m + 4 * q + e];
+        }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) N.b3[e] = (4 * q + e < NOUT) ? wq[OB3 + 4 * q + e] : 0.0f;
+}
+
+// One tile of 16 samples through the network.  x0, x1: the standardised inputs 4q .. 4q+3
+// and 16+4q .. 16+4q+3 of sample lane % 16 (B-operand layout).  Returns the output rows
+// 4q + e of that sample, biases included, in standardised target units.
+// Each product accumulates onto its biases (the accumulator starts at b instead of 0).
+__device__ inline v4f net_tile(const NetRegs &N, v4s x0, v4s x1)
+{
+    // layer 1: H1^T (64 x 16) = W1 (64 x 32) U^T (32 x 16) + b1
+    v4s h1[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        v4f acc = {N.b1[m][0], N.b1[m][1], N.b1[m][2], N.b1[m][3]};
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(N.w1[m][0], x0, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(N.w1[m][1], x1, acc, 0, 0, 0);
+        h1[m] = pack4(fast_tanh(acc[0]), fast_tanh(acc[1]), fast_tanh(acc[2]), fast_tanh(acc[3]));
+    }
+    // layer 2
+    v4s h2[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        v4f acc = {N.b2[m][0], N.b2[m][1], N.b2[m][2], N.b2[m][3]};
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(N.w2[m][kb], h1[kb], acc, 0, 0, 0);
+        h2[m] = pack4(fast_tanh(acc[0]), fast_tanh(acc[1]), fast_tanh(acc[2]), fast_tanh(acc[3]));
+    }
+    // layer 3: rows 0..6 of the 16-row output tile
+    v4f acc = {N.b3[0], N.b3[1], N.b3[2], N.b3[3]};
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(N.w3[kb], h2[kb], acc, 0, 0, 0);
+    return acc;
+}
+
+// Reciprocal standard deviations of the inputs (0 where a std is not positive): the
+// standardised value is rounded to bfloat16 next, far coarser than the multiply's rounding.
+__device__ inline float inv_std(float s) { return s > 0.0f ? 1.0f / s : 0.0f; }
+
+// Raw feature rows X[n][19] -> outputs Y[n][7] (target units), one 16-sample tile per wave
+// and step; the next tile's inputs are fetched before the current tile's products.
 struct InferArgs {
     const v4s *packed;
     const float *wq;     // biases
     const float *norm;
-    // S = 0
     const float *X;
     float *Y;
     long n;
-    // S = 1
+};
+
+__global__ __launch_bounds__(256) void k_infer(InferArgs A)
+{
+    const int lane = threadIdx.x & 63, col = lane & 15, q = lane >> 4;
+    NetRegs N;
+    load_net(A.packed, A.wq, lane, N);
+    // this lane's inputs: 4q + e (first K block) and 16 + 4q + e (second, q = 0 only)
+    float fm[8], fsi[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int f = (e < 4 ? 0 : 16) + 4 * q + (e & 3);
+        fm[e] = f < NIN ? A.norm[NFM + f] : 0.0f;
+        fsi[e] = f < NIN ? inv_std(A.norm[NFS + f]) : 0.0f;
+    }
+    const long ntiles = (A.n + 15) / 16;
+    const long wave = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const long nwaves = ((long)gridDim.x * blockDim.x) >> 6;
+    auto fetch = [&](long tile, float (&v)[8]) {
+        const long s = tile * 16 + col;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = 0.0f;
+        if (tile >= ntiles || s >= A.n) return;
+        const float *x = A.X + s * NIN;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int fi = (e < 4 ? 0 : 16) + 4 * q + (e & 3);
+            if (fi < NIN) v[e] = x[fi];
+        }
+    };
+    float cur[8], nxt[8];
+    fetch(wave, cur);
+    for (long tile = wave; tile < ntiles; tile += nwaves) {
+        fetch(tile + nwaves, nxt);
+        const long s = tile * 16 + col;
+        float u[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) u[e] = (cur[e] - fm[e]) * fsi[e];
+        if (q > 0) u[4] = u[5] = u[6] = u[7] = 0.0f;   // padded columns 20..31
+        const v4f acc = net_tile(N, pack4(u[0], u[1], u[2], u[3]), pack4(u[4], u[5], u[6], u[7]));
+        if (s < A.n && q <= 1) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int k = 4 * q + e;
+                if (k < NOUT) A.Y[s * NOUT + k] = A.norm[NTM + k] + A.norm[NTS + k] * acc[e];
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) cur[e] = nxt[e];
+    }
+}
+
+// Learned starting point of a two-fluid stage with right-hand side R: x0 = R_x + D y on the
+// seven source-carrying planes, for every cell of the padded grid.  One wavefront takes 64
+// consecutive cells, one per lane, so that every plane is read and written in whole
+// 512-byte rows; the standardised features go to the matrix-core layout (16 cells per
+// product) through LDS, and the outputs come back to their cells the same way.  The LDS
+// rows are private to the wavefront, so a wave-level fence orders them (no block barrier).
+struct GuessArgs {
+    const v4s *packed;
+    const float *wq, *norm;
     CPlanes R;
     Planes guess;
     Geo g;
     Phys P;
     double a;
 };
+constexpr int UROW = 40;   // bfloat16 per LDS feature row (32 used): 80-byte rows spread the
+                           // B-operand reads of 16 consecutive cells over the banks
 
-__device__ inline float fast_tanh(float z)
+__device__ inline void wave_lds_sync()
 {
-    // 1 - 2 / (1 + e^{2z}) with the hardware exponential and reciprocal (about 1 ulp each,
-    // far below the bfloat16 rounding that follows); saturates to +-1
-    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + __expf(2.0f * z));
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Four values rounded to bfloat16 (nearest, ties to even: gfx950's packed conversion, the
-// same rounding as bf16_bits for finite values) as an MFMA operand.
-__device__ inline v4s pack4(float a, float b, float c, float d)
+__global__ __launch_bounds__(256, 3) void k_guess(GuessArgs A)
 {
-    const __bf16 h[4] = {(__bf16)a, (__bf16)b, (__bf16)c, (__bf16)d};
-    v4s r;
-    memcpy(&r, h, sizeof(r));
-    return r;
-}
-
-template <int S>
-__global__ __launch_bounds__(256) void k_infer(InferArgs A)
-{
-    const int lane = threadIdx.x & 63, col = lane & 15, q = lane >> 4;
-    v4s w1[4][2], w2[4][4], w3[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int kb = 0; kb < 2; ++kb) w1[m][kb] = A.packed[(m * 2 + kb) * 64 + lane];
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int kb = 0; kb < 4; ++kb) w2[m][kb] = A.packed[(8 + m * 4 + kb) * 64 + lane];
-#pragma unroll
-    for (int kb = 0; kb < 4; ++kb) w3[kb] = A.packed[(24 + kb) * 64 + lane];
-    float b1[4][4], b2[4][4], b3[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            b1[m][e] = A.wq[OB1 + 16 * m + 4 * q + e];
-            b2[m][e] = A.wq[OB2 + 16 * m + 4 * q + e];
-        }
-#pragma unroll
-    for (int e = 0; e < 4; ++e) b3[e] = (4 * q + e < NOUT) ? A.wq[OB3 + 4 * q + e] : 0.0f;
-    // this lane's features: 4q + e (first K block) and 16 + 4q + e (second, q = 0 only)
-    float fm[8], fs[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const int f = (e < 4 ? 0 : 16) + 4 * q + (e & 3);
-        fm[e] = f < NIN ? A.norm[NFM + f] : 0.0f;
-        fs[e] = f < NIN ? A.norm[NFS + f] : 1.0f;
+    __shared__ __attribute__((aligned(16))) unsigned short s_u[4][64][UROW];
+    __shared__ float s_y[4][64][8];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, col = lane & 15, q = lane >> 4;
+    // standardisation of the features (means, reciprocal standard deviations), read from LDS
+    // as broadcasts
+    __shared__ float s_fm[NIN], s_fsi[NIN];
+    if (threadIdx.x < NIN) {
+        s_fm[threadIdx.x] = A.norm[NFM + threadIdx.x];
+        s_fsi[threadIdx.x] = inv_std(A.norm[NFS + threadIdx.x]);
     }
-
-    float fsi[8];   // reciprocal standard deviations: the standardised value is rounded to
-                    // bfloat16 next, far coarser than the multiply's rounding
+    __syncthreads();
+    NetRegs N;
+    load_net(A.packed, A.wq, lane, N);
+    const Geo &g = A.g;
+    const double sc = fabs(A.P.mu1), amu = A.a * A.P.mu1 * A.P.mu1;
+    const long nchunks = (g.plane + 63) / 64;
+    for (long c = (long)blockIdx.x * 4 + wv; c < nchunks; c += (long)gridDim.x * 4) {
+        const long s = c * 64 + lane;
+        const long r = s / g.pitch;
+        const bool live = s < g.plane && s - r * g.pitch < g.nxg && r < g.rows;
+        // every lane loads (a lane past the end from the last cell), so the loads need no
+        // branches; dead lanes' values are replaced below
+        const long sl = s < g.plane ? s : g.plane - 1;
+        double Rv[18];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) fsi[e] = fs[e] > 0.0f ? 1.0f / fs[e] : 0.0f;
-
-    const long nsamp = S == 0 ? A.n : A.g.plane;
-    const long ntiles = (nsamp + 15) / 16;
-    const long wave = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const long nwaves = ((long)gridDim.x * blockDim.x) >> 6;
-    // raw inputs of one tile for this lane; the next tile's are fetched before the current
-    // tile's products so that their latency overlaps the arithmetic
-    struct Raw {
-        double v[8];    // S = 1: D, the lane's 4 conserved values, 2 more (q = 0), sigma (q = 0)
-        double rv[4];   // S = 1: R's values of the lane's outputs
-        bool live;
-    };
-    auto fetch = [&](long tile, Raw &r) {
-        const long s = tile * 16 + col;
-        r.live = tile < ntiles && s < nsamp;
-        if constexpr (S == 1) {
-            const int i = (int)(s % A.g.pitch), j = (int)(s / A.g.pitch);
-            r.live = r.live && i < A.g.nxg && j < A.g.rows;
-        }
+        for (int v = 0; v < 18; ++v) Rv[v] = A.R.p[v][sl];
+        const double sig = cell_sigma(A.P, sl);
+        // features in FP32 (rounded to bfloat16 before the first product), standardised
+        const float iD = __builtin_amdgcn_rcpf((float)Rv[tf::D]);
+        float f[32];
+        f[0] = __log10f((float)(amu * Rv[tf::D]));
 #pragma unroll
-        for (int e = 0; e < 8; ++e) r.v[e] = 0.0;
+        for (int k = 1; k < 18; ++k) f[k] = (float)Rv[k] * iD;
+        f[18] = __log10f((float)(A.a * sig));
 #pragma unroll
-        for (int e = 0; e < 4; ++e) r.rv[e] = 0.0;
-        if (!r.live) return;
-        if constexpr (S == 0) {
-            const float *x = A.X + s * NIN;
+        for (int k = 0; k < NIN; ++k) f[k] = live ? (f[k] - s_fm[k]) * s_fsi[k] : 0.0f;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int fi = (e < 4 ? 0 : 16) + 4 * q + (e & 3);
-                if (fi < NIN) r.v[e] = x[fi];
-            }
-        } else {
-            // planes picked by selects on the wave-uniform pointers (a lane-indexed pointer
-            // table would live in scratch memory)
-            r.v[7] = A.R.p[tf::D][s];
+        for (int k = NIN; k < 32; ++k) f[k] = 0.0f;
+        v4s *row = (v4s *)&s_u[wv][lane][0];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const double *pl = q == 0 ? A.R.p[e] : q == 1 ? A.R.p[4 + e] : q == 2 ? A.R.p[8 + e] : A.R.p[12 + e];
-                r.v[e] = pl[s];
-            }
-            if (q == 0) {
-                r.v[4] = A.R.p[16][s];
-                r.v[5] = A.R.p[17][s];
-                r.v[6] = cell_sigma(A.P, s);
-            }
+        for (int k = 0; k < 8; ++k) row[k] = pack4(f[4 * k], f[4 * k + 1], f[4 * k + 2], f[4 * k + 3]);
+        wave_lds_sync();
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const v4s *src = (const v4s *)&s_u[wv][16 * t + col][0];
+            const v4f acc = net_tile(N, src[q], src[4 + q]);
             if (q <= 1) {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int p0 = e < 3 ? tf::SBX + e : tf::TAUB, p1 = tf::EX + (e < 3 ? e : 0);
-                    if (q == 0 || e < 3) r.rv[e] = q == 0 ? A.R.p[p0][s] : A.R.p[p1][s];
-                }
+                for (int e = 0; e < 4; ++e) s_y[wv][16 * t + col][4 * q + e] = acc[e];
             }
         }
-    };
-    Raw cur, nxt;
-    fetch(wave, cur);
-    for (long tile = wave; tile < ntiles; tile += nwaves) {
-        fetch(tile + nwaves, nxt);
-        const long s = tile * 16 + col;
-        const bool live = cur.live;
-        const double D = S == 1 ? cur.v[7] : 1.0;
-        float f[8];
-        if constexpr (S == 0) {
+        wave_lds_sync();
+        if (live) {
+            // x0 = R_x + D y; the momentum and energy differences in conserved units (times
+            // |mu1|), as the stage reads its starting point
+            const int px[NOUT] = {tf::SBX, tf::SBY, tf::SBZ, tf::TAUB, tf::EX, tf::EY, tf::EZ};
 #pragma unroll
-            for (int e = 0; e < 8; ++e) f[e] = (float)cur.v[e];
-        } else {
-            // features in FP32: they are rounded to bfloat16 before the first product
-            const float iD = live ? __builtin_amdgcn_rcpf((float)D) : 0.0f;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) f[e] = (float)cur.v[e] * iD;
-            f[4] = (float)cur.v[4] * iD;
-            f[5] = (float)cur.v[5] * iD;
-            f[6] = 0.0f;
-            f[7] = 0.0f;
-            if (q == 0 && live) {
-                f[0] = __log10f((float)(A.a * A.P.mu1 * A.P.mu1 * D));
-                f[6] = __log10f((float)(A.a * cur.v[6]));
+            for (int k = 0; k < NOUT; ++k) {
+                const float y = A.norm[NTM + k] + A.norm[NTS + k] * s_y[wv][lane][k];
+                const double scale = k < 4 ? sc : 1.0;
+                A.guess.p[px[k]][s] = Rv[px[k]] + Rv[tf::D] * scale * (double)y;
             }
         }
-        float u[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) u[e] = live ? (f[e] - fm[e]) * fsi[e] : 0.0f;
-        if (q > 0) u[4] = u[5] = u[6] = u[7] = 0.0f;   // padded columns 20..31
-        const v4s x0 = pack4(u[0], u[1], u[2], u[3]), x1 = pack4(u[4], u[5], u[6], u[7]);
-        // layer 1: H1^T (64 x 16) = W1 (64 x 32) U^T (32 x 16)
-        v4s h1[4];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w1[m][0], x0, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w1[m][1], x1, acc, 0, 0, 0);
-            h1[m] = pack4(fast_tanh(acc[0] + b1[m][0]), fast_tanh(acc[1] + b1[m][1]), fast_tanh(acc[2] + b1[m][2]),
-                          fast_tanh(acc[3] + b1[m][3]));
-        }
-        // layer 2
-        v4s h2[4];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-            for (int kb = 0; kb < 4; ++kb) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w2[m][kb], h1[kb], acc, 0, 0, 0);
-            h2[m] = pack4(fast_tanh(acc[0] + b2[m][0]), fast_tanh(acc[1] + b2[m][1]), fast_tanh(acc[2] + b2[m][2]),
-                          fast_tanh(acc[3] + b2[m][3]));
-        }
-        // layer 3: rows 0..6 of the 16-row output tile
-        v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int kb = 0; kb < 4; ++kb) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w3[kb], h2[kb], acc, 0, 0, 0);
-        if (live && q <= 1) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int k = 4 * q + e;
-            if (k >= NOUT) break;
-            const float y = A.norm[NTM + k] + A.norm[NTS + k] * (acc[e] + b3[e]);
-            if constexpr (S == 0) {
-                A.Y[s * NOUT + k] = y;
-            } else {
-                // x0 = R_x + D y; the momentum and energy differences are stored in conserved
-                // units (times |mu1|), as the stage reads its starting point.  Output 4q + e
-                // goes to Sbar/taubar (q = 0) or E (q = 1): planes picked by select.
-                const int p0 = e < 3 ? tf::SBX + e : tf::TAUB, p1 = tf::EX + (e < 3 ? e : 0);
-                double *out = q == 0 ? A.guess.p[p0] : A.guess.p[p1];
-                const double scale = q == 0 ? fabs(A.P.mu1) : 1.0;
-                out[s] = cur.rv[e] + D * scale * (double)y;
-            }
-        }
-        }
-        cur = nxt;
+        wave_lds_sync();   // this chunk's LDS reads before the next chunk's writes
     }
 }
 
@@ -692,7 +735,7 @@ extern "C" int rmhd_mlp_forward(rmhd_mlp *m, const float *X, long n, float *Y, i
     const long tiles = (n + 15) / 16;
     long blocks = (tiles + 3) / 4;
     if (blocks > 8L * m->cus) blocks = 8L * m->cus;
-    hipLaunchKernelGGL(k_infer<0>, dim3((unsigned)blocks), dim3(256), 0, m->stream, A);
+    hipLaunchKernelGGL(k_infer, dim3((unsigned)blocks), dim3(256), 0, m->stream, A);
     return mcheck(m, hipGetLastError(), "k_infer launch");
 }
 
@@ -823,7 +866,7 @@ namespace rmhd {
 int mlp_launch_guess(const rmhd_mlp *m, hipStream_t stream, const CPlanes &R, const Planes &guess, const Geo &g,
                      const Phys &P, double a)
 {
-    InferArgs A{};
+    GuessArgs A{};
     A.packed = (const v4s *)m->packed;
     A.wq = m->wq;
     A.norm = m->norm;
@@ -832,10 +875,11 @@ int mlp_launch_guess(const rmhd_mlp *m, hipStream_t stream, const CPlanes &R, co
     A.g = g;
     A.P = P;
     A.a = a;
-    const long tiles = (g.plane + 15) / 16;
-    long blocks = (tiles + 3) / 4;
-    if (blocks > 8L * m->cus) blocks = 8L * m->cus;
-    hipLaunchKernelGGL(k_infer<1>, dim3((unsigned)blocks), dim3(256), 0, stream, A);
+    // four 64-cell chunks per block and round; a few blocks per CU, each wave loading the
+    // weight tiles once
+    long blocks = (g.plane + 255) / 256;
+    if (blocks > 4L * m->cus) blocks = 4L * m->cus;
+    hipLaunchKernelGGL(k_guess, dim3((unsigned)blocks), dim3(256), 0, stream, A);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 }  // namespace rmhd

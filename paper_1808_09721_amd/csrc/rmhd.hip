@@ -262,7 +262,7 @@ static int launch_stage(rmhd_ctx *c, const StageArgs &A)
         int k = 0;
         for (int v : {tf::SBX, tf::SBY, tf::SBZ, tf::TAUB, tf::EX, tf::EY, tf::EZ}) G.p[v] = c->guess + (k++) * c->lay.plane;
         if (mlp_launch_guess(c->mlp, c->stream, A.R, G, c->geo, c->phys, A.a))
-            return hip_check(c, hipGetLastError(), "k_infer launch");
+            return fail(c, RMHD_EHIP, "k_guess launch failed");
         B.guess = as_const(G);
         B.use_guess = 1;
     }
@@ -765,6 +765,17 @@ extern "C" int rmhd_set_guess_model(rmhd_ctx *c, const rmhd_mlp *m)
     }
     c->mlp = m;
     free_graph(c);   // kernel sequence changed: capture again
+    return RMHD_OK;
+}
+
+extern "C" int rmhd_learned_guess(rmhd_ctx *c, const rmhd_mlp *m, double a, const double *R, double *guess)
+{
+    if (!c || !m || !R || !guess) return fail(c, RMHD_EINVAL, "rmhd_learned_guess: NULL argument");
+    if (c->prm.model != RMHD_TWO_FLUID) return fail(c, RMHD_EINVAL, "rmhd_learned_guess: two-fluid contexts only");
+    if (!(a > 0.0)) return fail(c, RMHD_EINVAL, "rmhd_learned_guess: a must be > 0");
+    const rmhd_layout &L = c->lay;
+    if (mlp_launch_guess(m, c->stream, cplanes_of(R, L, L.ncons), planes_of(guess, L, L.ncons), c->geo, c->phys, a))
+        return fail(c, RMHD_EHIP, "k_guess launch failed");
     return RMHD_OK;
 }
 

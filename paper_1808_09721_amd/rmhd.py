@@ -71,7 +71,8 @@ EXPORTS = ["rmhd_layout_of", "rmhd_create", "rmhd_destroy", "rmhd_init_state", "
            "rmhd_batch_last_error",
            "rmhd_mlp_create", "rmhd_mlp_destroy", "rmhd_mlp_get_params", "rmhd_mlp_get_norm", "rmhd_mlp_set_norm",
            "rmhd_mlp_fit_norm", "rmhd_mlp_forward", "rmhd_mlp_loss_grad", "rmhd_mlp_train_step", "rmhd_mlp_train",
-           "rmhd_mlp_steps", "rmhd_mlp_last_error", "rmhd_set_harvest", "rmhd_harvest_count", "rmhd_set_guess_model"]
+           "rmhd_mlp_steps", "rmhd_mlp_last_error", "rmhd_set_harvest", "rmhd_harvest_count", "rmhd_set_guess_model",
+           "rmhd_learned_guess"]
 
 MLP_NIN, MLP_NHID, MLP_NOUT, MLP_NPARAMS, MLP_NNORM, MLP_MAX_BATCH = 19, 64, 7, 5895, 52, 65536
 
@@ -131,6 +132,7 @@ def lib() -> ctypes.CDLL:
             "rmhd_set_harvest": (ctypes.c_int, [vp, vp, vp, ctypes.c_long]),
             "rmhd_harvest_count": (ctypes.c_long, [vp]),
             "rmhd_set_guess_model": (ctypes.c_int, [vp, vp]),
+            "rmhd_learned_guess": (ctypes.c_int, [vp, vp, ctypes.c_double, dp, dp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -512,6 +514,10 @@ def rmhd_harvest_count(ctx) -> int:
 
 def rmhd_set_guess_model(ctx, mlp):
     _check(lib().rmhd_set_guess_model(ctx, None if mlp is None else mlp.m), ctx)
+
+
+def rmhd_learned_guess(ctx, mlp, a, R, guess):
+    _check(lib().rmhd_learned_guess(ctx, mlp.m, float(a), _ptr(R), _ptr(guess)), ctx)
 
 
 def harvest_stages(workloads, steps: int, dt_factors=(1.0,)):

@@ -222,6 +222,46 @@ def test_harvest_matches_reference_stage(R, O):
     s.close()
 
 
+@pytest.mark.parametrize("case", ["2d", "3d"])
+def test_learned_guess_planes_match_reference(R, O, case):
+    """rmhd_learned_guess on an evolved two-fluid state: y = (x0 - R_x) / D at every cell of
+    the padded grid, ghosts included, against the reference network on the FP64 features of
+    the same R (bfloat16 layer inputs), at the inference test's tolerance; the other planes
+    and the row padding are left untouched."""
+    banner(f"learned guess planes {case}")
+    import torch
+    theta, norm = random_net(7)
+    net = R.Mlp(theta)
+    net.set_norm(norm)
+    wl = sheet(70, 37, seed=5, steps=1) if case == "2d" else WL.two_fluid_sheet_3d(16, 12, 10, steps=1)
+    s = gpu_solver(R, wl)
+    cons, prims = s.initial_state(wl.prims, wl.EB)
+    s.step(s.dt(), cons, prims)
+    a = 0.3 * s.dt()
+    guess = torch.full_like(cons, float("nan"))
+    R.rmhd_learned_guess(s.ctx, net, a, cons, guess)
+    torch.cuda.synchronize()
+    g = grid_of(wl)
+    Rc = s.grid.download_all(cons).reshape(18, -1).T
+    Gc = s.grid.download_all(guess).reshape(18, -1).T
+    sig = g.sigma_cell.reshape(-1) if g.sigma_cell is not None else wl.sigma
+    src = [6, 7, 8, 9, 13, 14, 15]
+    assert np.isfinite(Gc[:, src]).all()
+    assert np.isnan(np.delete(Gc, src, axis=1)).all()
+    # every plane's row padding is left as it was
+    assert torch.isnan(guess[..., s.grid.layout.nxg:]).all()
+    Rg = Rc.copy()
+    Rg[:, src] = Gc[:, src]
+    y = (M.unknowns(Rg, wl.mu1) - M.unknowns(Rc, wl.mu1)) / Rc[:, 0:1]
+    ref = oracle_predict(theta, norm, M.features(Rc, a, sig, wl.mu1), act_bf16=True)
+    ts = split_norm(norm)[3]
+    err = np.abs(y - ref).max(axis=1) / ts.max()
+    print("worst / median error (standardised units)", err.max(), np.median(err))
+    assert err.max() <= 5e-3 and np.median(err) <= 1e-4
+    s.close()
+    net.close()
+
+
 @pytest.fixture(scope="module")
 def trained(R):
     X, T = R.harvest_stages([sheet(64, 64, seed=sd, steps=4) for sd in (41, 42)], 4, (1.0, 0.5, 0.25))
