@@ -243,7 +243,9 @@ typedef struct rmhd_batch_tuning {
                                    (>= max_newton_iter: no queue) */
     int32_t flux_rows;          /* rows of a 2-D flux tile block: 8 or 16 */
     int32_t use_graph;          /* 1: capture the step in a HIP graph and replay it */
-    double step_ms;             /* set by rmhd_batch_autotune: time of the chosen shape */
+    double step_ms;             /* set by rmhd_batch_autotune: time of the chosen shape for one
+                                   implicit stage plus one flux pass (half an SSP2 step; the
+                                   best of three timed repetitions) */
 } rmhd_batch_tuning;
 
 /* Create a batch of n domains (each validated as for rmhd_create; single fluid, 1-D or 2-D,

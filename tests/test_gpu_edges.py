@@ -1,0 +1,106 @@
+"""Degenerate and boundary cases of the GPU path against the oracle: the smallest grids the
+library accepts (4 cells per simulated direction, both boundary conditions, every model),
+zero conductivity (no stiff source in the single-fluid model), and an implicit stage with
+coefficient a = 0, whose solution is its right-hand side."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from paper_1808_09721_amd import workloads as WL
+from tests.oracle_runs import advance, initial_state
+from tests.test_gpu_parity import gpu_solver, rel_linf, run_both, upload_all
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1808_09721_amd import rmhd
+    rmhd.lib()
+    return rmhd
+
+
+@pytest.fixture(scope="module")
+def O(oracle_lib):
+    return oracle_lib
+
+
+def banner(msg):
+    print(f"\n[gpu-case] {msg}", flush=True)
+
+
+def outflow(wl):
+    return dataclasses.replace(wl, bc=WL.BC_OUTFLOW)
+
+
+SMALLEST = {
+    "single fluid 1-D, 4 cells, outflow": lambda: WL.brio_wu_1d(4),
+    "single fluid 4x4, periodic": lambda: WL.kelvin_helmholtz_2d(4, 4, steps=20),
+    "single fluid 4x4, outflow": lambda: outflow(WL.kelvin_helmholtz_2d(4, 4, steps=20)),
+    "two fluid 4x4, periodic": lambda: WL.two_fluid_sheet_2d(4, 4, steps=20),
+    "two fluid 4x4, outflow": lambda: outflow(WL.two_fluid_sheet_2d(4, 4, steps=20)),
+    "ideal 4x4, periodic": lambda: WL.as_ideal(WL.kelvin_helmholtz_2d(4, 4, steps=20)),
+    "single fluid 4x4x4, periodic": lambda: WL.kelvin_helmholtz_3d(4, 4, 4, steps=20),
+}
+
+
+@pytest.mark.parametrize("case", list(SMALLEST))
+def test_smallest_grids_match_oracle(R, O, case):
+    """Every tile of these runs is mostly halo and ghost cells (a wavefront row of 64 lanes
+    holds 4 interior cells, and every interior cell is within two cells of a boundary):
+    20 steps against the oracle at the parity bar, 1e-9 relative L-infinity."""
+    banner(f"smallest grid: {case}")
+    wl = SMALLEST[case]()
+    g, oc, op, gc, gp, st = run_both(R, O, wl, 20)
+    assert st["failures"] == 0
+    err = rel_linf(g.interior(gc), g.interior(oc))
+    print("rel Linf per variable", err)
+    assert np.all(err < 1e-9)
+    assert np.all(rel_linf(g.interior(gp), g.interior(op)) < 1e-9)
+
+
+def test_zero_conductivity_single_fluid_matches_oracle(R, O):
+    """sigma = 0: the current vanishes, E follows the vacuum Maxwell equations and the stage
+    is no longer stiff; 50 steps of the Kelvin-Helmholtz set-up against the oracle."""
+    banner("single fluid, sigma = 0")
+    wl = WL.kelvin_helmholtz_2d(40, 28, sigma=0.0, steps=50)
+    g, oc, op, gc, gp, st = run_both(R, O, wl, 50)
+    assert st["failures"] == 0
+    assert np.all(rel_linf(g.interior(gc), g.interior(oc)) < 1e-9)
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_zero_coefficient_stage_is_identity(R, O, model):
+    """a = 0, the explicit limit of an implicit stage: Q = R on every cell, ghosts included
+    (single fluid bit for bit; two fluid to one rounding, since Sbar and taubar pass through
+    the unknowns scaled by 1/|mu1|), after exactly one Newton step per cell (the polishing
+    step, of length zero), with the primitives of R."""
+    banner(f"implicit stage with a = 0, model={model}")
+    import torch
+    wl = WL.kelvin_helmholtz_2d(40, 24, steps=2) if model == 0 else WL.two_fluid_sheet_2d(40, 24, steps=2)
+    g, oc, op = initial_state(wl)
+    advance(g, oc, op, O.dt(g, 0.5), steps=2)
+    s = gpu_solver(R, wl)
+    Rg = upload_all(R, s.grid, oc)
+    prims = upload_all(R, s.grid, op)
+    Q = s.grid.alloc(g.ncons, fill=float("nan"))
+    st = torch.full((1,) + s.grid.cell_shape, 9, dtype=torch.int8, device="cuda")
+    s.stats(reset=True)
+    R.rmhd_implicit_stage(s.ctx, 0.0, Rg, None, Q, prims, st)
+    torch.cuda.synchronize()
+    stats = s.stats(reset=True)
+    Qh = s.grid.download_all(Q)
+    if model == 0:
+        np.testing.assert_array_equal(Qh, oc)
+    else:
+        assert np.all(np.abs(Qh - oc) <= 2.0 ** -52 * np.abs(oc))
+    assert (s.grid.all_view(st).cpu().numpy() == 0).all()
+    assert stats["failures"] == 0 and stats["newton_max"] == 1
+    assert stats["newton_iters"] == stats["stage_cells"] == wl.nx * wl.ny
+    ow, ost, _ = O.cons2prim(g, oc, op.copy())
+    assert (ost == 0).all()
+    assert np.all(rel_linf(s.grid.download_all(prims), ow) < 1e-12)
+    s.close()
