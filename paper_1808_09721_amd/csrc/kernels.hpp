@@ -252,6 +252,8 @@ struct StageArgs {
     int write_all;
     int stats_detail; // also the Newton-step histogram and the largest final residual
     int use_guess;    // start Newton from guess (plain guess R_x again for a cell that fails)
+    int compare_start;   // with use_guess, two fluid: start at whichever of guess and R_x has
+                         // the smaller residual (one more residual per cell)
     // optional harvest of (features, target) rows of the learned guess, two fluid only:
     // interior cell (i, j) writes row hbase + (j - 2) nx + (i - 2)
     float *hx, *ht;
@@ -438,9 +440,10 @@ __device__ __forceinline__ void stage_write(const StageArgs &A, long idx, int i,
     if (A.iters) A.iters[idx] = nit;
 }
 
-// Implicit stage over every cell, ghosts included.  With a guess the cell starts there (TF:
-// at the better of guess and R_x); a failed cell is solved again from R_x.  A cell still
-// unconverged after A.cap steps is appended to the queue (one atomic per block).
+// Implicit stage over every cell, ghosts included.  With a guess the cell starts there (TF
+// with compare_start: at the better of guess and R_x); a failed cell is solved again from
+// R_x.  A cell still unconverged after A.cap steps is appended to the queue (one atomic per
+// block).
 template <int M>
 __global__ __launch_bounds__(256) void k_stage(StageArgs A)
 {
@@ -465,7 +468,7 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs A)
             if (attempt == 1 && A.use_guess)
 #pragma unroll
                 for (int v = 0; v < NP; ++v) w[v] = A.win.p[v][idx];
-            st = stage_solve<M>(R, A, sig, A.P, x, w, nit, cit, rit, attempt == 0, A.cap, gres);
+            st = stage_solve<M>(R, A, sig, A.P, x, w, nit, cit, rit, attempt == 0 && A.compare_start, A.cap, gres);
             if (st == CELL_OK || st == CELL_QUEUED || attempt == 1) break;
         }
         push = st == CELL_QUEUED;
