@@ -261,6 +261,7 @@ __device__ inline void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Bounded to three wavefronts per SIMD (168 registers), which the kernel fits without spills.
 __global__ __launch_bounds__(256, 3) void k_guess(GuessArgs A)
 {
     __shared__ __attribute__((aligned(16))) unsigned short s_u[4][64][UROW];
