@@ -8,7 +8,9 @@
 //   k_c2p     primitive recovery on every cell (Sec. 2.1.3)
 //   k_stage   implicit-stage Newton solve per cell, ghosts included (Sec. 2.2.1 Eq. 10)
 //   k_flux    FVS + WENO3 flux divergence L (Sec. 2.2.2 Eq. 12), fused with the SSP2 stage
-//             combiners (Eqs. 10-11, Table 2) and with the ghost fill of its first output
+//             combiners (Eqs. 10-11, Table 2), with the ghost fill of its first output and
+//             (single fluid, ideal) the recovery of that output's primitives; on 3-D grids
+//             k_flux forms the x and y terms and k_flux_z adds the z term and does the rest
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -118,27 +120,25 @@ __device__ __forceinline__ int bc_src(int i, int n, int bc)
     return i < 2 ? 2 : n + 1;
 }
 
-// Ghost images of interior cell (ii, jj) (interior coordinates) of a 1-D or 2-D grid under
-// the boundary condition: xi[0] and yj[0] stay the cell's own padded column and row, xi[1..2]
-// and yj[1..2] become the ghost columns and rows that copy it (-1: none).  With ydir false
-// only x images are formed.
+// Ghost images along one direction of n interior cells: v[0] is the padded index of the
+// cell with interior coordinate c, and v[1], v[2] become the ghost indices that copy it under
+// the boundary condition (-1: none).  n >= 4, so a cell has images on one side at most.
+__device__ __forceinline__ void images_1d(int bc, int n, int c, int (&v)[3])
+{
+    if (bc == RMHD_BC_PERIODIC) {
+        if (c < 2) v[1] = v[0] + n;
+        if (c >= n - 2) v[2] = v[0] - n;
+    } else {
+        if (c == 0) { v[1] = 0; v[2] = 1; }
+        if (c == n - 1) { v[1] = n + 2; v[2] = n + 3; }
+    }
+}
+
+// Ghost images of interior cell (ii, jj) (interior coordinates) in x and, with ydir, in y.
 __device__ __forceinline__ void ghost_images(const Geo &g, int ii, int jj, bool ydir, int (&xi)[3], int (&yj)[3])
 {
-    if (g.bc == RMHD_BC_PERIODIC) {
-        if (ii < 2) xi[1] = xi[0] + g.nx;
-        if (ii >= g.nx - 2) xi[2] = xi[0] - g.nx;
-        if (ydir) {
-            if (jj < 2) yj[1] = yj[0] + g.ny;
-            if (jj >= g.ny - 2) yj[2] = yj[0] - g.ny;
-        }
-    } else {
-        if (ii == 0) { xi[1] = 0; xi[2] = 1; }
-        if (ii == g.nx - 1) { xi[1] = g.nx + 2; xi[2] = g.nx + 3; }
-        if (ydir) {
-            if (jj == 0) { yj[1] = 0; yj[2] = 1; }
-            if (jj == g.ny - 1) { yj[1] = g.ny + 2; yj[2] = g.ny + 3; }
-        }
-    }
+    images_1d(g.bc, g.nx, ii, xi);
+    if (ydir) images_1d(g.bc, g.ny, jj, yj);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -203,10 +203,10 @@ __global__ __launch_bounds__(256) void k_init(CPlanes prims, CPlanes EB, Planes 
 // ---------------------------------------------------------------------------------------
 // primitive recovery
 // ---------------------------------------------------------------------------------------
+// Recovery of every cell, starting from the primitives prims holds (updated in place).
 template <int M>
-// guess.p[0] == nullptr: the guesses are read from prims itself.
-__global__ __launch_bounds__(256) void k_c2p(CPlanes cons, CPlanes guess, Planes prims, int8_t *status,
-                                             int32_t *iters, Geo g, Phys P)
+__global__ __launch_bounds__(256) void k_c2p(CPlanes cons, Planes prims, int8_t *status, int32_t *iters, Geo g,
+                                             Phys P)
 {
     constexpr int NC = Model<M>::NC, NP = Model<M>::NP;
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(256) void k_c2p(CPlanes cons, CPlanes guess, Planes
 #pragma unroll
     for (int v = 0; v < NC; ++v) q[v] = cons.p[v][idx];
 #pragma unroll
-    for (int v = 0; v < NP; ++v) w[v] = guess.p[0] ? guess.p[v][idx] : prims.p[v][idx];
+    for (int v = 0; v < NP; ++v) w[v] = prims.p[v][idx];
     int it = 0;
     const int st = cons2prim_m<M>(q, w, P, it);
 #pragma unroll
@@ -604,6 +604,20 @@ __device__ __forceinline__ void store_with_images(double *plane, long zoff, int 
     }
 }
 
+// The same on a 3-D grid: the cell and its x-y images on its own z plane and on each z image
+// plane zk[1], zk[2] (img_xy: the cell has x or y images; img: it has any).
+__device__ __forceinline__ void store_with_images3(double *plane, const Geo &g, const int (&xi)[3],
+                                                   const int (&yj)[3], const int (&zk)[3], bool img_xy, bool img,
+                                                   double val)
+{
+    store_with_images(plane, (long)zk[0] * g.slab, g.pitch, xi, yj, 3, img_xy, val);
+    if (img) {
+#pragma unroll
+        for (int cc = 1; cc < 3; ++cc)
+            if (zk[cc] >= 0) store_with_images(plane, (long)zk[cc] * g.slab, g.pitch, xi, yj, 3, img_xy, val);
+    }
+}
+
 // Primitives of a cell's new state q (guess w), written with the ghost images of the cell.
 template <int M>
 __device__ __forceinline__ void flux_recover(const FluxArgs &A, const double *q, const double *w,
@@ -927,6 +941,8 @@ __global__ __launch_bounds__(BX *BY) void k_flux(FluxArgs A)
 // Lz = -(H_{k+1/2} - H_{k-1/2}) / dz from the split z fluxes reconstructed as in x and y.
 // Blocks of 64 (x) x 16 (z) threads: one x row of one y row per wavefront, the z stencil
 // through LDS with two halo planes on each side (12 interior planes per block, no x halo).
+// This kernel completes output 0, so it also writes that output's ghost images in all three
+// directions (fuse_bc) and recovers its primitives (wnew), as the 2-D tile kernels do.
 // Every thread of the block reaches every barrier.
 template <int M, int NO>
 __global__ __launch_bounds__(1024) void k_flux_z(FluxArgs A)
@@ -953,6 +969,14 @@ __global__ __launch_bounds__(1024) void k_flux_z(FluxArgs A)
 
     const bool interior = ii < g.nx && tz >= 2 && tz < BZ - 2 && kk < g.nz;
     const bool do_z = tz >= 1 && tz <= BZ - 2;
+    // ghost images of this interior cell (output 0 and the recovered primitives)
+    int xi[3] = {i, -1, -1}, yj[3] = {by + 2, -1, -1}, zk[3] = {k, -1, -1};
+    if (A.fuse_bc && interior) {
+        ghost_images(g, ii, by, true, xi, yj);
+        images_1d(g.bc, g.nz, kk, zk);
+    }
+    const bool img_xy = xi[1] >= 0 || xi[2] >= 0 || yj[1] >= 0 || yj[2] >= 0;
+    const bool img = img_xy || zk[1] >= 0 || zk[2] >= 0;
 #pragma unroll
     for (int v0 = 0; v0 < NC; v0 += G) {
         // this round's outputs, read first so that the loads overlap the reconstruction
@@ -989,11 +1013,30 @@ __global__ __launch_bounds__(1024) void k_flux_z(FluxArgs A)
                 const double Lz =
                     -((shp[c][tz][tx] + shm[c][tz + 1][tx]) - (shp[c][tz - 1][tx] + shm[c][tz][tx])) * g.idz;
 #pragma unroll
-                for (int o = 0; o < NO; ++o) A.o[o].out.p[v][idx] = ov[c][o] + A.o[o].cL * Lz;
+                for (int o = 0; o < NO; ++o) {
+                    const double val = ov[c][o] + A.o[o].cL * Lz;
+                    if (o == 0) {
+                        store_with_images3(A.o[0].out.p[v], g, xi, yj, zk, img_xy, img, val);
+                        q[v] = val;   // this thread's own q[v] is not read again
+                    } else {
+                        A.o[o].out.p[v][idx] = val;
+                    }
+                }
             }
         }
         // sfp/sfm are rewritten only after every thread has passed the second barrier above,
         // shp/shm only after the next round's first barrier
+    }
+    // primitives of output 0 (guess: w), with their ghost images; the two-fluid step never
+    // asks for them here (its primitives come from the implicit stage)
+    if (M != 1 && A.wnew.p[0] && interior) {
+        double wn[NP];
+#pragma unroll
+        for (int v = 0; v < NP; ++v) wn[v] = w[v];
+        int it = 0;
+        cons2prim_m<M>(q, wn, A.P, it);
+#pragma unroll
+        for (int v = 0; v < NP; ++v) store_with_images3(A.wnew.p[v], g, xi, yj, zk, img_xy, img, wn[v]);
     }
 }
 

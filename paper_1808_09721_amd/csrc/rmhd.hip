@@ -283,11 +283,15 @@ template <int M, int NO>
 static void launch_flux_mo(rmhd_ctx *c, const FluxArgs &A)
 {
     if (c->prm.ndim == 3) {
-        // x and y terms per interior z plane (64 x 16 tiles), then the z term added in place
+        // x and y terms per interior z plane (64 x 16 tiles), then the z term added in place;
+        // the z kernel completes output 0, so it alone writes the ghost images and recovers
         constexpr int BX = 64;
+        FluxArgs Axy = A;
+        Axy.fuse_bc = 0;
+        Axy.wnew = Planes{};
         const dim3 gxy((unsigned)((c->prm.nx + (BX - 4) - 1) / (BX - 4)), (unsigned)((c->prm.ny + 11) / 12),
                        (unsigned)c->prm.nz);
-        hipLaunchKernelGGL((k_flux<M, 3, BX, 16, NO>), gxy, dim3(BX, 16), 0, c->stream, A);
+        hipLaunchKernelGGL((k_flux<M, 3, BX, 16, NO>), gxy, dim3(BX, 16), 0, c->stream, Axy);
         const dim3 gz((unsigned)((c->prm.nx + BX - 1) / BX), (unsigned)c->prm.ny, (unsigned)((c->prm.nz + 11) / 12));
         hipLaunchKernelGGL((k_flux_z<M, NO>), gz, dim3(BX, 16), 0, c->stream, A);
     } else if (c->prm.ndim == 1) {
@@ -318,24 +322,12 @@ static void launch_flux_m(rmhd_ctx *c, const FluxArgs &A)
     else launch_flux_mo<M, 1>(c, A);
 }
 
-// 3-D: the flux kernels write interior cells only; the ghost images of output 0 are filled by
-// the boundary kernel afterwards, and the step recovers the primitives in a separate kernel.
 static int launch_flux(rmhd_ctx *c, const FluxArgs &A)
 {
-    FluxArgs B = A;
-    if (c->prm.ndim == 3) {
-        if (A.wnew.p[0]) return fail(c, RMHD_EINVAL, "internal: fused recovery on a 3-D grid");
-        B.fuse_bc = 0;
-    }
-    if (c->prm.model == RMHD_SINGLE_FLUID) launch_flux_m<0>(c, B);
-    else if (c->prm.model == RMHD_TWO_FLUID) launch_flux_m<1>(c, B);
-    else launch_flux_m<2>(c, B);
-    int rc = hip_check(c, hipGetLastError(), "k_flux launch");
-    if (!rc && c->prm.ndim == 3 && A.fuse_bc) {
-        hipLaunchKernelGGL(k_bc, cells_grid(c), dim3(256), 0, c->stream, A.o[0].out, (int)c->lay.ncons, c->geo);
-        rc = hip_check(c, hipGetLastError(), "k_bc launch");
-    }
-    return rc;
+    if (c->prm.model == RMHD_SINGLE_FLUID) launch_flux_m<0>(c, A);
+    else if (c->prm.model == RMHD_TWO_FLUID) launch_flux_m<1>(c, A);
+    else launch_flux_m<2>(c, A);
+    return hip_check(c, hipGetLastError(), "k_flux launch");
 }
 
 extern "C" int rmhd_init_state(rmhd_ctx *c, const double *prims, const double *EB, double *cons)
@@ -355,27 +347,25 @@ extern "C" int rmhd_init_state(rmhd_ctx *c, const double *prims, const double *E
     return launch_bc(c, cons, L.ncons);
 }
 
-// Recovery on every cell; guess == nullptr: the guesses are prims' own values.
-static int launch_c2p(rmhd_ctx *c, const double *cons, const double *guess, double *prims, int8_t *status,
-                      int32_t *iters)
+// Recovery on every cell, starting from prims' own values.
+static int launch_c2p(rmhd_ctx *c, const double *cons, double *prims, int8_t *status, int32_t *iters)
 {
     const rmhd_layout &L = c->lay;
     const CPlanes Q = cplanes_of(cons, L, L.ncons);
-    const CPlanes G = guess ? cplanes_of(guess, L, L.nprim) : CPlanes{};
     const Planes W = planes_of(prims, L, L.nprim);
     if (c->prm.model == RMHD_SINGLE_FLUID)
-        hipLaunchKernelGGL(k_c2p<0>, cells_grid(c), dim3(256), 0, c->stream, Q, G, W, status, iters, c->geo, c->phys);
+        hipLaunchKernelGGL(k_c2p<0>, cells_grid(c), dim3(256), 0, c->stream, Q, W, status, iters, c->geo, c->phys);
     else if (c->prm.model == RMHD_TWO_FLUID)
-        hipLaunchKernelGGL(k_c2p<1>, cells_grid(c), dim3(256), 0, c->stream, Q, G, W, status, iters, c->geo, c->phys);
+        hipLaunchKernelGGL(k_c2p<1>, cells_grid(c), dim3(256), 0, c->stream, Q, W, status, iters, c->geo, c->phys);
     else
-        hipLaunchKernelGGL(k_c2p<2>, cells_grid(c), dim3(256), 0, c->stream, Q, G, W, status, iters, c->geo, c->phys);
+        hipLaunchKernelGGL(k_c2p<2>, cells_grid(c), dim3(256), 0, c->stream, Q, W, status, iters, c->geo, c->phys);
     return hip_check(c, hipGetLastError(), "k_c2p launch");
 }
 
 extern "C" int rmhd_cons2prim(rmhd_ctx *c, const double *cons, double *prims, int8_t *status, int32_t *iters)
 {
     if (!c || !cons || !prims) return fail(c, RMHD_EINVAL, "rmhd_cons2prim: NULL argument");
-    return launch_c2p(c, cons, nullptr, prims, status, iters);
+    return launch_c2p(c, cons, prims, status, iters);
 }
 
 extern "C" int rmhd_F(rmhd_ctx *c, double *cons, double *prims, double *Lout)
@@ -511,14 +501,13 @@ static int record_timing(rmhd_ctx *c, int nev, const int *kinds)
 //   SSP3(332)  flux 1: R2 = q^n + dt K1,  R3 = q^n + dt/4 K1,  ACC = q^n + dt/6 K1
 //              flux 2: R3 += dt/4 K(R2),  ACC += dt/6 K(R2)
 //              flux 3: q^{n+1} = ACC + 2 dt/3 K(R3)
-// Each pass writes the ghost images of its first output and recovers its primitives
-// (in the same kernel on 1-D and 2-D grids, in the recovery kernel on 3-D ones), each
-// recovery starting from the primitives of the state the pass read.
+// Each pass writes the ghost images of its first output and recovers its primitives in the
+// kernel that completes that output, each recovery starting from the primitives of the
+// state the pass read.
 static int enqueue_explicit(rmhd_ctx *c, double dt, double *cons, double *prims)
 {
     const rmhd_layout &L = c->lay;
     const bool ssp3 = c->prm.integrator == RMHD_SSP3_332;
-    const bool fused = c->prm.ndim < 3;
     int nev = 0, kinds[7];
     auto begin = [&]() {
         if (c->timing) hipEventRecord(c->ev[nev], c->stream);
@@ -529,7 +518,7 @@ static int enqueue_explicit(rmhd_ctx *c, double dt, double *cons, double *prims)
         nev += 2;
     };
     // one pass reading (q, w), writing outputs with the recovered primitives of output 0 in wout
-    auto pass = [&](const double *q, const double *w, double *out0, double *wout, const FluxOut *o, int n) {
+    auto pass = [&](const double *q, const double *w, double *wout, const FluxOut *o, int n) {
         FluxArgs F{};
         F.q = cplanes_of(q, L, L.ncons);
         F.w = cplanes_of(w, L, L.nprim);
@@ -537,34 +526,30 @@ static int enqueue_explicit(rmhd_ctx *c, double dt, double *cons, double *prims)
         F.P = c->phys;
         F.fuse_bc = 1;
         for (int k = 0; k < n; ++k) F.o[k] = o[k];
-        if (fused) F.wnew = planes_of(wout, L, L.nprim);
+        F.wnew = planes_of(wout, L, L.nprim);
         begin();
         int rc = launch_flux(c, F);
         end(1);
-        if (rc || fused) return rc;
-        begin();
-        rc = launch_c2p(c, out0, w, wout, nullptr, nullptr);
-        end(2);
         return rc;
     };
     int rc;
     if (!ssp3) {
         const FluxOut o1[2] = {flux_out(cons, c->r2, L, dt, dt), flux_out(cons, c->acc, L, 0.5 * dt, 0.5 * dt)};
-        rc = pass(cons, prims, c->r2, c->w1, o1, 2);
+        rc = pass(cons, prims, c->w1, o1, 2);
         if (rc) return rc;
         const FluxOut o2[1] = {flux_out(c->acc, cons, L, 0.5 * dt, 0.5 * dt)};
-        rc = pass(c->r2, c->w1, cons, prims, o2, 1);
+        rc = pass(c->r2, c->w1, prims, o2, 1);
     } else {
         const FluxOut o1[3] = {flux_out(cons, c->r2, L, dt, dt), flux_out(cons, c->r3, L, 0.25 * dt, 0.25 * dt),
                                flux_out(cons, c->acc, L, dt / 6.0, dt / 6.0)};
-        rc = pass(cons, prims, c->r2, c->w1, o1, 3);
+        rc = pass(cons, prims, c->w1, o1, 3);
         if (rc) return rc;
         const FluxOut o2[2] = {flux_out(c->r3, c->r3, L, 0.25 * dt, 0.25 * dt),
                                flux_out(c->acc, c->acc, L, dt / 6.0, dt / 6.0)};
-        rc = pass(c->r2, c->w1, c->r3, c->w2, o2, 2);
+        rc = pass(c->r2, c->w1, c->w2, o2, 2);
         if (rc) return rc;
         const FluxOut o3[1] = {flux_out(c->acc, cons, L, 2.0 * dt / 3.0, 2.0 * dt / 3.0)};
-        rc = pass(c->r3, c->w2, cons, prims, o3, 1);
+        rc = pass(c->r3, c->w2, prims, o3, 1);
     }
     if (rc || !c->timing) return rc;
     return record_timing(c, nev, kinds);
@@ -577,8 +562,8 @@ static int enqueue_imex(rmhd_ctx *c, double dt, double *cons, double *prims)
     const double gm = SSP2_GAMMA;
     const int M = c->prm.model;
     const bool ssp3 = c->prm.integrator == RMHD_SSP3_332;
-    // single fluid: the last flux pass also recovers the primitives (1-D and 2-D)
-    const bool fused = M == RMHD_SINGLE_FLUID && c->prm.ndim < 3;
+    // single fluid: the last flux pass also recovers the primitives
+    const bool fused = M == RMHD_SINGLE_FLUID;
     // event pairs: stages, flux passes, recovery (kinds 0, 1, 2)
     int nev = 0, kinds[7];
     auto begin = [&]() {
