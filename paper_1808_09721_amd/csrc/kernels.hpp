@@ -134,11 +134,26 @@ __device__ __forceinline__ void images_1d(int bc, int n, int c, int (&v)[3])
     }
 }
 
-// Ghost images of interior cell (ii, jj) (interior coordinates) in x and, with ydir, in y.
+// Ghost images of interior cell (ii, jj) (interior coordinates) in x and, with ydir, in y:
+// images_1d in both directions, written with one branch on the boundary condition (the form
+// the 2-D flux kernels compile best with).
 __device__ __forceinline__ void ghost_images(const Geo &g, int ii, int jj, bool ydir, int (&xi)[3], int (&yj)[3])
 {
-    images_1d(g.bc, g.nx, ii, xi);
-    if (ydir) images_1d(g.bc, g.ny, jj, yj);
+    if (g.bc == RMHD_BC_PERIODIC) {
+        if (ii < 2) xi[1] = xi[0] + g.nx;
+        if (ii >= g.nx - 2) xi[2] = xi[0] - g.nx;
+        if (ydir) {
+            if (jj < 2) yj[1] = yj[0] + g.ny;
+            if (jj >= g.ny - 2) yj[2] = yj[0] - g.ny;
+        }
+    } else {
+        if (ii == 0) { xi[1] = 0; xi[2] = 1; }
+        if (ii == g.nx - 1) { xi[1] = g.nx + 2; xi[2] = g.nx + 3; }
+        if (ydir) {
+            if (jj == 0) { yj[1] = 0; yj[2] = 1; }
+            if (jj == g.ny - 1) { yj[1] = g.ny + 2; yj[2] = g.ny + 3; }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------------------
