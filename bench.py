@@ -167,12 +167,12 @@ def learned_measure(steps: int, warmup: int, n: int = 1024, train_n: int = 512, 
 
     wl = WL.learned_guess_sheet(n, seed=5, steps=steps)
     res = {}
-    for mode in ("plain_single_pass", "plain", "learned"):
+    for mode in ("plain_queue", "plain", "learned"):
         s = R.Solver.for_workload(wl)
         c, w = s.initial_state(wl.prims, wl.EB)
         dt = s.dt()
-        if mode == "plain_single_pass":
-            s.set_newton_cap(1000)     # no queue: every wavefront runs to its slowest cell
+        if mode == "plain_queue":
+            s.set_newton_cap(1)        # the stage queue after one Newton step (plain default: none)
         if mode == "learned":
             s.set_guess_model(net)
         for _ in range(warmup):
@@ -212,7 +212,7 @@ def learned_measure(steps: int, warmup: int, n: int = 1024, train_n: int = 512, 
             "cells": wl.cells, "unit": "cell-updates/s", "steps": steps,
             "value": res["learned"]["value"], "plain_value": res["plain"]["value"],
             "speedup_vs_plain": res["plain"]["ms_per_step"] / res["learned"]["ms_per_step"],
-            "plain": res["plain"], "learned": res["learned"], "plain_single_pass": res["plain_single_pass"],
+            "plain": res["plain"], "learned": res["learned"], "plain_queue": res["plain_queue"],
             "training": {"rows": off, "harvest": f"{len(train_seeds)} seeds x {harvest_steps} steps x 2 stages of "
                                                  f"{train_n}x{train_n}, dt factors {list(dt_factors)}",
                          "epochs": epochs, "batch": 16384,

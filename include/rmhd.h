@@ -198,8 +198,9 @@ int rmhd_set_stats_detail(rmhd_ctx *ctx, int detail);
  * cells need instead of what the slowest cell of each wavefront needs.  cap >=
  * max_newton_iter disables the queue and gives the uninterrupted solve bit for bit; a queued
  * cell resumes from its saved unknowns and pressures with a fresh Jacobian, which agrees with
- * the uninterrupted solve to the Newton tolerance.  Default: 1 for the two-fluid model, no
- * queue for the single-fluid model.  cap must be >= 1. */
+ * the uninterrupted solve to the Newton tolerance.  Default (until a cap is set): 1 for
+ * two-fluid stages that start from the learned guess (rmhd_set_guess_model), no queue
+ * otherwise.  cap must be >= 1. */
 int rmhd_set_newton_cap(rmhd_ctx *ctx, int cap);
 
 /* Rows of the 2-D flux-pass thread block: 16 (12 interior rows per 64 x 16 block) or 8

@@ -172,9 +172,8 @@ extern "C" int rmhd_create(const rmhd_params *p, void *stream, rmhd_ctx **out)
     if (e == hipSuccess) e = hipMalloc((void **)&c->status, (size_t)L.plane);
     if (e == hipSuccess) e = hipMalloc((void **)&c->iters, (size_t)L.plane * sizeof(int32_t));
     const int nx_unk = p->model == RMHD_TWO_FLUID ? 7 : 3;
-    // stage queue by default for the two-fluid stage only: its 7-unknown Newton step is
-    // costly enough to repay the second launch; the single-fluid one is not
-    c->cap = p->model == RMHD_TWO_FLUID ? 1 : 1 << 30;
+    // 0: the default cap, chosen per stage launch (launch_stage_m)
+    c->cap = 0;
     if (e == hipSuccess) e = hipMalloc((void **)&c->qidx, (size_t)L.plane * 2 * sizeof(int));
     if (e == hipSuccess) e = hipMalloc((void **)&c->qx, pl * (nx_unk + 2));
     if (e == hipSuccess) e = hipMalloc((void **)&c->qcount, 256);
@@ -234,10 +233,15 @@ static int launch_bc(rmhd_ctx *c, double *arr, int nvar)
     return hip_check(c, hipGetLastError(), "k_bc launch");
 }
 
+// Default cap (none set): the queue with one Newton step in the first pass for two-fluid
+// stages that start from the learned guess, no queue otherwise.  Measured: with the learned
+// guess most cells converge after one step, and the queue takes the 1024^2 sheet's step from
+// 1.76 to 1.62 ms; from the plain guess the queue is 12-14 % slower on the 512^2 and 128^3
+// sheets (equal on 1024^2), and slower on every single-fluid grid measured.
 template <int M>
-static int launch_stage_m(rmhd_ctx *c, StageArgs B)
+static int launch_stage_m(rmhd_ctx *c, StageArgs B, bool learned = false)
 {
-    B.cap = c->cap;
+    B.cap = c->cap ? c->cap : (learned ? 1 : 1 << 30);
     B.stats_detail = c->stats_detail;
     B.qcap = (int)c->lay.plane;
     B.qidx = c->qidx;
@@ -276,7 +280,7 @@ static int launch_stage(rmhd_ctx *c, const StageArgs &A)
         B.hbase = c->hcount;
         c->hcount += cells;
     }
-    return launch_stage_m<1>(c, B);
+    return launch_stage_m<1>(c, B, B.use_guess && !A.use_guess);
 }
 
 template <int M, int NO>
