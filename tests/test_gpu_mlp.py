@@ -310,6 +310,37 @@ def test_bad_network_falls_back_to_plain_guess(R, O):
     net.close()
 
 
+def test_default_stage_queue_follows_the_starting_guess(R):
+    """Without an explicit Newton cap, a plain two-fluid stage runs as one uncapped pass and a
+    stage started from the learned guess uses the queue after one Newton step: each default
+    run equals the run with that cap set explicitly, bit for bit."""
+    banner("default stage queue")
+    theta, norm = random_net(9, scale=0.01)
+    net = R.Mlp(theta)
+    net.set_norm(norm)
+    wl = sheet(40, 28, seed=6, steps=3)
+
+    def run(cap, model):
+        s = gpu_solver(R, wl)
+        if cap is not None:
+            s.set_newton_cap(cap)
+        cons, prims = s.initial_state(wl.prims, wl.EB)
+        if model is not None:
+            s.set_guess_model(model)
+        for _ in range(wl.steps):
+            s.step(s.dt(), cons, prims)
+        out = (s.grid.download_all(cons), s.grid.download_all(prims), s.stats())
+        s.close()
+        return out
+
+    for model, cap in ((None, 1000), (net, 1)):
+        a, b = run(None, model), run(cap, model)
+        np.testing.assert_array_equal(a[0], b[0])
+        np.testing.assert_array_equal(a[1], b[1])
+        assert a[2]["newton_iters"] == b[2]["newton_iters"] and a[2]["failures"] == 0
+    net.close()
+
+
 def test_learned_guess_gain(R, trained):
     """Newton iterations per cell and stage with and without the network, at the same final
     residual tolerance, on a held-out seed."""
