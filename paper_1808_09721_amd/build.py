@@ -15,8 +15,7 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    # multiply-adds are fused only within one source expression, so a device function
-    # rounds the same way in every kernel it is inlined into
+    # multiply-adds are fused only within one source expression, never across statements
     "-ffp-contract=on",
     "-I", os.path.join(ROOT, "include"),
     "-Wno-unused-command-line-argument",
