@@ -44,6 +44,7 @@ struct BatchArgs {
     double *qx, *qp;            // their current unknowns (3 per entry) and pressure
     int qcap;
     unsigned long long *stats;
+    unsigned long long *wstats;  // per-wavefront slots of the basic counters (detail off), or nullptr
 };
 
 // source-carrying single-fluid components in the order of the scratch planes
@@ -118,6 +119,11 @@ __global__ __launch_bounds__(256) void kb_stage(BatchArgs A)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int grabbed = 0, pos_in_item = 0;
     int item = A.persistent ? -1 : (int)blockIdx.x;
+    // basic counters: per-lane sums over this block's chunks, one wavefront slot write at the end
+    const bool wave_stats = A.stats && A.wstats && !A.stats_detail;
+    WaveStats ws{};
+    if (wave_stats) wave_stats_begin(A.wstats, ws);
+    unsigned a_cells = 0, a_nit = 0, a_nmax = 0, a_cit = 0, a_fail = 0, a_rit = 0;
     for (;;) {
         if (A.persistent) {
             if (pos_in_item == 0 || pos_in_item >= A.chunks_per_item) {
@@ -170,12 +176,22 @@ __global__ __launch_bounds__(256) void kb_stage(BatchArgs A)
         }
         if (A.stats) {
             const bool c = live && is_interior(g, i, j);
-            stats_block_add(A.stats, c, c ? nit : 0, c ? nit : 0, c ? cit : 0, c && !push && st != CELL_OK,
-                            c ? rit : 0, c && !push ? nit : -1, gres, A.stats_detail != 0);
+            if (wave_stats) {
+                a_cells += c;
+                a_nit += c ? nit : 0;
+                a_nmax = max(a_nmax, c ? (unsigned)nit : 0u);
+                a_cit += c ? cit : 0;
+                a_fail += c && !push && st != CELL_OK;
+                a_rit += c ? rit : 0;
+            } else {
+                stats_block_add(A.stats, c, c ? nit : 0, c ? nit : 0, c ? cit : 0, c && !push && st != CELL_OK,
+                                c ? rit : 0, c && !push ? nit : -1, gres, A.stats_detail != 0);
+            }
         }
         if (!A.persistent) break;
         __syncthreads();  // s_wcount / s_base are rewritten by the next chunk
     }
+    if (wave_stats) wave_stats_end(ws, a_cells, a_nit, a_nmax, a_cit, a_fail, a_rit);
 }
 
 // Drain the queue: each lane continues one queued cell from its saved unknowns.  The grid is
@@ -189,6 +205,9 @@ __global__ __launch_bounds__(256) void kb_drain(BatchArgs A)
     int nit = 0, cit = 0, rit = 0, st = CELL_OK, done_it = 0;
     double gres = 0.0;
     bool interior = false;
+    const bool wave_stats = A.stats && A.wstats && !A.stats_detail;
+    WaveStats ws{};
+    if (wave_stats) wave_stats_begin(A.wstats, ws);
     if (live) {
         const DomainDev &D = A.dom[A.qdom[e]];
         const long idx = A.qidx[e];
@@ -201,8 +220,11 @@ __global__ __launch_bounds__(256) void kb_drain(BatchArgs A)
     // the cell was counted by kb_stage; only iterations and failures are added here
     if (A.stats) {
         const bool c = live && interior;
-        stats_block_add(A.stats, 0u, c ? nit : 0, c ? nit + done_it : 0, c ? cit : 0, c && st != CELL_OK, c ? rit : 0,
-                        c ? nit + done_it : -1, gres, A.stats_detail != 0);
+        if (wave_stats)
+            wave_stats_end(ws, 0u, c ? nit : 0, c ? nit + done_it : 0, c ? cit : 0, c && st != CELL_OK, c ? rit : 0);
+        else
+            stats_block_add(A.stats, 0u, c ? nit : 0, c ? nit + done_it : 0, c ? cit : 0, c && st != CELL_OK,
+                            c ? rit : 0, c ? nit + done_it : -1, gres, A.stats_detail != 0);
     }
 }
 
@@ -308,6 +330,8 @@ struct rmhd_batch {
     int qcap = 0;
     int max_newton = 50;
     unsigned long long *stats = nullptr;
+    unsigned long long *wstats = nullptr;   // per-wavefront counter slots (folded on read)
+    long nwslots = 0;
     rmhd_batch_tuning tune{};
     int stats_detail = 0;
     hipGraph_t graph = nullptr;
@@ -352,6 +376,7 @@ extern "C" void rmhd_batch_destroy(rmhd_batch *b)
     hipFree(b->qx);
     hipFree(b->qp);
     hipFree(b->stats);
+    hipFree(b->wstats);
     delete b;
 }
 
@@ -447,6 +472,18 @@ extern "C" int rmhd_batch_create(const rmhd_params *domains, int n, void *stream
     const size_t sb = (size_t)STATS_SLOTS * STATS_STRIDE * sizeof(unsigned long long);
     if (e == hipSuccess) e = hipMalloc((void **)&b->stats, sb);
     if (e == hipSuccess) e = hipMemset(b->stats, 0, sb);
+    {
+        // slots for the default launch shapes (a larger persistent grid set by the caller
+        // falls back to the block-level counters)
+        int dev = 0, ncu = 0;
+        hipGetDevice(&dev);
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        const long blocks = std::max({(long)b->nitems, 8L * std::max(1, ncu), (long)((b->qcap + 255) / 256)});
+        b->nwslots = blocks * 4;
+        const size_t wb = (size_t)b->nwslots * STATS_WAVE * sizeof(unsigned long long);
+        if (e == hipSuccess) e = hipMalloc((void **)&b->wstats, wb);
+        if (e == hipSuccess) e = hipMemset(b->wstats, 0, wb);
+    }
     if (e == hipSuccess) e = hipMemset(b->counters, 0, 8 * sizeof(unsigned));
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     if (e != hipSuccess) return bfail(b, e == hipErrorOutOfMemory ? RMHD_ENOMEM : RMHD_EHIP,
@@ -485,6 +522,7 @@ static int enqueue_step(rmhd_batch *b, hipStream_t s)
     A.stats = b->stats;
     const dim3 sgrid(T.persistent ? (unsigned)std::max(1, T.persistent_blocks) : (unsigned)b->nitems);
     const dim3 dgrid((unsigned)((b->qcap + 255) / 256));
+    A.wstats = (long)std::max(sgrid.x, dgrid.x) * 4 <= b->nwslots ? b->wstats : nullptr;
     BatchFluxArgs F{};
     F.dom = b->ddom;
     for (int phase = 1; phase <= 2; ++phase) {
@@ -689,7 +727,9 @@ extern "C" int rmhd_batch_get_stats(rmhd_batch *b, rmhd_stats *out, int reset)
 {
     if (!b || !out) return bfail(b, RMHD_EINVAL, "rmhd_batch_get_stats: NULL argument");
     unsigned long long raw[STATS_SLOTS * STATS_STRIDE];
-    int rc = bcheck(b, hipMemcpyAsync(raw, b->stats, sizeof(raw), hipMemcpyDeviceToHost, b->stream), "stats copy");
+    hipLaunchKernelGGL(k_wave_stats_fold, dim3(1), dim3(256), 0, b->stream, b->wstats, b->nwslots, b->stats);
+    int rc = bcheck(b, hipGetLastError(), "k_wave_stats_fold launch");
+    if (!rc) rc = bcheck(b, hipMemcpyAsync(raw, b->stats, sizeof(raw), hipMemcpyDeviceToHost, b->stream), "stats copy");
     if (!rc && reset) rc = bcheck(b, hipMemsetAsync(b->stats, 0, sizeof(raw), b->stream), "stats reset");
     if (!rc) rc = bcheck(b, hipStreamSynchronize(b->stream), "stats sync");
     if (rc) return rc;

@@ -261,6 +261,7 @@ struct StageArgs {
     int8_t *status;
     int32_t *iters;
     unsigned long long *stats;  // [0] cells [1] newton [2] c2p [3] failures [4] newton max [5] residuals
+    unsigned long long *wstats; // per-wavefront slots of the basic counters (detail off), or nullptr
     double a;
     Geo g;
     Phys P;
@@ -370,6 +371,69 @@ __device__ __forceinline__ void stats_block_add(unsigned long long *stats, unsig
     __syncthreads();  // red[] may be reused by a following call in the same block
 }
 
+// The basic counters without block barriers or atomics (used while the detailed statistics
+// are off): every wavefront of a launch owns one slot of STATS_WAVE counters in wstats, at
+// its index in the launch.  It reads its slot when it starts, so the load is long done by
+// its end, when its first lane writes back the slot plus the wavefront's totals.  Launches
+// on one stream run one after another, so a slot never has two writers at once;
+// rmhd_get_stats folds the slots into the counters.  Measured: the block reduction and
+// atomics of stats_block_add cost ~3 us per stage launch on the 256 x 512 grid, where every
+// block ends at about the same time.
+constexpr int STATS_WAVE = 8;   // [0] cells [1] newton [2] c2p [3] failures [4] newton max [5] residuals
+}  // namespace rmhd
+// wavefront sum of the device library (its 32-bit and max forms are declared by HIP itself)
+extern "C" __device__ __attribute__((const)) unsigned long long __ockl_wfred_add_u64(unsigned long long);
+namespace rmhd {
+struct WaveStats {
+    unsigned long long *slot;
+    unsigned long long old[6];
+};
+__device__ __forceinline__ void wave_stats_begin(unsigned long long *wstats, WaveStats &ws)
+{
+    ws.slot = wstats + ((long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * STATS_WAVE;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) ws.old[k] = ws.slot[k];
+}
+__device__ __forceinline__ void wave_stats_end(const WaveStats &ws, unsigned cells, unsigned nit, unsigned nmax,
+                                               unsigned cit, unsigned fail, unsigned rit)
+{
+    // the device library's wavefront reductions (cross-lane data-parallel moves, much shorter
+    // than a shuffle tree); a wavefront's totals fit 32 bits except the recovery iterations
+    const unsigned long long v[6] = {__ockl_wfred_add_u32(cells), __ockl_wfred_add_u32(nit),
+                                     __ockl_wfred_add_u64(cit), __ockl_wfred_add_u32(fail),
+                                     (unsigned long long)__ockl_wfred_max_i32((int)nmax), __ockl_wfred_add_u32(rit)};
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) ws.slot[k] = k == 4 ? max(ws.old[k], v[k]) : ws.old[k] + v[k];
+    }
+}
+
+// Fold the wavefront slots into slot 0 of the counters and clear them (one block).
+static __global__ __launch_bounds__(256) void k_wave_stats_fold(unsigned long long *wstats, long nslots,
+                                                                unsigned long long *stats)
+{
+    __shared__ unsigned long long red[256][6];
+    unsigned long long t[6] = {0, 0, 0, 0, 0, 0};
+    for (long sl = threadIdx.x; sl < nslots; sl += blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const unsigned long long x = wstats[sl * STATS_WAVE + k];
+            t[k] = k == 4 ? max(t[k], x) : t[k] + x;
+            wstats[sl * STATS_WAVE + k] = 0;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) red[threadIdx.x][k] = t[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int r = 1; r < (int)blockDim.x; ++r)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) t[k] = k == 4 ? max(t[k], red[r][k]) : t[k] + red[r][k];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) stats[k] = k == 4 ? max(stats[k], t[k]) : stats[k] + t[k];
+    }
+}
+
 // Starting unknowns of a cell: the caller's guess planes, or the plain guess R_x.
 template <int M>
 __device__ __forceinline__ void stage_start(const StageArgs &A, long idx, bool guess, double (&x)[Model<M>::NX])
@@ -471,6 +535,9 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs A)
     int nit = 0, cit = 0, rit = 0, st = CELL_OK;
     bool push = false;
     double x[NX], w[NP], gres = 0.0;
+    const bool wave_stats = A.stats && A.wstats && !A.stats_detail;
+    WaveStats ws{};
+    if (wave_stats) wave_stats_begin(A.wstats, ws);
     if (live) {
         const double sig = cell_sigma(A.P, idx);
         double R[NC];
@@ -517,8 +584,12 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs A)
     }
     if (A.stats) {
         const bool c = live && is_interior(g, i, j);
-        stats_block_add(A.stats, c, c ? nit : 0, c && !push ? nit : 0, c ? cit : 0, c && !push && st != CELL_OK,
-                        c ? rit : 0, c && !push ? nit : -1, gres, A.stats_detail != 0);
+        if (wave_stats)
+            wave_stats_end(ws, c, c ? nit : 0, c && !push ? nit : 0, c ? cit : 0, c && !push && st != CELL_OK,
+                           c ? rit : 0);
+        else
+            stats_block_add(A.stats, c, c ? nit : 0, c && !push ? nit : 0, c ? cit : 0, c && !push && st != CELL_OK,
+                            c ? rit : 0, c && !push ? nit : -1, gres, A.stats_detail != 0);
     }
 }
 
@@ -536,6 +607,9 @@ __global__ __launch_bounds__(256) void k_drain(StageArgs A)
     int nit = 0, cit = 0, rit = 0, st = CELL_OK, done = 0;
     bool interior = false;
     double gres = 0.0;
+    const bool wave_stats = A.stats && A.wstats && !A.stats_detail;
+    WaveStats ws{};
+    if (wave_stats) wave_stats_begin(A.wstats, ws);
     if (e < tail) {
         const long idx = A.qidx[e];
         const int i = (int)(idx % g.pitch), j = (int)(idx / g.pitch);
@@ -569,8 +643,11 @@ __global__ __launch_bounds__(256) void k_drain(StageArgs A)
     // the cell was counted by k_stage; iterations, the maximum and failures are added here
     if (A.stats) {
         const bool c = e < tail && interior;
-        stats_block_add(A.stats, 0u, c ? nit : 0, c ? done + nit : 0, c ? cit : 0, c && st != CELL_OK, c ? rit : 0,
-                        c ? done + nit : -1, gres, A.stats_detail != 0);
+        if (wave_stats)
+            wave_stats_end(ws, 0u, c ? nit : 0, c ? done + nit : 0, c ? cit : 0, c && st != CELL_OK, c ? rit : 0);
+        else
+            stats_block_add(A.stats, 0u, c ? nit : 0, c ? done + nit : 0, c ? cit : 0, c && st != CELL_OK, c ? rit : 0,
+                            c ? done + nit : -1, gres, A.stats_detail != 0);
     }
 }
 

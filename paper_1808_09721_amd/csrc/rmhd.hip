@@ -32,6 +32,8 @@ struct rmhd_ctx {
     int8_t *status;   // one plane
     int32_t *iters;   // one plane
     unsigned long long *stats;  // STATS_SLOTS x STATS_STRIDE counters
+    unsigned long long *wstats; // nwslots x STATS_WAVE per-wavefront counters (folded on read)
+    long nwslots;
     // learned starting guess (two fluid): network, and the seven planes it writes
     const rmhd_mlp *mlp;
     double *guess;
@@ -184,6 +186,11 @@ extern "C" int rmhd_create(const rmhd_params *p, void *stream, rmhd_ctx **out)
     const size_t stats_bytes = (size_t)STATS_SLOTS * STATS_STRIDE * sizeof(unsigned long long);
     if (e == hipSuccess) e = hipMalloc((void **)&c->stats, stats_bytes);
     if (e == hipSuccess) e = hipMemsetAsync(c->stats, 0, stats_bytes, c->stream);
+    // one slot per wavefront of a stage launch (k_stage and k_drain use the same grid)
+    c->nwslots = (long)((L.plane + 255) / 256) * 4;
+    const size_t wstats_bytes = (size_t)c->nwslots * STATS_WAVE * sizeof(unsigned long long);
+    if (e == hipSuccess) e = hipMalloc((void **)&c->wstats, wstats_bytes);
+    if (e == hipSuccess) e = hipMemsetAsync(c->wstats, 0, wstats_bytes, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         std::string m = std::string("scratch allocation: ") + hipGetErrorString(e);
@@ -218,6 +225,7 @@ extern "C" void rmhd_destroy(rmhd_ctx *c)
     hipFree(c->status);
     hipFree(c->iters);
     hipFree(c->stats);
+    hipFree(c->wstats);
     hipFree(c->guess);
     hipFree(c->qidx);
     hipFree(c->qx);
@@ -407,6 +415,7 @@ extern "C" int rmhd_implicit_stage(rmhd_ctx *c, double a, const double *R, const
     A.status = status;
     A.iters = iters;
     A.stats = c->stats;
+    A.wstats = c->wstats;
     A.a = a;
     A.g = c->geo;
     A.P = c->phys;
@@ -593,6 +602,7 @@ static int enqueue_imex(rmhd_ctx *c, double dt, double *cons, double *prims)
     S.status = c->status;
     S.iters = c->iters;
     S.stats = c->stats;
+    S.wstats = c->wstats;
     S.a = gm * dt;
     S.g = c->geo;
     S.P = c->phys;
@@ -719,7 +729,9 @@ extern "C" int rmhd_get_stats(rmhd_ctx *c, rmhd_stats *out, int reset)
 {
     if (!c || !out) return fail(c, RMHD_EINVAL, "rmhd_get_stats: NULL argument");
     unsigned long long raw[STATS_SLOTS * STATS_STRIDE];
-    int rc = hip_check(c, hipMemcpyAsync(raw, c->stats, sizeof(raw), hipMemcpyDeviceToHost, c->stream), "stats copy");
+    hipLaunchKernelGGL(k_wave_stats_fold, dim3(1), dim3(256), 0, c->stream, c->wstats, c->nwslots, c->stats);
+    int rc = hip_check(c, hipGetLastError(), "k_wave_stats_fold launch");
+    if (!rc) rc = hip_check(c, hipMemcpyAsync(raw, c->stats, sizeof(raw), hipMemcpyDeviceToHost, c->stream), "stats copy");
     if (!rc && reset) rc = hip_check(c, hipMemsetAsync(c->stats, 0, sizeof(raw), c->stream), "stats reset");
     if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "stats sync");
     if (rc) return rc;
