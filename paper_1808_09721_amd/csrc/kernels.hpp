@@ -668,6 +668,8 @@ struct FluxOut {
 };
 constexpr int FLUX_MAXOUT = 3;
 
+// Apart from q, every set of planes here lies g.plane doubles apart from its first plane (the
+// tile kernels read only p[0] of them).
 struct FluxArgs {
     CPlanes q, w;
     FluxOut o[FLUX_MAXOUT];   // outputs 0 .. n-1 used (the launch fixes n), the rest ignored
@@ -679,6 +681,15 @@ struct FluxArgs {
     // (halo cells of other tiles still read w)
     Planes wnew;
 };
+
+// Plane v of a set whose planes lie g.plane doubles apart, as the outputs, bases and
+// primitives of every flux pass do (only q mixes planes of several arrays): one pointer per
+// set rather than one per variable keeps the tile kernels within their scalar registers.
+template <typename P>
+__device__ __forceinline__ auto plane_at(const P &s, int v, const Geo &g)
+{
+    return s.p[0] + (long)v * g.plane;
+}
 
 // Store a cell's value and, where the cell has ghost images (img), the images too: the
 // image loop sits behind one branch, which whole wavefronts away from the boundary skip.
@@ -723,7 +734,7 @@ __device__ __forceinline__ void flux_recover(const FluxArgs &A, const double *q,
     cons2prim_m<M>(q, wn, A.P, it);
     const bool img = xi[1] >= 0 || xi[2] >= 0 || yj[1] >= 0 || yj[2] >= 0;
 #pragma unroll
-    for (int v = 0; v < NP; ++v) store_with_images(A.wnew.p[v], zoff, A.g.pitch, xi, yj, ny_img, img, wn[v]);
+    for (int v = 0; v < NP; ++v) store_with_images(plane_at(A.wnew, v, A.g), zoff, A.g.pitch, xi, yj, ny_img, img, wn[v]);
 }
 
 // WENO3 value at the downwind face of b from the upwind-ordered stencil (a, b, c):
@@ -772,7 +783,7 @@ __device__ __forceinline__ void flux_tile_lds(const FluxArgs &A, int bx, int by,
 #pragma unroll
     for (int v = 0; v < NC; ++v) q[v] = A.q.p[v][idx];
 #pragma unroll
-    for (int v = 0; v < NP; ++v) w[v] = A.w.p[v][idx];
+    for (int v = 0; v < NP; ++v) w[v] = plane_at(A.w, v, g)[idx];
     const double sig = cell_sigma(A.P, idx);
     flux_source_m<M>(q, w, sig, A.P, fx, fy, src);
 
@@ -791,7 +802,7 @@ __device__ __forceinline__ void flux_tile_lds(const FluxArgs &A, int bx, int by,
         // base terms first, so that their loads overlap the reconstruction
         double bv[NO];
 #pragma unroll
-        for (int k = 0; k < NO; ++k) bv[k] = (interior && A.o[k].base.p[0]) ? A.o[k].base.p[v][idx] : 0.0;
+        for (int k = 0; k < NO; ++k) bv[k] = (interior && A.o[k].base.p[0]) ? plane_at(A.o[k].base, v, g)[idx] : 0.0;
         sfp[0][ty][tx] = 0.5 * (fx[v] + q[v]);
         sfm[0][ty][tx] = 0.5 * (fx[v] - q[v]);
         if constexpr (NDIM == 2) {
@@ -829,9 +840,9 @@ __device__ __forceinline__ void flux_tile_lds(const FluxArgs &A, int bx, int by,
                 const double o = bv[k] + F.cL * L + F.cS * S;
                 if (k == 0) {
                     o0 = o;
-                    store_with_images(F.out.p[v], zoff, g.pitch, xi, yj, NDIM == 2 ? 3 : 1, img, o);
+                    store_with_images(plane_at(F.out, v, g), zoff, g.pitch, xi, yj, NDIM == 2 ? 3 : 1, img, o);
                 } else {
-                    F.out.p[v][idx] = o;
+                    plane_at(F.out, v, g)[idx] = o;
                 }
             }
             q[v] = o0;   // this thread's own q[v] is not read again
@@ -891,7 +902,7 @@ __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by
 #pragma unroll
     for (int v = 0; v < NC; ++v) q[v] = A.q.p[v][idx];
 #pragma unroll
-    for (int v = 0; v < NP; ++v) w[v] = A.w.p[v][idx];
+    for (int v = 0; v < NP; ++v) w[v] = plane_at(A.w, v, g)[idx];
     // quantities shared by the flux components; each round forms only its own components
     const auto I = row_quantities<M>(q, w, cell_sigma(A.P, idx), A.P);
 
@@ -913,7 +924,7 @@ __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by
         for (int k = 0; k < G; ++k)
 #pragma unroll
             for (int kk = 0; kk < NO; ++kk)
-                bv[k][kk] = (v0 + k < NC && interior && A.o[kk].base.p[0]) ? A.o[kk].base.p[v0 + k][idx] : 0.0;
+                bv[k][kk] = (v0 + k < NC && interior && A.o[kk].base.p[0]) ? plane_at(A.o[kk].base, v0 + k, g)[idx] : 0.0;
         double Lx[G];
 #pragma unroll
         for (int k = 0; k < G; ++k) {
@@ -956,9 +967,9 @@ __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by
                     const FluxOut &F = A.o[kk];
                     const double o = bv[k][kk] + F.cL * L + F.cS * S;
                     if (kk == 0) {
-                        store_with_images(F.out.p[v], zoff, g.pitch, xi, yj, 3, img, o);
+                        store_with_images(plane_at(F.out, v, g), zoff, g.pitch, xi, yj, 3, img, o);
                     } else {
-                        F.out.p[v][idx] = o;
+                        plane_at(F.out, v, g)[idx] = o;
                     }
                 }
             }
@@ -971,7 +982,7 @@ __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by
             // the new state, read back from output 0 (written above by this thread)
             double qn[NC];
 #pragma unroll
-            for (int v = 0; v < NC; ++v) qn[v] = A.o[0].out.p[v][idx];
+            for (int v = 0; v < NC; ++v) qn[v] = plane_at(A.o[0].out, v, g)[idx];
             flux_recover<M>(A, qn, w, xi, yj, 3, zoff);
         }
 }
