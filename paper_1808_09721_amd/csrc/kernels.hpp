@@ -1067,7 +1067,7 @@ __global__ __launch_bounds__(1024) void k_flux_z(FluxArgs A)
 #pragma unroll
     for (int v = 0; v < NC; ++v) q[v] = A.q.p[v][idx];
 #pragma unroll
-    for (int v = 0; v < NP; ++v) w[v] = A.w.p[v][idx];
+    for (int v = 0; v < NP; ++v) w[v] = plane_at(A.w, v, g)[idx];
     flux_z_m<M>(q, w, cell_sigma(A.P, idx), A.P, fz);
 
     const bool interior = ii < g.nx && tz >= 2 && tz < BZ - 2 && kk < g.nz;
@@ -1087,7 +1087,7 @@ __global__ __launch_bounds__(1024) void k_flux_z(FluxArgs A)
 #pragma unroll
         for (int c = 0; c < G; ++c)
 #pragma unroll
-            for (int o = 0; o < NO; ++o) ov[c][o] = (v0 + c < NC && interior) ? A.o[o].out.p[v0 + c][idx] : 0.0;
+            for (int o = 0; o < NO; ++o) ov[c][o] = (v0 + c < NC && interior) ? plane_at(A.o[o].out, v0 + c, g)[idx] : 0.0;
 #pragma unroll
         for (int c = 0; c < G; ++c) {
             const int v = v0 + c;
@@ -1119,10 +1119,10 @@ __global__ __launch_bounds__(1024) void k_flux_z(FluxArgs A)
                 for (int o = 0; o < NO; ++o) {
                     const double val = ov[c][o] + A.o[o].cL * Lz;
                     if (o == 0) {
-                        store_with_images3(A.o[0].out.p[v], g, xi, yj, zk, img_xy, img, val);
+                        store_with_images3(plane_at(A.o[0].out, v, g), g, xi, yj, zk, img_xy, img, val);
                         q[v] = val;   // this thread's own q[v] is not read again
                     } else {
-                        A.o[o].out.p[v][idx] = val;
+                        plane_at(A.o[o].out, v, g)[idx] = val;
                     }
                 }
             }
@@ -1139,7 +1139,7 @@ __global__ __launch_bounds__(1024) void k_flux_z(FluxArgs A)
         int it = 0;
         cons2prim_m<M>(q, wn, A.P, it);
 #pragma unroll
-        for (int v = 0; v < NP; ++v) store_with_images3(A.wnew.p[v], g, xi, yj, zk, img_xy, img, wn[v]);
+        for (int v = 0; v < NP; ++v) store_with_images3(plane_at(A.wnew, v, g), g, xi, yj, zk, img_xy, img, wn[v]);
     }
 }
 
