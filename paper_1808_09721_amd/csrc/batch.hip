@@ -727,7 +727,8 @@ extern "C" int rmhd_batch_get_stats(rmhd_batch *b, rmhd_stats *out, int reset)
 {
     if (!b || !out) return bfail(b, RMHD_EINVAL, "rmhd_batch_get_stats: NULL argument");
     unsigned long long raw[STATS_SLOTS * STATS_STRIDE];
-    hipLaunchKernelGGL(k_wave_stats_fold, dim3(1), dim3(256), 0, b->stream, b->wstats, b->nwslots, b->stats);
+    hipLaunchKernelGGL(k_wave_stats_fold, dim3(wave_stats_fold_blocks(b->nwslots)), dim3(256), 0, b->stream, b->wstats,
+                       b->nwslots, b->stats);
     int rc = bcheck(b, hipGetLastError(), "k_wave_stats_fold launch");
     if (!rc) rc = bcheck(b, hipMemcpyAsync(raw, b->stats, sizeof(raw), hipMemcpyDeviceToHost, b->stream), "stats copy");
     if (!rc && reset) rc = bcheck(b, hipMemsetAsync(b->stats, 0, sizeof(raw), b->stream), "stats reset");

@@ -408,13 +408,15 @@ __device__ __forceinline__ void wave_stats_end(const WaveStats &ws, unsigned cel
     }
 }
 
-// Fold the wavefront slots into slot 0 of the counters and clear them (one block).
+// Fold the wavefront slots into slot 0 of the counters and clear them.  Each block folds a
+// strided share of the slots (blocks of 256 threads) and adds its totals with device atomics:
+// integer sums and one maximum, so the result does not depend on the order of the blocks.
 static __global__ __launch_bounds__(256) void k_wave_stats_fold(unsigned long long *wstats, long nslots,
                                                                 unsigned long long *stats)
 {
-    __shared__ unsigned long long red[256][6];
+    __shared__ unsigned long long red[6][256];
     unsigned long long t[6] = {0, 0, 0, 0, 0, 0};
-    for (long sl = threadIdx.x; sl < nslots; sl += blockDim.x) {
+    for (long sl = (long)blockIdx.x * blockDim.x + threadIdx.x; sl < nslots; sl += (long)gridDim.x * blockDim.x) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             const unsigned long long x = wstats[sl * STATS_WAVE + k];
@@ -423,15 +425,28 @@ static __global__ __launch_bounds__(256) void k_wave_stats_fold(unsigned long lo
         }
     }
 #pragma unroll
-    for (int k = 0; k < 6; ++k) red[threadIdx.x][k] = t[k];
+    for (int k = 0; k < 6; ++k) red[k][threadIdx.x] = t[k];
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int r = 1; r < (int)blockDim.x; ++r)
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
 #pragma unroll
-            for (int k = 0; k < 6; ++k) t[k] = k == 4 ? max(t[k], red[r][k]) : t[k] + red[r][k];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) stats[k] = k == 4 ? max(stats[k], t[k]) : stats[k] + t[k];
+            for (int k = 0; k < 6; ++k) {
+                const unsigned long long a = red[k][threadIdx.x], b = red[k][threadIdx.x + h];
+                red[k][threadIdx.x] = k == 4 ? max(a, b) : a + b;
+            }
+        }
+        __syncthreads();
     }
+    if (threadIdx.x < 6) {
+        if (threadIdx.x == 4) atomicMax(&stats[4], red[4][0]);
+        else atomicAdd(&stats[threadIdx.x], red[threadIdx.x][0]);
+    }
+}
+// Blocks for a fold of nslots slots (at least one, at most 256).
+static inline unsigned wave_stats_fold_blocks(long nslots)
+{
+    const long b = (nslots + 255) / 256;
+    return (unsigned)(b < 1 ? 1 : b > 256 ? 256 : b);
 }
 
 // Starting unknowns of a cell: the caller's guess planes, or the plain guess R_x.

@@ -729,7 +729,8 @@ extern "C" int rmhd_get_stats(rmhd_ctx *c, rmhd_stats *out, int reset)
 {
     if (!c || !out) return fail(c, RMHD_EINVAL, "rmhd_get_stats: NULL argument");
     unsigned long long raw[STATS_SLOTS * STATS_STRIDE];
-    hipLaunchKernelGGL(k_wave_stats_fold, dim3(1), dim3(256), 0, c->stream, c->wstats, c->nwslots, c->stats);
+    hipLaunchKernelGGL(k_wave_stats_fold, dim3(wave_stats_fold_blocks(c->nwslots)), dim3(256), 0, c->stream, c->wstats,
+                       c->nwslots, c->stats);
     int rc = hip_check(c, hipGetLastError(), "k_wave_stats_fold launch");
     if (!rc) rc = hip_check(c, hipMemcpyAsync(raw, c->stats, sizeof(raw), hipMemcpyDeviceToHost, c->stream), "stats copy");
     if (!rc && reset) rc = hip_check(c, hipMemsetAsync(c->stats, 0, sizeof(raw), c->stream), "stats reset");
