@@ -80,8 +80,12 @@ typedef struct rmhd_params {
     double x0, x1, y0, y1;    /* domain; dx = (x1-x0)/nx, dy = (y1-y0)/ny */
     double gamma_eos;         /* Gamma-law index (both species) */
     double sigma;             /* conductivity; two-fluid resistivity eta = 1/sigma */
-    const double *sigma_cell; /* optional device plane of per-cell conductivities (ghosts
-                                 included, same indexing as a state plane), or NULL */
+    const double *sigma_cell; /* optional device plane of per-cell conductivities (same
+                                 indexing as a state plane), or NULL.  Only its interior cells
+                                 are read, once, by rmhd_create: the context keeps its own
+                                 copy and fills that copy's ghost cells by the boundary
+                                 condition, so the caller's ghost values are ignored and the
+                                 plane may be released after rmhd_create returns */
     double mu1, mu2;          /* two-fluid charge-to-mass ratios */
     double kappa;             /* divergence-cleaning damping rate (1 in the paper) */
     double cfl;               /* CFL number for rmhd_dt() */
@@ -134,8 +138,8 @@ typedef struct rmhd_ctx rmhd_ctx;
 int rmhd_layout_of(const rmhd_params *params, rmhd_layout *out);
 
 /* Create a context on the current HIP device: validates params, allocates the library's
- * own scratch (stage buffers, counters) and binds the stream (hipStream_t, NULL = default).
- * The params (and sigma_cell pointer) are copied; sigma_cell must stay valid. */
+ * own scratch (stage buffers, counters, the copy of sigma_cell) and binds the stream
+ * (hipStream_t, NULL = default).  The params are copied; sigma_cell is read before return. */
 int rmhd_create(const rmhd_params *params, void *hip_stream, rmhd_ctx **out);
 void rmhd_destroy(rmhd_ctx *ctx);
 

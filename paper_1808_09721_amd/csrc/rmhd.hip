@@ -34,6 +34,8 @@ struct rmhd_ctx {
     unsigned long long *stats;  // STATS_SLOTS x STATS_STRIDE counters
     unsigned long long *wstats; // nwslots x STATS_WAVE per-wavefront counters (folded on read)
     long nwslots;
+    // per-cell conductivity: the library's own copy of the caller's plane, ghosts filled
+    double *sigma_own;
     // learned starting guess (two fluid): network, and the seven planes it writes
     const rmhd_mlp *mlp;
     double *guess;
@@ -191,6 +193,18 @@ extern "C" int rmhd_create(const rmhd_params *p, void *stream, rmhd_ctx **out)
     const size_t wstats_bytes = (size_t)c->nwslots * STATS_WAVE * sizeof(unsigned long long);
     if (e == hipSuccess) e = hipMalloc((void **)&c->wstats, wstats_bytes);
     if (e == hipSuccess) e = hipMemsetAsync(c->wstats, 0, wstats_bytes, c->stream);
+    // per-cell conductivity: copy the caller's plane (only its interior cells matter) and
+    // fill the copy's ghost cells by the boundary condition, as the state's are
+    if (e == hipSuccess && p->sigma_cell) {
+        e = hipMalloc((void **)&c->sigma_own, pl);
+        if (e == hipSuccess) e = hipMemcpyAsync(c->sigma_own, p->sigma_cell, pl, hipMemcpyDeviceToDevice, c->stream);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_bc, dim3((unsigned)((L.plane + 255) / 256)), dim3(256), 0, c->stream,
+                               planes_of(c->sigma_own, L, 1), 1, c->geo);
+            e = hipGetLastError();
+        }
+        c->phys.sigma_cell = c->sigma_own;
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         std::string m = std::string("scratch allocation: ") + hipGetErrorString(e);
@@ -230,6 +244,7 @@ extern "C" void rmhd_destroy(rmhd_ctx *c)
     hipFree(c->qidx);
     hipFree(c->qx);
     hipFree(c->qcount);
+    hipFree(c->sigma_own);
     delete c;
 }
 

@@ -188,6 +188,8 @@ def rmhd_create(params: rmhd_params, stream=None):
     torch's current stream)."""
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
+    if s != torch.cuda.current_stream():
+        s.wait_stream(torch.cuda.current_stream())   # sigma_cell may have been written there
     ctx = ctypes.c_void_p()
     _check(lib().rmhd_create(ctypes.byref(params), ctypes.c_void_p(s.cuda_stream), ctypes.byref(ctx)))
     return ctx
@@ -326,19 +328,10 @@ class Grid:
         return self.all_view(t).cpu().numpy().copy()
 
     def sigma_plane(self, sigma_interior: np.ndarray):
-        """Per-cell conductivity as one padded device plane, ghosts copied as the boundary
-        condition copies state (periodic wrap or outflow edge)."""
-        import torch
-        mode = "wrap" if self.params.bc == BC_PERIODIC else "edge"
-        if self.ndim == 3:
-            a = np.asarray(sigma_interior, dtype=np.float64).reshape(self.nz, self.ny, self.nx)
-            full = np.pad(a, ((2, 2), (2, 2), (2, 2)), mode=mode)
-        else:
-            a = np.asarray(sigma_interior, dtype=np.float64).reshape(self.ny if self.ndim == 2 else 1, self.nx)
-            full = np.pad(a, ((2, 2) if self.ndim == 2 else (0, 0), (2, 2)), mode=mode)
-        t = self.alloc(1)
-        self.all_view(t)[...] = torch.from_numpy(full[None]).cuda()
-        return t
+        """Per-cell conductivity as one padded device plane with its interior filled (the
+        ghost cells are left NaN: rmhd_create fills its own copy's ghosts)."""
+        return self.upload_interior(np.asarray(sigma_interior, dtype=np.float64)[None], nvar=1,
+                                    fill=float("nan"))
 
 
 class Solver:
@@ -355,7 +348,7 @@ class Solver:
         if wl.sigma_cell is not None:
             sigma = Grid(params_from(wl, **param_kw)).sigma_plane(wl.sigma_cell)
         s = cls(params_from(wl, sigma_cell=sigma, **param_kw), stream)
-        s._sigma_plane = sigma    # kept alive with the context
+        del sigma                 # read by rmhd_create; the context holds its own copy
         return s
 
     def close(self):
@@ -542,6 +535,37 @@ def harvest_stages(workloads, steps: int, dt_factors=(1.0,)):
     if off != rows:
         raise RmhdError(f"harvested {off} rows, expected {rows}")
     return X, T
+
+
+def train_guess_network(train_n: int = 512, seeds=(1, 2, 3, 4), harvest_steps: int = 6,
+                        dt_factors=(1.0, 0.5, 0.25), epochs: int = 8, batch: int = 16384, init_seed: int = 7,
+                        shuffle_seed: int = 11, lr0: float = 3e-3, lr1: float = 1e-4):
+    """The learned guess's network trained on the device: rows harvested from train_n^2
+    two-fluid current sheets with per-cell conductivity 10^U[2, 6] at the given seeds (steps
+    cycling through dt_factors of the CFL step), normalisation fitted on them, then Adam.
+    Returns (network, info dict)."""
+    import time
+
+    import torch
+
+    from . import workloads as WL
+    t0 = time.perf_counter()
+    X, T = harvest_stages([WL.learned_guess_sheet(train_n, seed=sd, steps=harvest_steps) for sd in seeds],
+                          harvest_steps, dt_factors)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    net = Mlp(WL.mlp_initial_params(init_seed))
+    net.fit_norm(X, T)
+    hist = net.train(X, T, batch=batch, epochs=epochs, lr0=lr0, lr1=lr1, seed=shuffle_seed)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    info = {"rows": int(X.shape[0]),
+            "harvest": f"{len(seeds)} seeds x {harvest_steps} steps x 2 stages of {train_n}x{train_n}, "
+                       f"dt factors {list(dt_factors)}",
+            "epochs": epochs, "batch": batch, "loss_first_epoch": float(hist[0]),
+            "loss_last_epoch": float(hist[-1]), "harvest_s": t1 - t0, "train_s": t2 - t1}
+    del X, T
+    return net, info
 
 
 class Mlp:

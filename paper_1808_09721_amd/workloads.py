@@ -383,3 +383,36 @@ def learned_guess_sheet(n: int = 1024, seed: int = 5, steps: int = 10) -> Worklo
     to 1e-2), the workload of the learned starting guess.  Training data come from the same
     set-up at other seeds (the evaluation seed 5 is held out)."""
     return two_fluid_sheet_2d(n, n, seed=seed, steps=steps, sigma_range=(1e2, 1e6))
+
+
+def charged_field(ndim: int, n: int = 32, bc: int = BC_PERIODIC, seed: int = 8, sigma: float = 10.0,
+                  ny: int | None = None, nz: int | None = None) -> Workload:
+    """Single-fluid plasma at rest (rho = 1, p = 1, seeded velocity noise 1e-3 per component)
+    on the unit square / cube with an electric field of nonzero divergence, for the initial
+    charge density of Gauss's law: E_x = sin(2 pi x) cos(2 pi y), E_y = 1/2 cos(2 pi x)
+    sin(4 pi y), E_z = 1/4 sin(2 pi z) (only the components along simulated directions vary
+    along them), B = (0.3, 0, 0.2).  Its divergence is
+    2 pi cos(2 pi x)[cos(2 pi y) + cos(4 pi y)] + pi/2 cos(2 pi z) in 3-D (drop the terms of
+    directions not simulated)."""
+    rng = np.random.default_rng(seed)
+    nx = n
+    ny = (ny or n) if ndim >= 2 else 1
+    nz = (nz or n) if ndim == 3 else 1
+    x = _centres(nx, 0.0, 1.0)
+    y = _centres(ny, 0.0, 1.0) if ndim >= 2 else np.zeros(1)
+    z = _centres(nz, 0.0, 1.0) if ndim == 3 else np.zeros(1)
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    EB = np.zeros((6, nz, ny, nx))
+    EB[0] = 0.3
+    EB[2] = 0.2
+    EB[3] = np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Y)
+    EB[4] = 0.5 * np.cos(2 * np.pi * X) * np.sin(4 * np.pi * Y)
+    EB[5] = 0.25 * np.sin(2 * np.pi * Z)
+    prims = np.zeros((5, nz, ny, nx))
+    prims[0] = 1.0
+    prims[4] = 1.0
+    prims[1:4] = 1e-3 * rng.uniform(-1.0, 1.0, (3, nz, ny, nx))
+    if ndim < 3:
+        prims, EB = prims[:, 0], EB[:, 0]
+    return Workload(f"charged_field_{ndim}d", SINGLE_FLUID, ndim, nx, ny, 0.0, 1.0, 0.0, 1.0, gamma=4.0 / 3.0,
+                    sigma=sigma, bc=bc, steps=0, prims=prims, EB=EB, nz=nz if ndim == 3 else 1, z0=0.0, z1=1.0)

@@ -40,10 +40,14 @@ def sheet3(steps=1):
     return WL.two_fluid_sheet_3d(20, 14, 13, steps=steps)
 
 
-@pytest.mark.parametrize("case", ["khi", "sheet"])
+@pytest.mark.parametrize("case", ["khi", "sheet", "gauss_periodic", "gauss_outflow"])
 def test_3d_init_and_cons2prim_match_oracle(R, O, case):
+    """Initial data and recovery on ragged 3-D tilings; the gauss cases start with a field of
+    nonzero divergence in all three directions (initial charge density, Sec. 2.1.1)."""
     banner(f"3-D init/cons2prim {case}")
-    wl = khi3() if case == "khi" else sheet3()
+    wl = {"khi": khi3, "sheet": sheet3,
+          "gauss_periodic": lambda: WL.charged_field(3, 21, ny=14, nz=13),
+          "gauss_outflow": lambda: WL.charged_field(3, 21, ny=14, nz=13, bc=WL.BC_OUTFLOW)}[case]()
     s = gpu_solver(R, wl)
     cons, prims = s.initial_state(wl.prims, wl.EB)
     g, ocons, oprims = initial_state(wl)

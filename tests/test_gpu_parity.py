@@ -50,19 +50,12 @@ def rel_linf(gpu, ref, mu=None):
 
 
 def gpu_solver(R, wl, **kw):
+    """A context for a workload; a per-cell conductivity is handed over with its interior only
+    (ghost cells NaN): the library fills the ghosts of its own copy."""
     sigma_cell = None
     if wl.sigma_cell is not None:
-        import torch
-        params = R.params_from(wl)
-        grid = R.Grid(params)
-        sc = grid.alloc(1)
-        full = np.zeros((1, grid.layout.nyg, grid.layout.nxg))
-        og = grid_of(wl)
-        full[0] = og.sigma_cell
-        grid.all_view(sc)[...] = torch.from_numpy(full).cuda()
-        sigma_cell = sc
+        sigma_cell = R.Grid(R.params_from(wl, **kw)).sigma_plane(wl.sigma_cell)
     s = R.Solver(R.params_from(wl, sigma_cell=sigma_cell, **kw))
-    s._sigma_cell = sigma_cell
     return s
 
 
@@ -76,11 +69,17 @@ def upload_all(R, grid, arr):
 # ------------------------------------------------------------------------------------------
 # per-kernel parity
 # ------------------------------------------------------------------------------------------
-@pytest.mark.parametrize("case", ["brio_wu", "khi", "sheet"])
+@pytest.mark.parametrize("case", ["brio_wu", "khi", "sheet", "gauss_periodic", "gauss_outflow", "gauss_1d"])
 def test_init_and_cons2prim_match_oracle(R, O, case):
+    """Initial data and recovery; the gauss cases carry an electric field of nonzero
+    divergence, so the initial charge density rho_e = div E (Sec. 2.1.1) is exercised through
+    both boundary maps."""
     banner(f"init/cons2prim {case}")
-    wl = {"brio_wu": WL.brio_wu_1d(), "khi": WL.kelvin_helmholtz_2d(70, 37, steps=1),
-          "sheet": WL.two_fluid_sheet_2d(70, 37, steps=1)}[case]
+    wl = {"brio_wu": lambda: WL.brio_wu_1d(), "khi": lambda: WL.kelvin_helmholtz_2d(70, 37, steps=1),
+          "sheet": lambda: WL.two_fluid_sheet_2d(70, 37, steps=1),
+          "gauss_periodic": lambda: WL.charged_field(2, 70, ny=37),
+          "gauss_outflow": lambda: WL.charged_field(2, 70, ny=37, bc=WL.BC_OUTFLOW),
+          "gauss_1d": lambda: WL.charged_field(1, 301, bc=WL.BC_OUTFLOW)}[case]()
     s = gpu_solver(R, wl)
     cons, prims = s.initial_state(wl.prims, wl.EB)
     g, ocons, oprims = initial_state(wl)
@@ -88,6 +87,33 @@ def test_init_and_cons2prim_match_oracle(R, O, case):
     gp = s.grid.download_all(prims)
     assert np.all(rel_linf(gc, ocons) < 1e-14)
     assert np.all(rel_linf(gp, oprims) < 1e-12)
+    if case.startswith("gauss"):
+        assert np.abs(g.interior(ocons)[11]).max() > 1.0   # a charge density to compare
+
+
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+@pytest.mark.parametrize("bc", [0, 1])
+def test_ghost_fill_matches_oracle(R, O, ndim, bc):
+    """rmhd_F first fills the ghost cells of its state and primitives in place (outflow copy
+    or periodic wrap, corners included): bit for bit the oracle's fill of the same interior,
+    with the ghosts NaN on entry."""
+    banner(f"ghost fill ndim={ndim} bc={bc}")
+    wl = {1: lambda: WL.charged_field(1, 37, bc=bc), 2: lambda: WL.charged_field(2, 70, ny=37, bc=bc),
+          3: lambda: WL.charged_field(3, 21, ny=14, nz=13, bc=bc)}[ndim]()
+    g, ocons, oprims = initial_state(wl)
+    advance(g, ocons, oprims, O.dt(g, 0.5), steps=2)   # structure in every field
+    s = gpu_solver(R, wl)
+    c_in, p_in = ocons.copy(), oprims.copy()
+    ghost = np.ones(c_in.shape[1:], bool)
+    ghost[tuple(slice(2, -2) if n > 1 else slice(None) for n in ghost.shape)] = False
+    c_in[:, ghost] = np.nan
+    p_in[:, ghost] = np.nan
+    cons, prims = upload_all(R, s.grid, c_in), upload_all(R, s.grid, p_in)
+    Lg = s.grid.alloc(g.ncons)
+    R.rmhd_F(s.ctx, cons, prims, Lg)
+    np.testing.assert_array_equal(s.grid.download_all(cons), ocons)
+    np.testing.assert_array_equal(s.grid.download_all(prims), oprims)
+    s.close()
 
 
 @pytest.mark.parametrize("model", [0, 1])
@@ -390,10 +416,26 @@ def family_scale(g, c):
     return tot
 
 
+def roundoff_bound(g, c0, c1, steps, mu=None, c=4.0):
+    """Round-off bound on the change of each conserved total over ``steps`` steps under
+    periodic boundaries: c eps steps max(sum|x| at the start, at the end).  Both cells of a
+    face use the same face flux (it is formed once, or formed identically), so the flux
+    differences telescope exactly and a total changes only by the rounding of each cell's
+    update, a few roundings of terms of the size of |x| per step.  Components of a vector are
+    measured against the vector's total; two-fluid charge-to-mass weighted sums against |mu|
+    times their plain sums (the size of the species terms they cancel)."""
+    eps = np.finfo(np.float64).eps
+    scale = np.maximum(family_scale(g, c0), family_scale(g, c1))
+    if g.ncons == 18:
+        mu = 1000.0 if mu is None else mu
+        scale[5:10] = np.maximum(scale[5:10], abs(mu) * scale[0:5])
+    return c * eps * steps * scale
+
+
 def test_khi_full_size_100_steps(R, O):
-    """Kelvin-Helmholtz at 256 x 512, sigma = 1e3, 100 steps: the benchmark workload.  Also
-    conservation of the source-free components: the GPU's change of each total is within ten
-    times the oracle's round-off change on the same run (or 1e-13 of the total's scale)."""
+    """Kelvin-Helmholtz at 256 x 512, sigma = 1e3, 100 steps: element-wise against the oracle,
+    and conservation of every source-free total (D, S, tau, B, rho_e) within the round-off
+    bound of the GPU's own updates (no reference to the oracle's drift)."""
     banner("KHI 256x512 100 steps")
     wl = WL.kelvin_helmholtz_2d()
     g0, oc0, _ = initial_state(wl)
@@ -403,11 +445,11 @@ def test_khi_full_size_100_steps(R, O):
     print("rel Linf per variable", err)
     assert np.all(err < 1e-9)
     tot0 = g.interior(oc0).sum(axis=(1, 2))
-    d_or = np.abs(g.interior(oc).sum(axis=(1, 2)) - tot0)
     d_gpu = np.abs(g.interior(gc).sum(axis=(1, 2)) - tot0)
-    fam = family_scale(g, oc0)
+    bound = roundoff_bound(g, oc0, gc, 100)
+    print("conservation: change", d_gpu, "bound", bound)
     for v in (0, 1, 2, 3, 4, 5, 6, 7, 11):
-        assert d_gpu[v] <= max(10 * d_or[v], 1e-13 * fam[v]), (v, d_gpu[v], d_or[v])
+        assert d_gpu[v] <= bound[v], (v, d_gpu[v], bound[v])
 
 
 def test_two_fluid_sheet_128_100_steps(R, O):
@@ -444,16 +486,40 @@ def test_two_fluid_sheet_full_size_properties(R, O):
         np.testing.assert_allclose(Qh[:, k], Qo, rtol=1e-12, atol=1e-12 * np.abs(Qo).max())
     c0 = s.grid.download_all(cons)
     tot0 = g.interior(c0).sum(axis=(1, 2))
-    scale = family_scale(g, c0)
-    scale[5:10] = np.maximum(scale[5:10], abs(wl.mu1) * scale[0:5])   # weighted sums vs summands
     s.stats(reset=True)
     for _ in range(100):
         s.step(s.dt(), cons, prims)
     st = s.stats()
     assert st["failures"] == 0 and st["stage_cells"] == 2 * 100 * wl.cells
-    tot = g.interior(s.grid.download_all(cons)).sum(axis=(1, 2))
+    c1 = s.grid.download_all(cons)
+    tot = g.interior(c1).sum(axis=(1, 2))
+    bound = roundoff_bound(g, c0, c1, 100, mu=wl.mu1)
     for v in (0, 1, 2, 3, 4, 5, 10, 11, 12):
-        assert abs(tot[v] - tot0[v]) <= 1e-13 * scale[v], (v, tot[v] - tot0[v], scale[v])
+        assert abs(tot[v] - tot0[v]) <= bound[v], (v, tot[v] - tot0[v], bound[v])
+
+
+@pytest.mark.parametrize("case", ["brio_wu_outflow", "khi_periodic", "sheet_outflow", "sheet_periodic"])
+def test_per_cell_sigma_matches_oracle(R, O, case):
+    """Per-cell conductivity handed over with NaN ghost cells: the library's copy gets its
+    ghosts from the boundary condition (periodic wrap or outflow copy), so every step matches
+    the oracle (whose conductivity ghosts are filled by its own boundary fill) to 1e-9."""
+    banner(f"per-cell sigma {case}")
+    rng = np.random.default_rng(61)
+    if case == "brio_wu_outflow":
+        wl, steps = WL.brio_wu_1d(), 60
+        wl.sigma_cell = 10.0 ** rng.uniform(1.0, 4.0, (1, wl.nx))
+    elif case == "khi_periodic":
+        wl, steps = WL.kelvin_helmholtz_2d(70, 37, steps=30, seed=62), 30
+        wl.sigma_cell = 10.0 ** rng.uniform(1.0, 5.0, (wl.ny, wl.nx))
+    else:
+        wl, steps = WL.two_fluid_sheet_2d(48, 40, steps=30, seed=63, sigma_range=(1e2, 1e6)), 30
+        wl.bc = WL.BC_OUTFLOW if case == "sheet_outflow" else WL.BC_PERIODIC
+    g, oc, op, gc, gp, st = run_both(R, O, wl, steps)
+    assert st["failures"] == 0
+    err = rel_linf(gc, oc)
+    print("rel Linf per variable", err)
+    assert np.all(err < 1e-9)
+    assert np.all(rel_linf(gp, op) < 1e-9)
 
 
 def test_padding_is_never_read(R, O):
