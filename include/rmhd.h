@@ -40,6 +40,7 @@
 #ifndef RMHD_H
 #define RMHD_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -223,6 +224,32 @@ int rmhd_get_timing(rmhd_ctx *ctx, rmhd_timing *out, int reset);
 /* Message of the last failing call on ctx (or of the last failing rmhd_create/layout call
  * when ctx is NULL).  Owned by the library; valid until the next call on the same ctx. */
 const char *rmhd_last_error(const rmhd_ctx *ctx);
+
+/* ------------------------------------------------------------------------------------
+ * The step without allocation, for callers that cannot allocate device memory: code being
+ * captured into a HIP graph, tight serving loops, harnesses that forbid hipMalloc.
+ * rmhd_imex_step_noalloc() does what rmhd_imex_step() does on a context made from *params
+ * (same kernels, results equal bit for bit), but needs no context: its stage scratch lives
+ * in one array of RMHD_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends, and the call itself allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine) and launches kernels only (no memset, no copy), on hip_stream.
+ * Limits: the grid's scratch (rmhd_noalloc_scratch_bytes) must fit the array -- e.g. the
+ * single-fluid 256 x 512 grid needs 41 MB with SSP2(222), 62 MB with SSP3(332) -- else
+ * RMHD_EINVAL; sigma_cell must be NULL (scalar conductivity); no statistics, timing, stage
+ * queue or learned guess.  Every call on one GPU shares that GPU's array: calls that overlap
+ * in time on one GPU (two streams, two threads) race and give wrong results; calls ordered
+ * on one stream are safe.  Nothing in the array has to start at zero.  Errors are reported
+ * by rmhd_last_error(NULL).
+ * ------------------------------------------------------------------------------------ */
+#define RMHD_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* Scratch bytes rmhd_imex_step_noalloc() needs for *params (0 if params are invalid). */
+size_t rmhd_noalloc_scratch_bytes(const rmhd_params *params);
+
+/* One IMEX step of size dt of cons/prims (device arrays laid out as rmhd_layout_of(params)
+ * gives, exactly as for rmhd_imex_step()), enqueued on hip_stream (hipStream_t, NULL =
+ * default), with no context and no allocation. */
+int rmhd_imex_step_noalloc(const rmhd_params *params, void *hip_stream, double dt, double *cons, double *prims);
 
 /* ------------------------------------------------------------------------------------
  * Batched form: many independent single-fluid domains of uneven size and stiffness advanced

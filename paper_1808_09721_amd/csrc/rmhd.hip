@@ -4,6 +4,7 @@
 
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -832,4 +833,104 @@ extern "C" int rmhd_set_graph(rmhd_ctx *c, int enable)
     c->use_graph = enable != 0;
     free_graph(c);
     return RMHD_OK;
+}
+
+// ---- the step without allocation (include/rmhd.h: rmhd_imex_step_noalloc) ---------------
+// The stage scratch of one step (stage-1 source parts and primitives, R2, ACC, and for
+// SSP3(332) R3 and the second stage's primitives) lives in this file-scope array instead
+// of memory allocated by rmhd_create.  Every GPU the library runs on holds its own copy from
+// the time the code object is loaded until the process ends.  In host code the name only
+// stands in for the symbol: the device address of each GPU's copy comes from
+// hipGetSymbolAddress with that GPU current, and only that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[RMHD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];   // device address of scratch per device, once looked up
+}  // namespace
+
+// Address of the current device's copy of scratch (looked up once per device).
+static int noalloc_scratch(void **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(nullptr, RMHD_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(nullptr, RMHD_EINVAL, "rmhd_imex_step_noalloc: device index too large");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(nullptr, RMHD_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return RMHD_OK;
+}
+
+// Bytes of scratch one step of this parameter set needs (each part rounded up to 256 bytes).
+static size_t noalloc_bytes(const rmhd_params *p, const rmhd_layout &L)
+{
+    const size_t pl = ((size_t)L.plane * sizeof(double) + 255) & ~(size_t)255;
+    const int nsrc = p->model == RMHD_SINGLE_FLUID ? 5 : p->model == RMHD_TWO_FLUID ? 9 : 1;
+    size_t n = (size_t)nsrc + L.nprim + 2 * (size_t)L.ncons;
+    if (p->integrator == RMHD_SSP3_332) n += (size_t)L.ncons + L.nprim;
+    return n * pl;
+}
+
+extern "C" size_t rmhd_noalloc_scratch_bytes(const rmhd_params *p)
+{
+    if (check_params_impl(p, nullptr)) return 0;
+    rmhd_layout L;
+    layout_from(p, &L);
+    return noalloc_bytes(p, L);
+}
+
+extern "C" int rmhd_imex_step_noalloc(const rmhd_params *p, void *hip_stream, double dt, double *cons, double *prims)
+{
+    int rc = check_params_impl(p, nullptr);
+    if (rc) return rc;
+    if (!cons || !prims) return fail(nullptr, RMHD_EINVAL, "rmhd_imex_step_noalloc: NULL argument");
+    if (!(dt > 0.0)) return fail(nullptr, RMHD_EINVAL, "rmhd_imex_step_noalloc: dt must be > 0");
+    if (p->sigma_cell)
+        return fail(nullptr, RMHD_EINVAL,
+                    "rmhd_imex_step_noalloc: per-cell conductivity needs a context (rmhd_create keeps a ghost-filled copy)");
+    rmhd_ctx c{};
+    c.prm = *p;
+    layout_from(p, &c.lay);
+    const size_t need = noalloc_bytes(p, c.lay);
+    if (need > (size_t)RMHD_NOALLOC_SCRATCH_BYTES)
+        return fail(nullptr, RMHD_EINVAL,
+                    "rmhd_imex_step_noalloc: grid needs " + std::to_string(need) + " bytes of scratch, more than the " +
+                        std::to_string((size_t)RMHD_NOALLOC_SCRATCH_BYTES) + " the library holds; use rmhd_create");
+    void *base = nullptr;
+    rc = noalloc_scratch(&base);
+    if (rc) return rc;
+    c.stream = (hipStream_t)hip_stream;
+    c.geo = geo_from(p, c.lay);
+    c.phys = phys_from(p);
+    hipGetDevice(&c.device);
+    const size_t pl = ((size_t)c.lay.plane * sizeof(double) + 255) & ~(size_t)255;
+    unsigned char *s = (unsigned char *)base;
+    auto take = [&](int nplanes) {
+        double *q = (double *)s;
+        s += (size_t)nplanes * pl;
+        return q;
+    };
+    const int nsrc = p->model == RMHD_SINGLE_FLUID ? 5 : p->model == RMHD_TWO_FLUID ? 9 : 1;
+    // every plane below is written before it is read within the step, so nothing is cleared;
+    // no statistics, status or iteration planes and no stage queue (cap left at the plain
+    // default, which is none)
+    c.q1src = take(nsrc);
+    c.w1 = take(c.lay.nprim);
+    c.r2 = take(c.lay.ncons);
+    c.acc = take(c.lay.ncons);
+    if (p->integrator == RMHD_SSP3_332) {
+        c.r3 = take(c.lay.ncons);
+        c.w2 = take(c.lay.nprim);
+    }
+    rc = enqueue_imex(&c, dt, cons, prims);
+    if (rc) g_err = c.err;
+    return rc;
 }

@@ -72,7 +72,7 @@ EXPORTS = ["rmhd_layout_of", "rmhd_create", "rmhd_destroy", "rmhd_init_state", "
            "rmhd_mlp_create", "rmhd_mlp_destroy", "rmhd_mlp_get_params", "rmhd_mlp_get_norm", "rmhd_mlp_set_norm",
            "rmhd_mlp_fit_norm", "rmhd_mlp_forward", "rmhd_mlp_loss_grad", "rmhd_mlp_train_step", "rmhd_mlp_train",
            "rmhd_mlp_steps", "rmhd_mlp_last_error", "rmhd_set_harvest", "rmhd_harvest_count", "rmhd_set_guess_model",
-           "rmhd_learned_guess"]
+           "rmhd_learned_guess", "rmhd_noalloc_scratch_bytes", "rmhd_imex_step_noalloc"]
 
 MLP_NIN, MLP_NHID, MLP_NOUT, MLP_NPARAMS, MLP_NNORM, MLP_MAX_BATCH = 19, 64, 7, 5895, 52, 65536
 
@@ -133,6 +133,8 @@ def lib() -> ctypes.CDLL:
             "rmhd_harvest_count": (ctypes.c_long, [vp]),
             "rmhd_set_guess_model": (ctypes.c_int, [vp, vp]),
             "rmhd_learned_guess": (ctypes.c_int, [vp, vp, ctypes.c_double, dp, dp]),
+            "rmhd_noalloc_scratch_bytes": (ctypes.c_size_t, [P]),
+            "rmhd_imex_step_noalloc": (ctypes.c_int, [P, vp, ctypes.c_double, dp, dp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -218,6 +220,18 @@ def rmhd_implicit_stage(ctx, a, R, guess, Q, prims, status=None, iters=None):
 
 def rmhd_imex_step(ctx, dt, cons, prims):
     _check(lib().rmhd_imex_step(ctx, float(dt), _ptr(cons), _ptr(prims)), ctx)
+
+
+def rmhd_noalloc_scratch_bytes(params: rmhd_params) -> int:
+    return lib().rmhd_noalloc_scratch_bytes(ctypes.byref(params))
+
+
+def rmhd_imex_step_noalloc(params: rmhd_params, dt, cons, prims, stream=None):
+    """One step with no context and no allocation (stream: torch stream, None = current)."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib().rmhd_imex_step_noalloc(ctypes.byref(params), ctypes.c_void_p(s.cuda_stream), float(dt),
+                                        _ptr(cons), _ptr(prims)))
 
 
 def rmhd_set_graph(ctx, enable: bool):
