@@ -120,6 +120,8 @@ typedef struct rmhd_stats {
     /* collected only while detailed statistics are on (rmhd_set_stats_detail): */
     int64_t newton_hist[16];  /* cell solves by Newton iteration count (last bin: 15 or more) */
     double residual_max;      /* largest final |G|_inf / max(1, |R_x|_inf) of a converged cell */
+    int64_t jacobian_evals;   /* Jacobian evaluations of the counted cell solves, summed (the
+                                 polishing step after convergence reuses the last one) */
 } rmhd_stats;
 
 /* Per-kernel GPU time of rmhd_imex_step, from HIP events recorded on the context's stream
@@ -203,10 +205,19 @@ int rmhd_set_stats_detail(rmhd_ctx *ctx, int detail);
  * cells need instead of what the slowest cell of each wavefront needs.  cap >=
  * max_newton_iter disables the queue and gives the uninterrupted solve bit for bit; a queued
  * cell resumes from its saved unknowns and pressures with a fresh Jacobian, which agrees with
- * the uninterrupted solve to the Newton tolerance.  Default (until a cap is set): 1 for
- * two-fluid stages that start from the learned guess (rmhd_set_guess_model), no queue
- * otherwise.  cap must be >= 1. */
+ * the uninterrupted solve to the Newton tolerance.  Default (until a cap is set): no queue.
+ * cap must be >= 1. */
 int rmhd_set_newton_cap(rmhd_ctx *ctx, int cap);
+
+/* Jacobian reuse in the implicit stage's Newton iteration (resistive models): after a step
+ * that cut ||G||_inf to at most keep times its previous value, the next step reuses the same
+ * factorised Jacobian (a chord step) instead of forming it at the new iterate; a chord step
+ * is accepted only at full length and only if it cuts ||G||_inf by the same factor, else the
+ * Jacobian is formed afresh there.  The stopping rule and the polishing step are unchanged,
+ * so results agree with the iteration without reuse to the Newton tolerance.  Default 0.1
+ * (also in the batched form); keep = 0: a fresh Jacobian at every unconverged iterate.  keep
+ * must lie in [0, 1). */
+int rmhd_set_jacobian_reuse(rmhd_ctx *ctx, double keep);
 
 /* Rows of the 2-D flux-pass thread block: 16 (12 interior rows per 64 x 16 block) or 8
  * (4 interior rows, more blocks and more halo work); 0 (default) = 16.  Results do not

@@ -58,7 +58,7 @@ __device__ __forceinline__ int sf_src_slot(int v)
 // the cell.  Resumed pass: up to budget more steps, no cap.
 __device__ __forceinline__ int batch_cell(const DomainDev &D, int phase, long idx, double (&x)[3], double *w,
                                           int cap, int budget, bool resume, int &nit, int &cit, int &rit,
-                                          double &gres)
+                                          double &gres, int &jit)
 {
     const Geo &g = D.g;
     (void)g;
@@ -78,7 +78,7 @@ __device__ __forceinline__ int batch_cell(const DomainDev &D, int phase, long id
     Phys P = D.P;
     if (resume) P.max_newton = budget;
     int n = 0, c = 0, r = 0;
-    const int st = sf_stage(R, a, cell_sigma(D.P, idx), P, x, w, n, c, r, resume ? 1 << 30 : cap, &gres);
+    const int st = sf_stage(R, a, cell_sigma(D.P, idx), P, x, w, n, c, r, resume ? 1 << 30 : cap, &gres, &jit);
     nit += n;
     cit += c;
     rit += r;
@@ -123,7 +123,7 @@ __global__ __launch_bounds__(256) void kb_stage(BatchArgs A)
     const bool wave_stats = A.stats && A.wstats && !A.stats_detail;
     WaveStats ws{};
     if (wave_stats) wave_stats_begin(A.wstats, ws);
-    unsigned a_cells = 0, a_nit = 0, a_nmax = 0, a_cit = 0, a_fail = 0, a_rit = 0;
+    unsigned a_cells = 0, a_nit = 0, a_nmax = 0, a_cit = 0, a_fail = 0, a_rit = 0, a_jit = 0;
     for (;;) {
         if (A.persistent) {
             if (pos_in_item == 0 || pos_in_item >= A.chunks_per_item) {
@@ -146,9 +146,9 @@ __global__ __launch_bounds__(256) void kb_stage(BatchArgs A)
         const long idx = (long)it.y + threadIdx.x;
         const int i = (int)(idx % g.pitch), j = (int)(idx / g.pitch);
         const bool live = idx < g.plane && i < g.nxg && j < g.nyg;
-        int nit = 0, cit = 0, rit = 0, st = CELL_OK;
+        int nit = 0, cit = 0, rit = 0, jit = 0, st = CELL_OK;
         double x[3] = {0, 0, 0}, w[sf::NP] = {0, 0, 0, 0, 0}, gres = 0.0;
-        if (live) st = batch_cell(D, A.phase, idx, x, w, A.K, 0, false, nit, cit, rit, gres);
+        if (live) st = batch_cell(D, A.phase, idx, x, w, A.K, 0, false, nit, cit, rit, gres, jit);
         const bool push = live && st == CELL_QUEUED;
         if (live && !push) batch_write(D, A.phase, idx, x, w);
         // block-aggregated queue append
@@ -183,15 +183,16 @@ __global__ __launch_bounds__(256) void kb_stage(BatchArgs A)
                 a_cit += c ? cit : 0;
                 a_fail += c && !push && st != CELL_OK;
                 a_rit += c ? rit : 0;
+                a_jit += c ? jit : 0;
             } else {
                 stats_block_add(A.stats, c, c ? nit : 0, c ? nit : 0, c ? cit : 0, c && !push && st != CELL_OK,
-                                c ? rit : 0, c && !push ? nit : -1, gres, A.stats_detail != 0);
+                                c ? rit : 0, c && !push ? nit : -1, gres, A.stats_detail != 0, c ? jit : 0);
             }
         }
         if (!A.persistent) break;
         __syncthreads();  // s_wcount / s_base are rewritten by the next chunk
     }
-    if (wave_stats) wave_stats_end(ws, a_cells, a_nit, a_nmax, a_cit, a_fail, a_rit);
+    if (wave_stats) wave_stats_end(ws, a_cells, a_nit, a_nmax, a_cit, a_fail, a_rit, a_jit);
 }
 
 // Drain the queue: each lane continues one queued cell from its saved unknowns.  The grid is
@@ -202,7 +203,7 @@ __global__ __launch_bounds__(256) void kb_drain(BatchArgs A)
     const int e = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if ((int)(blockIdx.x * blockDim.x) >= tail) return;   // whole block past the tail
     const bool live = e < tail;
-    int nit = 0, cit = 0, rit = 0, st = CELL_OK, done_it = 0;
+    int nit = 0, cit = 0, rit = 0, jit = 0, st = CELL_OK, done_it = 0;
     double gres = 0.0;
     bool interior = false;
     const bool wave_stats = A.stats && A.wstats && !A.stats_detail;
@@ -214,17 +215,18 @@ __global__ __launch_bounds__(256) void kb_drain(BatchArgs A)
         interior = is_interior(D.g, (int)(idx % D.g.pitch), (int)(idx / D.g.pitch));
         double x[3] = {A.qx[3 * e], A.qx[3 * e + 1], A.qx[3 * e + 2]}, w[sf::NP] = {0, 0, 0, 0, A.qp[e]};
         done_it = A.qit[e];
-        st = batch_cell(D, A.phase, idx, x, w, 0, max(1, D.P.max_newton - done_it), true, nit, cit, rit, gres);
+        st = batch_cell(D, A.phase, idx, x, w, 0, max(1, D.P.max_newton - done_it), true, nit, cit, rit, gres, jit);
         batch_write(D, A.phase, idx, x, w);
     }
     // the cell was counted by kb_stage; only iterations and failures are added here
     if (A.stats) {
         const bool c = live && interior;
         if (wave_stats)
-            wave_stats_end(ws, 0u, c ? nit : 0, c ? nit + done_it : 0, c ? cit : 0, c && st != CELL_OK, c ? rit : 0);
+            wave_stats_end(ws, 0u, c ? nit : 0, c ? nit + done_it : 0, c ? cit : 0, c && st != CELL_OK, c ? rit : 0,
+                           c ? jit : 0);
         else
             stats_block_add(A.stats, 0u, c ? nit : 0, c ? nit + done_it : 0, c ? cit : 0, c && st != CELL_OK,
-                            c ? rit : 0, c ? nit + done_it : -1, gres, A.stats_detail != 0);
+                            c ? rit : 0, c ? nit + done_it : -1, gres, A.stats_detail != 0, c ? jit : 0);
     }
 }
 

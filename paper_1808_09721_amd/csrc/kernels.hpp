@@ -254,6 +254,7 @@ constexpr double SSP2_GAMMA = 0.29289321881345247559915563789515;
 constexpr int STATS_SLOTS = 64;
 constexpr int STATS_STRIDE = 32;
 constexpr int STATS_HIST = 6, STATS_NHIST = 16, STATS_RES = 22;   // [22]: largest final relative residual (bits)
+constexpr int STATS_JAC = 23;   // Jacobian evaluations
 
 struct StageArgs {
     CPlanes R, guess, win;
@@ -312,18 +313,18 @@ __device__ __forceinline__ double wave_maxd(double v)
 //   gres: its final relative residual (>= 0), for the maximum.
 __device__ __forceinline__ void stats_block_add(unsigned long long *stats, unsigned cells, unsigned nit, unsigned nmax,
                                                 unsigned cit, unsigned fail, unsigned rit, int hbin, double gres,
-                                                bool detail)
+                                                bool detail, unsigned jac)
 {
-    __shared__ unsigned long long red[16][6];
+    __shared__ unsigned long long red[16][7];
     __shared__ unsigned hist[16][STATS_NHIST];
     __shared__ double gmax[16];
-    unsigned long long v[6] = {cells, nit, cit, fail, nmax, rit};
+    unsigned long long v[7] = {cells, nit, cit, fail, nmax, rit, jac};
 #pragma unroll
-    for (int k = 0; k < 6; ++k) v[k] = k == 4 ? (unsigned long long)wave_max((int)nmax) : wave_sum(v[k]);
+    for (int k = 0; k < 7; ++k) v[k] = k == 4 ? (unsigned long long)wave_max((int)nmax) : wave_sum(v[k]);
     const int tid = threadIdx.x + blockDim.x * threadIdx.y, wave = tid >> 6;
     if ((tid & 63) == 0)
 #pragma unroll
-        for (int k = 0; k < 6; ++k) red[wave][k] = v[k];
+        for (int k = 0; k < 7; ++k) red[wave][k] = v[k];
     if (detail) {   // block-uniform
         const int bin = hbin < 0 ? -1 : min(hbin, STATS_NHIST - 1);
         unsigned hc[STATS_NHIST];
@@ -353,11 +354,11 @@ __device__ __forceinline__ void stats_block_add(unsigned long long *stats, unsig
         if (t) atomicAdd(&stats[((blockIdx.x + gridDim.x * blockIdx.y) % STATS_SLOTS) * STATS_STRIDE + STATS_HIST + tid], t);
     }
     if (tid == 0) {
-        unsigned long long t[6] = {0, 0, 0, 0, 0, 0};
+        unsigned long long t[7] = {0, 0, 0, 0, 0, 0, 0};
         const int nw = (int)((blockDim.x * blockDim.y + 63) >> 6);
         for (int wv = 0; wv < nw; ++wv)
 #pragma unroll
-            for (int k = 0; k < 6; ++k) t[k] = k == 4 ? max(t[k], red[wv][k]) : t[k] + red[wv][k];
+            for (int k = 0; k < 7; ++k) t[k] = k == 4 ? max(t[k], red[wv][k]) : t[k] + red[wv][k];
         if (t[0] || t[1] || t[3]) {
             unsigned long long *slot = stats + ((blockIdx.x + gridDim.x * blockIdx.y) % STATS_SLOTS) * STATS_STRIDE;
             if (t[0]) atomicAdd(&slot[0], t[0]);
@@ -366,6 +367,7 @@ __device__ __forceinline__ void stats_block_add(unsigned long long *stats, unsig
             if (t[3]) atomicAdd(&slot[3], t[3]);
             atomicMax(&slot[4], t[4]);
             if (t[5]) atomicAdd(&slot[5], t[5]);
+            if (t[6]) atomicAdd(&slot[STATS_JAC], t[6]);
         }
     }
     __syncthreads();  // red[] may be reused by a following call in the same block
@@ -380,31 +382,33 @@ __device__ __forceinline__ void stats_block_add(unsigned long long *stats, unsig
 // atomics of stats_block_add cost ~3 us per stage launch on the 256 x 512 grid, where every
 // block ends at about the same time.
 constexpr int STATS_WAVE = 8;   // [0] cells [1] newton [2] c2p [3] failures [4] newton max [5] residuals
+                                // [6] Jacobian evaluations
 }  // namespace rmhd
 // wavefront sum of the device library (its 32-bit and max forms are declared by HIP itself)
 extern "C" __device__ __attribute__((const)) unsigned long long __ockl_wfred_add_u64(unsigned long long);
 namespace rmhd {
 struct WaveStats {
     unsigned long long *slot;
-    unsigned long long old[6];
+    unsigned long long old[7];
 };
 __device__ __forceinline__ void wave_stats_begin(unsigned long long *wstats, WaveStats &ws)
 {
     ws.slot = wstats + ((long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * STATS_WAVE;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) ws.old[k] = ws.slot[k];
+    for (int k = 0; k < 7; ++k) ws.old[k] = ws.slot[k];
 }
 __device__ __forceinline__ void wave_stats_end(const WaveStats &ws, unsigned cells, unsigned nit, unsigned nmax,
-                                               unsigned cit, unsigned fail, unsigned rit)
+                                               unsigned cit, unsigned fail, unsigned rit, unsigned jac)
 {
     // the device library's wavefront reductions (cross-lane data-parallel moves, much shorter
     // than a shuffle tree); a wavefront's totals fit 32 bits except the recovery iterations
-    const unsigned long long v[6] = {__ockl_wfred_add_u32(cells), __ockl_wfred_add_u32(nit),
+    const unsigned long long v[7] = {__ockl_wfred_add_u32(cells), __ockl_wfred_add_u32(nit),
                                      __ockl_wfred_add_u64(cit), __ockl_wfred_add_u32(fail),
-                                     (unsigned long long)__ockl_wfred_max_i32((int)nmax), __ockl_wfred_add_u32(rit)};
+                                     (unsigned long long)__ockl_wfred_max_i32((int)nmax), __ockl_wfred_add_u32(rit),
+                                     __ockl_wfred_add_u32(jac)};
     if ((threadIdx.x & 63) == 0) {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) ws.slot[k] = k == 4 ? max(ws.old[k], v[k]) : ws.old[k] + v[k];
+        for (int k = 0; k < 7; ++k) ws.slot[k] = k == 4 ? max(ws.old[k], v[k]) : ws.old[k] + v[k];
     }
 }
 
@@ -414,31 +418,32 @@ __device__ __forceinline__ void wave_stats_end(const WaveStats &ws, unsigned cel
 static __global__ __launch_bounds__(256) void k_wave_stats_fold(unsigned long long *wstats, long nslots,
                                                                 unsigned long long *stats)
 {
-    __shared__ unsigned long long red[6][256];
-    unsigned long long t[6] = {0, 0, 0, 0, 0, 0};
+    __shared__ unsigned long long red[7][256];
+    unsigned long long t[7] = {0, 0, 0, 0, 0, 0, 0};
     for (long sl = (long)blockIdx.x * blockDim.x + threadIdx.x; sl < nslots; sl += (long)gridDim.x * blockDim.x) {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) {
+        for (int k = 0; k < 7; ++k) {
             const unsigned long long x = wstats[sl * STATS_WAVE + k];
             t[k] = k == 4 ? max(t[k], x) : t[k] + x;
             wstats[sl * STATS_WAVE + k] = 0;
         }
     }
 #pragma unroll
-    for (int k = 0; k < 6; ++k) red[k][threadIdx.x] = t[k];
+    for (int k = 0; k < 7; ++k) red[k][threadIdx.x] = t[k];
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
         if ((int)threadIdx.x < h) {
 #pragma unroll
-            for (int k = 0; k < 6; ++k) {
+            for (int k = 0; k < 7; ++k) {
                 const unsigned long long a = red[k][threadIdx.x], b = red[k][threadIdx.x + h];
                 red[k][threadIdx.x] = k == 4 ? max(a, b) : a + b;
             }
         }
         __syncthreads();
     }
-    if (threadIdx.x < 6) {
+    if (threadIdx.x < 7) {
         if (threadIdx.x == 4) atomicMax(&stats[4], red[4][0]);
+        else if (threadIdx.x == 6) atomicAdd(&stats[STATS_JAC], red[6][0]);
         else atomicAdd(&stats[threadIdx.x], red[threadIdx.x][0]);
     }
 }
@@ -468,17 +473,17 @@ __device__ __forceinline__ void stage_start(const StageArgs &A, long idx, bool g
 template <int M>
 __device__ __forceinline__ int stage_solve(const double *R, const StageArgs &A, double sig, const Phys &P,
                                           double (&x)[Model<M>::NX], double *w, int &nit, int &cit, int &rit,
-                                          bool alt, int cap, double &gres)
+                                          bool alt, int cap, double &gres, int &jit)
 {
     int n = 0, c = 0, r = 0, st;
     if constexpr (M == 0) {
         (void)alt;
-        st = sf_stage(R, A.a, sig, P, x, w, n, c, r, cap, &gres);
+        st = sf_stage(R, A.a, sig, P, x, w, n, c, r, cap, &gres, &jit);
     } else {
         const double isc = 1.0 / fabs(P.mu1);
         const double rx[7] = {R[tf::SBX] * isc, R[tf::SBY] * isc, R[tf::SBZ] * isc, R[tf::TAUB] * isc,
                               R[tf::EX], R[tf::EY], R[tf::EZ]};
-        st = tf_stage(R, A.a, sig, P, x, w, n, c, r, alt ? rx : nullptr, cap, &gres);
+        st = tf_stage(R, A.a, sig, P, x, w, n, c, r, alt ? rx : nullptr, cap, &gres, &jit);
     }
     nit += n;
     cit += c;
@@ -547,7 +552,7 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs A)
     const int i = (int)(t % g.pitch), j = (int)(t / g.pitch);
     const bool live = i < g.nxg && j < g.rows;   // j: row of all z planes
     const long idx = (long)j * g.pitch + i;
-    int nit = 0, cit = 0, rit = 0, st = CELL_OK;
+    int nit = 0, cit = 0, rit = 0, jit = 0, st = CELL_OK;
     bool push = false;
     double x[NX], w[NP], gres = 0.0;
     const bool wave_stats = A.stats && A.wstats && !A.stats_detail;
@@ -565,7 +570,8 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs A)
             if (attempt == 1 && A.use_guess)
 #pragma unroll
                 for (int v = 0; v < NP; ++v) w[v] = A.win.p[v][idx];
-            st = stage_solve<M>(R, A, sig, A.P, x, w, nit, cit, rit, attempt == 0 && A.compare_start, A.cap, gres);
+            st = stage_solve<M>(R, A, sig, A.P, x, w, nit, cit, rit, attempt == 0 && A.compare_start, A.cap, gres,
+                                jit);
             if (st == CELL_OK || st == CELL_QUEUED || attempt == 1) break;
         }
         push = st == CELL_QUEUED;
@@ -601,10 +607,10 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs A)
         const bool c = live && is_interior(g, i, j);
         if (wave_stats)
             wave_stats_end(ws, c, c ? nit : 0, c && !push ? nit : 0, c ? cit : 0, c && !push && st != CELL_OK,
-                           c ? rit : 0);
+                           c ? rit : 0, c ? jit : 0);
         else
             stats_block_add(A.stats, c, c ? nit : 0, c && !push ? nit : 0, c ? cit : 0, c && !push && st != CELL_OK,
-                            c ? rit : 0, c && !push ? nit : -1, gres, A.stats_detail != 0);
+                            c ? rit : 0, c && !push ? nit : -1, gres, A.stats_detail != 0, c ? jit : 0);
     }
 }
 
@@ -619,7 +625,7 @@ __global__ __launch_bounds__(256) void k_drain(StageArgs A)
     if ((int)(blockIdx.x * blockDim.x) >= tail) return;   // whole block past the tail
     const int e = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     const Geo &g = A.g;
-    int nit = 0, cit = 0, rit = 0, st = CELL_OK, done = 0;
+    int nit = 0, cit = 0, rit = 0, jit = 0, st = CELL_OK, done = 0;
     bool interior = false;
     double gres = 0.0;
     const bool wave_stats = A.stats && A.wstats && !A.stats_detail;
@@ -650,7 +656,7 @@ __global__ __launch_bounds__(256) void k_drain(StageArgs A)
                 for (int v = 0; v < NP; ++v) w[v] = A.win.p[v][idx];
                 P.max_newton = A.P.max_newton;
             }
-            st = stage_solve<M>(R, A, sig, P, x, w, nit, cit, rit, false, 1 << 30, gres);
+            st = stage_solve<M>(R, A, sig, P, x, w, nit, cit, rit, false, 1 << 30, gres, jit);
             if (st == CELL_OK || !A.use_guess || attempt == 1) break;
         }
         stage_write<M>(A, idx, i, j, R, x, w, st, done + nit, sig);
@@ -659,10 +665,11 @@ __global__ __launch_bounds__(256) void k_drain(StageArgs A)
     if (A.stats) {
         const bool c = e < tail && interior;
         if (wave_stats)
-            wave_stats_end(ws, 0u, c ? nit : 0, c ? done + nit : 0, c ? cit : 0, c && st != CELL_OK, c ? rit : 0);
+            wave_stats_end(ws, 0u, c ? nit : 0, c ? done + nit : 0, c ? cit : 0, c && st != CELL_OK, c ? rit : 0,
+                           c ? jit : 0);
         else
             stats_block_add(A.stats, 0u, c ? nit : 0, c ? done + nit : 0, c ? cit : 0, c && st != CELL_OK, c ? rit : 0,
-                            c ? done + nit : -1, gres, A.stats_detail != 0);
+                            c ? done + nit : -1, gres, A.stats_detail != 0, c ? jit : 0);
     }
 }
 
@@ -1176,6 +1183,9 @@ static inline void stats_fold(const unsigned long long *raw, rmhd_stats *out)
     out->failures = (int32_t)h[3];
     out->newton_max = (int32_t)h[4];
     out->residual_evals = (int64_t)h[5];
+    unsigned long long jac = 0;
+    for (int sl = 0; sl < STATS_SLOTS; ++sl) jac += raw[sl * STATS_STRIDE + STATS_JAC];
+    out->jacobian_evals = (int64_t)jac;
     for (int b = 0; b < STATS_NHIST; ++b) out->newton_hist[b] = (int64_t)h[STATS_HIST + b];
     unsigned long long g = 0;
     for (int sl = 0; sl < STATS_SLOTS; ++sl) g = raw[sl * STATS_STRIDE + STATS_RES] > g ? raw[sl * STATS_STRIDE + STATS_RES] : g;
@@ -1231,6 +1241,10 @@ static inline Phys phys_from(const rmhd_params *p)
     P.max_newton = p->max_newton_iter;
     P.friction_covariant = p->friction_covariant;
     P.c2p_fallback = p->c2p_primary_only ? 0 : 1;
+    // Jacobian reuse after a step that cut the residual tenfold (measured on the two-fluid
+    // 1024^2 sheet: Jacobians per cell and stage 1.39 -> 1.00 at the same Newton step count,
+    // step 1.43 -> 1.24 ms; every first step there cuts it by more than tenfold)
+    P.jac_keep = 0.1;
     return P;
 }
 

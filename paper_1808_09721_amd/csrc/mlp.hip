@@ -21,164 +21,45 @@
 #include "../../include/rmhd_mlp.h"
 #include "kernels.hpp"
 #include "mlp.hpp"
+#include "mlp_net.hpp"
 
 namespace rmhd {
 namespace mlp {
-
-constexpr int NIN = RMHD_MLP_NIN, NH = RMHD_MLP_NHID, NOUT = RMHD_MLP_NOUT, NPAR = RMHD_MLP_NPARAMS;
-constexpr int OW1 = 0, OB1 = OW1 + NH * NIN, OW2 = OB1 + NH, OB2 = OW2 + NH * NH, OW3 = OB2 + NH,
-              OB3 = OW3 + NOUT * NH;
-static_assert(OB3 + NOUT == NPAR, "parameter layout");
-// normalisation vector
-constexpr int NFM = 0, NFS = NIN, NTM = 2 * NIN, NTS = 2 * NIN + NOUT;
-// matrix-core operand tiles: W1 as 4 x 2 tiles of 16x16 (19 columns padded to 32), W2 as
-// 4 x 4, W3 as 1 x 4 (7 rows padded to 16); each tile is 64 lanes x 4 bfloat16
-constexpr int TILES = 8 + 16 + 4;
-constexpr int PACKED = TILES * 64 * 4;
-
-typedef short v4s __attribute__((ext_vector_type(4)));
-typedef float v4f __attribute__((ext_vector_type(4)));
-
-__host__ __device__ inline unsigned short bf16_bits(float f)
-{
-    unsigned u;
-    memcpy(&u, &f, 4);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
-}
-__host__ __device__ inline float bf16_float(float f)
-{
-    const unsigned u = (unsigned)bf16_bits(f) << 16;
-    float r;
-    memcpy(&r, &u, 4);
-    return r;
-}
 
 // ---------------------------------------------------------------------------------------
 // re-rounding of the master weights
 // ---------------------------------------------------------------------------------------
 // Tile t, lane l, element e holds the weight of row 16 m + (l % 16) and column
-// 16 kb + 4 (l / 16) + e: the A-operand layout of the 16x16x16 matrix instruction.
+// operand_col(kb, l / 16, e) of its matrix: the A-operand layout of the 16x16x32 matrix
+// instruction with the K order the network's B operands use.
 __global__ void k_quantize(const float *master, float *wq, unsigned short *packed)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < NPAR) wq[t] = bf16_float(master[t]);
     if (t >= PACKED) return;
-    const int tile = t >> 8, lane = (t >> 2) & 63, e = t & 3;
-    const int r16 = lane & 15, c = 4 * (lane >> 4) + e;
+    const int tile = t >> 9, lane = (t >> 3) & 63, e = t & 7;
+    const int r16 = lane & 15, q = lane >> 4;
     float v = 0.0f;
-    if (tile < 8) {
-        const int m = tile >> 1, kb = tile & 1, row = 16 * m + r16, col = 16 * kb + c;
+    if (tile < 4) {
+        const int row = 16 * tile + r16, col = operand_col(0, q, e);
         if (col < NIN) v = master[OW1 + row * NIN + col];
-    } else if (tile < 24) {
-        const int m = (tile - 8) >> 2, kb = (tile - 8) & 3;
-        v = master[OW2 + (16 * m + r16) * NH + 16 * kb + c];
+    } else if (tile < 12) {
+        const int m = (tile - 4) >> 1, kb = (tile - 4) & 1;
+        v = master[OW2 + (16 * m + r16) * NH + operand_col(kb, q, e)];
     } else {
-        const int kb = tile - 24;
-        if (r16 < NOUT) v = master[OW3 + r16 * NH + 16 * kb + c];
+        const int kb = tile - 12;
+        if (r16 < NOUT) v = master[OW3 + r16 * NH + operand_col(kb, q, e)];
     }
     packed[t] = bf16_bits(v);
 }
 
 // ---------------------------------------------------------------------------------------
-// inference on the matrix cores
+// inference on the matrix cores (net_tile, mlp_net.hpp)
 // ---------------------------------------------------------------------------------------
-// The network is evaluated transposed, H^T = W U^T, on tiles of 16 samples per wave: the
-// accumulator layout of one product (lane l: rows 4 (l / 16) + e, column l % 16) is the
-// B-operand layout of the next, so activations never leave registers.
-__device__ inline float fast_tanh(float z)
-{
-    // 1 - 2 / (1 + e^{2z}) = 1 - 2 / (1 + 2^{2 z log2 e}) with the hardware base-2 exponential
-    // and reciprocal (about 1 ulp each, far below the bfloat16 rounding that follows);
-    // saturates to +-1.  The constant is 2 log2 e, so the product is twice z log2 e exactly.
-    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z * 2.8853900817779268f));
-}
-
-typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
-
-// Four values rounded to bfloat16 (nearest, ties to even: gfx950's packed conversion, two
-// values per instruction, the same rounding as bf16_bits for finite values) as an MFMA
-// operand.
-__device__ inline v4s pack4(float a, float b, float c, float d)
-{
-    const f4 x = {a, b, c, d};
-    const bf4 h = __builtin_convertvector(x, bf4);
-    v4s r;
-    memcpy(&r, &h, sizeof(r));
-    return r;
-}
-
-// The network as one wavefront holds it: the 28 weight tiles in the A-operand layout and the
-// biases of the accumulator rows of this lane (rows 4q + e, q = lane / 16).
-struct NetRegs {
-    v4s w1[4][2], w2[4][4], w3[4];
-    float b1[4][4], b2[4][4], b3[4];
-};
-
-__device__ inline void load_net(const v4s *packed, const float *wq, int lane, NetRegs &N)
-{
-    const int q = lane >> 4;
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int kb = 0; kb < 2; ++kb) N.w1[m][kb] = packed[(m * 2 + kb) * 64 + lane];
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int kb = 0; kb < 4; ++kb) N.w2[m][kb] = packed[(8 + m * 4 + kb) * 64 + lane];
-#pragma unroll
-    for (int kb = 0; kb < 4; ++kb) N.w3[kb] = packed[(24 + kb) * 64 + lane];
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            N.b1[m][e] = wq[OB1 + 16 * m + 4 * q + e];
-            N.b2[m][e] = wq[OB2 + 16 * m + 4 * q + e];
-        }
-#pragma unroll
-    for (int e = 0; e < 4; ++e) N.b3[e] = (4 * q + e < NOUT) ? wq[OB3 + 4 * q + e] : 0.0f;
-}
-
-// One tile of 16 samples through the network.  x0, x1: the standardised inputs 4q .. 4q+3
-// and 16+4q .. 16+4q+3 of sample lane % 16 (B-operand layout).  Returns the output rows
-// 4q + e of that sample, biases included, in standardised target units.
-// Each product accumulates onto its biases (the accumulator starts at b instead of 0).
-__device__ inline v4f net_tile(const NetRegs &N, v4s x0, v4s x1)
-{
-    // layer 1: H1^T (64 x 16) = W1 (64 x 32) U^T (32 x 16) + b1
-    v4s h1[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        v4f acc = {N.b1[m][0], N.b1[m][1], N.b1[m][2], N.b1[m][3]};
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(N.w1[m][0], x0, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(N.w1[m][1], x1, acc, 0, 0, 0);
-        h1[m] = pack4(fast_tanh(acc[0]), fast_tanh(acc[1]), fast_tanh(acc[2]), fast_tanh(acc[3]));
-    }
-    // layer 2
-    v4s h2[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        v4f acc = {N.b2[m][0], N.b2[m][1], N.b2[m][2], N.b2[m][3]};
-#pragma unroll
-        for (int kb = 0; kb < 4; ++kb) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(N.w2[m][kb], h1[kb], acc, 0, 0, 0);
-        h2[m] = pack4(fast_tanh(acc[0]), fast_tanh(acc[1]), fast_tanh(acc[2]), fast_tanh(acc[3]));
-    }
-    // layer 3: rows 0..6 of the 16-row output tile
-    v4f acc = {N.b3[0], N.b3[1], N.b3[2], N.b3[3]};
-#pragma unroll
-    for (int kb = 0; kb < 4; ++kb) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(N.w3[kb], h2[kb], acc, 0, 0, 0);
-    return acc;
-}
-
-// Reciprocal standard deviations of the inputs (0 where a std is not positive): the
-// standardised value is rounded to bfloat16 next, far coarser than the multiply's rounding.
-__device__ inline float inv_std(float s) { return s > 0.0f ? 1.0f / s : 0.0f; }
-
 // Raw feature rows X[n][19] -> outputs Y[n][7] (target units), one 16-sample tile per wave
 // and step; the next tile's inputs are fetched before the current tile's products.
 struct InferArgs {
-    const v4s *packed;
+    const bf8 *packed;
     const float *wq;     // biases
     const float *norm;
     const float *X;
@@ -223,7 +104,7 @@ __global__ __launch_bounds__(256) void k_infer(InferArgs A)
 #pragma unroll
         for (int e = 0; e < 8; ++e) u[e] = (cur[e] - fm[e]) * fsi[e];
         if (q > 0) u[4] = u[5] = u[6] = u[7] = 0.0f;   // padded columns 20..31
-        const v4f acc = net_tile(N, pack4(u[0], u[1], u[2], u[3]), pack4(u[4], u[5], u[6], u[7]));
+        const f4 acc = net_tile(N, cat8(pack4(u[0], u[1], u[2], u[3]), pack4(u[4], u[5], u[6], u[7])));
         if (s < A.n && q <= 1) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
@@ -243,7 +124,7 @@ __global__ __launch_bounds__(256) void k_infer(InferArgs A)
 // product) through LDS, and the outputs come back to their cells the same way.  The LDS
 // rows are private to the wavefront, so a wave-level fence orders them (no block barrier).
 struct GuessArgs {
-    const v4s *packed;
+    const bf8 *packed;
     const float *wq, *norm;
     CPlanes R;
     Planes guess;
@@ -251,16 +132,6 @@ struct GuessArgs {
     Phys P;
     double a;
 };
-constexpr int UROW = 40;   // bfloat16 per LDS feature row (32 used): 80-byte rows spread the
-                           // B-operand reads of 16 consecutive cells over the banks
-
-__device__ inline void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Bounded to three wavefronts per SIMD (168 registers), which the kernel fits without spills.
 __global__ __launch_bounds__(256, 3) void k_guess(GuessArgs A)
 {
@@ -292,24 +163,11 @@ __global__ __launch_bounds__(256, 3) void k_guess(GuessArgs A)
         for (int v = 0; v < 18; ++v) Rv[v] = A.R.p[v][sl];
         const double sig = cell_sigma(A.P, sl);
         // features in FP32 (rounded to bfloat16 before the first product), standardised
-        const float iD = __builtin_amdgcn_rcpf((float)Rv[tf::D]);
-        float f[32];
-        f[0] = __log10f((float)(amu * Rv[tf::D]));
-#pragma unroll
-        for (int k = 1; k < 18; ++k) f[k] = (float)Rv[k] * iD;
-        f[18] = __log10f((float)(A.a * sig));
-#pragma unroll
-        for (int k = 0; k < NIN; ++k) f[k] = live ? (f[k] - s_fm[k]) * s_fsi[k] : 0.0f;
-#pragma unroll
-        for (int k = NIN; k < 32; ++k) f[k] = 0.0f;
-        v4s *row = (v4s *)&s_u[wv][lane][0];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) row[k] = pack4(f[4 * k], f[4 * k + 1], f[4 * k + 2], f[4 * k + 3]);
+        guess_features(Rv, sig, amu, A.a, live, s_fm, s_fsi, &s_u[wv][lane][0]);
         wave_lds_sync();
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const v4s *src = (const v4s *)&s_u[wv][16 * t + col][0];
-            const v4f acc = net_tile(N, src[q], src[4 + q]);
+            const f4 acc = net_tile(N, guess_operand(s_u[wv], t, lane));
             if (q <= 1) {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) s_y[wv][16 * t + col][4 * q + e] = acc[e];
@@ -317,15 +175,12 @@ __global__ __launch_bounds__(256, 3) void k_guess(GuessArgs A)
         }
         wave_lds_sync();
         if (live) {
-            // x0 = R_x + D y; the momentum and energy differences in conserved units (times
-            // |mu1|), as the stage reads its starting point
+            // x0 = R_x + D y in conserved units, as the stage reads its starting point
             const int px[NOUT] = {tf::SBX, tf::SBY, tf::SBZ, tf::TAUB, tf::EX, tf::EY, tf::EZ};
+            double x0[NOUT];
+            guess_start(Rv, s_y[wv][lane], A.norm, sc, x0);
 #pragma unroll
-            for (int k = 0; k < NOUT; ++k) {
-                const float y = A.norm[NTM + k] + A.norm[NTS + k] * s_y[wv][lane][k];
-                const double scale = k < 4 ? sc : 1.0;
-                A.guess.p[px[k]][s] = Rv[px[k]] + Rv[tf::D] * scale * (double)y;
-            }
+            for (int k = 0; k < NOUT; ++k) A.guess.p[px[k]][s] = x0[k];
         }
         wave_lds_sync();   // this chunk's LDS reads before the next chunk's writes
     }
@@ -744,7 +599,7 @@ extern "C" int rmhd_mlp_forward(rmhd_mlp *m, const float *X, long n, float *Y, i
         return mcheck(m, hipGetLastError(), "k_fwd32 launch");
     }
     InferArgs A{};
-    A.packed = (const v4s *)m->packed;
+    A.packed = (const bf8 *)m->packed;
     A.wq = m->wq;
     A.norm = m->norm;
     A.X = X;
@@ -881,11 +736,12 @@ extern "C" const char *rmhd_mlp_last_error(const rmhd_mlp *m) { return m ? m->er
 
 // ---- internal interface for the solver context -----------------------------------------
 namespace rmhd {
+
 int mlp_launch_guess(const rmhd_mlp *m, hipStream_t stream, const CPlanes &R, const Planes &guess, const Geo &g,
                      const Phys &P, double a)
 {
     GuessArgs A{};
-    A.packed = (const v4s *)m->packed;
+    A.packed = (const bf8 *)m->packed;
     A.wq = m->wq;
     A.norm = m->norm;
     A.R = R;

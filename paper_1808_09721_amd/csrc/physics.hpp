@@ -42,6 +42,9 @@ struct Phys {
     int max_c2p, max_newton;
     int friction_covariant;
     int c2p_fallback;  // 1: the pressure residual takes over where the z residual fails
+    double jac_keep;   // implicit stage: a Newton step that cut ||G|| to at most this fraction
+                       // of its previous value lets the next step reuse the same Jacobian
+                       // (0: a fresh Jacobian at every unconverged iterate)
 };
 
 __device__ __forceinline__ double cell_sigma(const Phys &P, long idx)

@@ -241,11 +241,11 @@ extern "C" void rmhd_destroy(rmhd_ctx *c)
     hipFree(c->iters);
     hipFree(c->stats);
     hipFree(c->wstats);
-    hipFree(c->guess);
     hipFree(c->qidx);
     hipFree(c->qx);
     hipFree(c->qcount);
     hipFree(c->sigma_own);
+    hipFree(c->guess);
     delete c;
 }
 
@@ -257,15 +257,15 @@ static int launch_bc(rmhd_ctx *c, double *arr, int nvar)
     return hip_check(c, hipGetLastError(), "k_bc launch");
 }
 
-// Default cap (none set): the queue with one Newton step in the first pass for two-fluid
-// stages that start from the learned guess, no queue otherwise.  Measured: with the learned
-// guess most cells converge after one step, and the queue takes the 1024^2 sheet's step from
-// 1.76 to 1.62 ms; from the plain guess the queue is 12-14 % slower on the 512^2 and 128^3
-// sheets (equal on 1024^2), and slower on every single-fluid grid measured.
+// Default cap (none set): no queue.  Measured on the two-fluid 1024^2 sheet with Jacobian
+// reuse on: a queue after one Newton step makes the learned-guess step slower (1.48 against
+// 1.42 ms); without reuse it was faster there (1.48 against 1.61 ms), since a queued cell's
+// second step took a fresh Jacobian either way.  From the plain guess the queue is 12-14 %
+// slower on the 512^2 and 128^3 sheets, and slower on every single-fluid grid measured.
 template <int M>
-static int launch_stage_m(rmhd_ctx *c, StageArgs B, bool learned = false)
+static int launch_stage_m(rmhd_ctx *c, StageArgs B)
 {
-    B.cap = c->cap ? c->cap : (learned ? 1 : 1 << 30);
+    B.cap = c->cap ? c->cap : 1 << 30;
     B.stats_detail = c->stats_detail;
     B.qcap = (int)c->lay.plane;
     B.qidx = c->qidx;
@@ -284,7 +284,10 @@ static int launch_stage(rmhd_ctx *c, const StageArgs &A)
 {
     if (c->prm.model == RMHD_SINGLE_FLUID) return launch_stage_m<0>(c, A);
     StageArgs B = A;
-    // learned starting point, unless the caller gave one
+    // learned starting point, unless the caller gave one.  The network runs in a kernel of its
+    // own: evaluated inside the stage kernel (one wavefront per SIMD there) the stage took
+    // 0.61 ms instead of 0.44 + 0.06 ms on the two-fluid 1024^2 sheet, its matrix products,
+    // LDS hand-offs and transcendentals exposed with no other wavefront to hide them
     if (c->mlp && !A.use_guess) {
         Planes G{};
         int k = 0;
@@ -304,7 +307,7 @@ static int launch_stage(rmhd_ctx *c, const StageArgs &A)
         B.hbase = c->hcount;
         c->hcount += cells;
     }
-    return launch_stage_m<1>(c, B, B.use_guess && !A.use_guess);
+    return launch_stage_m<1>(c, B);
 }
 
 template <int M, int NO>
@@ -806,6 +809,15 @@ extern "C" int rmhd_set_newton_cap(rmhd_ctx *c, int cap)
     if (!c) return fail(c, RMHD_EINVAL, "rmhd_set_newton_cap: NULL context");
     if (cap < 1) return fail(c, RMHD_EINVAL, "rmhd_set_newton_cap: cap must be >= 1");
     c->cap = cap;
+    free_graph(c);   // kernel arguments changed: capture again
+    return RMHD_OK;
+}
+
+extern "C" int rmhd_set_jacobian_reuse(rmhd_ctx *c, double keep)
+{
+    if (!c) return fail(c, RMHD_EINVAL, "rmhd_set_jacobian_reuse: NULL context");
+    if (!(keep >= 0.0 && keep < 1.0)) return fail(c, RMHD_EINVAL, "rmhd_set_jacobian_reuse: keep must lie in [0, 1)");
+    c->phys.jac_keep = keep;
     free_graph(c);   // kernel arguments changed: capture again
     return RMHD_OK;
 }

@@ -11,6 +11,11 @@
 // times) until the primitives stay physical and ||G||_inf drops; at ||G||_inf <= tol max(1,
 // ||R_x||_inf) one further Newton step is taken with the last Jacobian (it changed by the
 // order of the last step only), so the answer sits at round-off whatever the starting point.
+// With P.jac_keep > 0 a step that cut ||G||_inf to at most jac_keep times its previous value
+// lets the next step reuse the same factorised Jacobian (a chord step, about a tenth of the
+// cost of a Jacobian evaluation in the two-fluid stage); a reused Jacobian's step is taken
+// whole or not at all, and where it does not cut ||G|| by that factor the Jacobian is formed
+// afresh at the current iterate.
 #pragma once
 
 #include "physics.hpp"
@@ -178,7 +183,8 @@ __device__ __forceinline__ bool inverse3(const double (&A)[3][3], double (&Ai)[3
 // cap: Newton steps allowed from unconverged iterates in this call; a cell still unconverged
 // after them returns CELL_QUEUED with x and w (pressure) ready for a later call to resume.
 __device__ inline int sf_stage(const double *R, double a, double sig, const Phys &P, double (&x)[3], double *w,
-                               int &newton_it, int &c2p_it, int &res_it, int cap = 1 << 30, double *gres = nullptr)
+                               int &newton_it, int &c2p_it, int &res_it, int cap = 1 << 30, double *gres = nullptr,
+                               int *jac_it = nullptr)
 {
     SFCell c;
     c.D = R[sf::D];
@@ -201,14 +207,17 @@ __device__ inline int sf_stage(const double *R, double a, double sig, const Phys
         const double target = P.newton_tol * gscale;
         st = CELL_NEWTON_NOCONV;
         double Ji[3][3];
-        bool have_J = false;
+        bool have_J = false, fresh = false;
+        double ratio = 1.0;   // ||G|| after the last accepted step over ||G|| before it
         for (int it = 0; it < P.max_newton; ++it) {
             const double nrm = maxabs(G);
             const bool conv = nrm <= target;
             if (!conv && it >= cap) { st = CELL_QUEUED; break; }
-            if (!conv || !have_J) {
+            fresh = !have_J || (!conv && !(ratio <= P.jac_keep));
+            if (fresh) {
                 double A[3][3];
                 sf_jacobian(c, x, r, P, A);
+                if (jac_it) ++*jac_it;
                 if (!inverse3(A, Ji)) { st = CELL_LINESEARCH; break; }
                 have_J = true;
             }
@@ -219,17 +228,21 @@ __device__ inline int sf_stage(const double *R, double a, double sig, const Phys
             Root rt;
             bool ok = false;
             const double pcur = r.z - Eh;
-            for (int h = 0; h <= 30; ++h) {
+            // a reused Jacobian's step must cut ||G|| by the reuse factor at full length
+            const double accept = fresh ? nrm : P.jac_keep * nrm;
+            for (int h = 0; h <= (fresh || conv ? 30 : 0); ++h) {
 #pragma unroll
                 for (int i = 0; i < 3; ++i) xt[i] = x[i] + lam * dx[i];
                 ++res_it;
-                if (sf_residual(c, xt, pcur, P, Gt, rt, Eht, c2p_it) == CELL_OK && (conv || maxabs(Gt) < nrm)) {
+                if (sf_residual(c, xt, pcur, P, Gt, rt, Eht, c2p_it) == CELL_OK && (conv || maxabs(Gt) < accept)) {
                     ok = true;
                     break;
                 }
                 lam *= 0.5;
             }
+            if (!ok && !fresh && !conv) { ratio = 1.0; continue; }   // form the Jacobian afresh
             if (!ok) { st = conv ? CELL_OK : CELL_LINESEARCH; break; }
+            ratio = nrm > 0.0 ? maxabs(Gt) / nrm : 0.0;
 #pragma unroll
             for (int i = 0; i < 3; ++i) { x[i] = xt[i]; G[i] = Gt[i]; }
             r = rt;
@@ -360,7 +373,7 @@ __device__ __forceinline__ void tf_jacobian(const TFCell &c, const double (&x)[7
 // Newton begins at whichever of x and alt has the smaller residual.  cap: as for sf_stage.
 __device__ inline int tf_stage(const double *R, double a, double sig, const Phys &P, double (&x)[7], double *w,
                                int &newton_it, int &c2p_it, int &res_it, const double *alt = nullptr,
-                               int cap = 1 << 30, double *gres = nullptr)
+                               int cap = 1 << 30, double *gres = nullptr, int *jac_it = nullptr)
 {
     TFCell c;
     c.D = R[tf::D];
@@ -410,13 +423,16 @@ __device__ inline int tf_stage(const double *R, double a, double sig, const Phys
         st = CELL_NEWTON_NOCONV;
         double A[7][7];
         unsigned long long swaps = 0ull;
-        bool have_J = false;
+        bool have_J = false, fresh = false;
+        double ratio = 1.0;   // ||G|| after the last accepted step over ||G|| before it
         for (int it = 0; it < P.max_newton; ++it) {
             const double nrm = maxabs(G);
             const bool conv = nrm <= target;
             if (!conv && it >= cap) { st = CELL_QUEUED; break; }
-            if (!conv || !have_J) {
+            fresh = !have_J || (!conv && !(ratio <= P.jac_keep));
+            if (fresh) {
                 tf_jacobian(c, x, r, P, A);
+                if (jac_it) ++*jac_it;
                 if (!lu_factor<7>(A, swaps)) { st = CELL_LINESEARCH; break; }
                 have_J = true;
             }
@@ -428,17 +444,21 @@ __device__ inline int tf_stage(const double *R, double a, double sig, const Phys
             Root rt[2];
             bool ok = false;
             const double pcur[2] = {r[0].z - Eh[0], r[1].z - Eh[1]};
-            for (int h = 0; h <= 30; ++h) {
+            // a reused Jacobian's step must cut ||G|| by the reuse factor at full length
+            const double accept = fresh ? nrm : P.jac_keep * nrm;
+            for (int h = 0; h <= (fresh || conv ? 30 : 0); ++h) {
 #pragma unroll
                 for (int i = 0; i < 7; ++i) xt[i] = x[i] + lam * dx[i];
                 ++res_it;
-                if (tf_residual(c, xt, pcur, P, Gt, rt, Eht, c2p_it) == CELL_OK && (conv || maxabs(Gt) < nrm)) {
+                if (tf_residual(c, xt, pcur, P, Gt, rt, Eht, c2p_it) == CELL_OK && (conv || maxabs(Gt) < accept)) {
                     ok = true;
                     break;
                 }
                 lam *= 0.5;
             }
+            if (!ok && !fresh && !conv) { ratio = 1.0; continue; }   // form the Jacobian afresh
             if (!ok) { st = conv ? CELL_OK : CELL_LINESEARCH; break; }
+            ratio = nrm > 0.0 ? maxabs(Gt) / nrm : 0.0;
 #pragma unroll
             for (int i = 0; i < 7; ++i) { x[i] = xt[i]; G[i] = Gt[i]; }
             r[0] = rt[0]; r[1] = rt[1];

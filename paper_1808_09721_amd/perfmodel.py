@@ -2,27 +2,41 @@
 
 FLOPs are counted from the kernel source with +, -, *, /, sqrt each one FLOP and a fused
 multiply-add two (divisions and square roots are therefore undercounted relative to their
-hardware cost, which only lowers the reported fraction).  Dual-number operations count
-their value and tangent parts: add/sub 2, dual*double 2, dual*dual 4, reciprocal 4,
-square root 3.
+hardware cost, which only lowers the reported fraction).
+
+A Jacobian evaluation is counted as forward-mode differentiation needs it: the tangent
+propagation of each of its columns (7 two-fluid, 3 single-fluid), at the tangent-only cost
+of every elementary operation (add/sub 1, product with a constant 1, product of two
+varying values 3, reciprocal 3, square root 2), the primal values being those of the
+residual evaluation at the same iterate; plus the factorisation.  The kernel recomputes
+the primal in every pass (which overlaps the passes at one wavefront per SIMD), so it
+executes more than this; the counted figure stays below the FP64 operations the hardware
+counters report for the same dispatch (two-fluid 1024^2 sheet: 3.9 kFLOP counted against
+4.5 kFLOP executed on active lanes per cell and stage).
 
 Single-fluid implicit stage, per cell (stage.hpp, physics.hpp):
   primitive-recovery Newton iteration (fluid_root loop body)          22
   residual evaluation without the recovery iterations
     (split 26 + recovery set-up/final 7 + finish 54)                  87
-  Newton iteration: exact Jacobian, 3 dual columns of
-    (split 62 + root tangent 19 + finish 143)                         672
-    3x3 elimination with pivoting                                     31
-    step update                                                       8   -> 711
+  Jacobian evaluation: 3 tangent columns of
+    (split 62 + root tangent 19 + finish 143 as dual arithmetic, 224,
+     less the primal split 26 and finish 54) = 3 x 144 = 432,
+    inverse by the adjugate 42                                        474
+  Newton step (applying the inverse 15, step update 6)                21
   per-cell set-up, closed forms of psi and phi, final primitives      41
 Two-fluid implicit stage, per cell:
   primitive-recovery Newton iteration                                 22
   residual evaluation without the recovery iterations
     (split 62 + two recovery set-ups/finals 14 + finish 148)          224
-  Newton iteration: 7 dual columns of
-    (split 137 + two root tangents 38 + finish 371) = 3822,
-    7x7 elimination with pivoting 301, step update 15                 4138
+  Jacobian evaluation: 7 tangent columns of
+    (split 137 + two root tangents 38 + finish 371 as dual arithmetic, 546,
+     less the primal split 62 and finish 148) = 7 x 336 = 2352,
+    7x7 LU factorisation with pivoting 210                            2562
+  Newton step (LU solve 91, step update 15)                           106
   per-cell set-up, closed forms and final primitives                  110
+A Newton step counts every step a cell takes, the polishing step after convergence
+included; Jacobian evaluations are counted apart (rmhd_stats.jacobian_evals): the
+polishing step and chord steps reuse the last one.
 
 Flux kernel, algorithmic HBM bytes per interior cell (each value read or written once):
   first pass  q^n (ncons) + Q1 source parts (nsrc) + w1 (nprim) in, R2 + ACC (2 ncons) out
@@ -33,8 +47,8 @@ Flux kernel, algorithmic HBM bytes per interior cell (each value read or written
 from __future__ import annotations
 
 STAGE_FLOPS = {
-    0: {"c2p_iter": 22, "residual": 87, "newton": 711, "cell": 41},
-    1: {"c2p_iter": 22, "residual": 224, "newton": 4138, "cell": 110},
+    0: {"c2p_iter": 22, "residual": 87, "jacobian": 474, "newton": 21, "cell": 41},
+    1: {"c2p_iter": 22, "residual": 224, "jacobian": 2562, "newton": 106, "cell": 110},
 }
 
 NCONS = {0: 14, 1: 18}
@@ -46,10 +60,17 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP64_VECTOR_TFLOPS = 78.6
 
 
-def stage_flops(model: int, stage_cells: int, residual_evals: int, newton_iters: int, c2p_iters: int) -> float:
+def stage_flops(model: int, stage_cells: int, residual_evals: int, newton_iters: int, c2p_iters: int,
+                jacobian_evals: int) -> float:
     k = STAGE_FLOPS[model]
-    return (k["cell"] * stage_cells + k["residual"] * residual_evals + k["newton"] * newton_iters
-            + k["c2p_iter"] * c2p_iters)
+    return (k["cell"] * stage_cells + k["residual"] * residual_evals + k["jacobian"] * jacobian_evals
+            + k["newton"] * newton_iters + k["c2p_iter"] * c2p_iters)
+
+
+def stage_flops_of(model: int, stats: dict) -> float:
+    """Algorithmic FLOPs of the stage solves counted in a statistics record."""
+    return stage_flops(model, stats["stage_cells"], stats["residual_evals"], stats["newton_iters"],
+                       stats["c2p_iters"], stats["jacobian_evals"])
 
 
 def flux_bytes_per_cell(model: int, which: str) -> int:

@@ -310,10 +310,10 @@ def test_bad_network_falls_back_to_plain_guess(R, O):
     net.close()
 
 
-def test_default_stage_queue_follows_the_starting_guess(R):
-    """Without an explicit Newton cap, a plain two-fluid stage runs as one uncapped pass and a
-    stage started from the learned guess uses the queue after one Newton step: each default
-    run equals the run with that cap set explicitly, bit for bit."""
+def test_default_stage_queue_is_off(R):
+    """Without an explicit Newton cap, a two-fluid stage runs as one uncapped pass from the
+    plain and from the learned guess: each default run equals the run with a cap above the
+    iteration limit set explicitly, bit for bit."""
     banner("default stage queue")
     theta, norm = random_net(9, scale=0.01)
     net = R.Mlp(theta)
@@ -333,7 +333,7 @@ def test_default_stage_queue_follows_the_starting_guess(R):
         s.close()
         return out
 
-    for model, cap in ((None, 1000), (net, 1)):
+    for model, cap in ((None, 1000), (net, 1000)):
         a, b = run(None, model), run(cap, model)
         np.testing.assert_array_equal(a[0], b[0])
         np.testing.assert_array_equal(a[1], b[1])
@@ -350,12 +350,16 @@ def test_learned_guess_gain(R, trained):
     learned, sl = run_sheet(R, wl, trained)
     ip = sp["newton_iters"] / sp["stage_cells"]
     il = sl["newton_iters"] / sl["stage_cells"]
-    print(f"newton iterations per cell and stage: plain {ip:.3f}, learned {il:.3f}", flush=True)
+    print(f"newton iterations per cell and stage: plain {ip:.3f}, learned {il:.3f}; Jacobians "
+          f"{sp['jacobian_evals'] / sp['stage_cells']:.3f} / {sl['jacobian_evals'] / sl['stage_cells']:.3f}", flush=True)
     assert sp["failures"] == 0 and sl["failures"] == 0
     # equal final residual: both end every cell below the same stopping tolerance
     assert 0.0 < sp["residual_max"] <= 1e-12 and 0.0 < sl["residual_max"] <= 1e-12
     assert rel_linf(learned, plain).max() < 1e-9
-    assert il <= ip + 0.05
+    # a network trained on two 64^2 sheets gains a little on this 128^2 one; the trained
+    # network of the benchmark, on its held-out 1024^2 sheet, must gain at least 10 %
+    # (test_gpu_fullsize)
+    assert il < ip
 
 
 def test_learned_guess_and_harvest_on_a_3d_grid(R, O, trained):
@@ -387,3 +391,44 @@ def test_learned_guess_and_harvest_on_a_3d_grid(R, O, trained):
     x = X[:n].cpu().numpy()
     qi = g.interior(initial_state(wl)[1]).reshape(18, -1)
     np.testing.assert_allclose(x[:, 1], (qi[1] / qi[0]).astype(np.float32), rtol=1e-5, atol=1e-7)
+
+
+def test_learned_start_matches_caller_guess_planes(R, trained):
+    """The learned start a context with the network set takes (inference kernel, then the
+    stage from its planes) against the same planes handed to rmhd_implicit_stage as the
+    caller's guess (which starts at the better of that guess and R_x): on an evolved state
+    both converge every cell to the same solution within the Newton tolerance, and the Newton
+    step counts agree wherever the caller-guess path kept the learned start (nearly
+    everywhere)."""
+    banner("learned start vs caller guess planes")
+    import torch
+    wl = sheet(70, 37, seed=5, steps=2)
+    s = gpu_solver(R, wl)
+    cons, prims = s.initial_state(wl.prims, wl.EB)
+    for _ in range(wl.steps):
+        s.step(s.dt(), cons, prims)
+    a = 0.29 * s.dt()
+    out = {}
+    for mode in ("fused", "planes"):
+        Q = torch.full_like(cons, float("nan"))
+        w = prims.clone()
+        st = torch.zeros(s.grid.cell_shape, dtype=torch.int8, device="cuda")
+        it = torch.zeros(s.grid.cell_shape, dtype=torch.int32, device="cuda")
+        if mode == "fused":
+            s.set_guess_model(trained)
+            R.rmhd_implicit_stage(s.ctx, a, cons, None, Q, w, st, it)
+            s.set_guess_model(None)
+        else:
+            guess = torch.full_like(cons, float("nan"))
+            R.rmhd_learned_guess(s.ctx, trained, a, cons, guess)
+            R.rmhd_implicit_stage(s.ctx, a, cons, guess, Q, w, st, it)
+        torch.cuda.synchronize()
+        out[mode] = (s.grid.download_all(Q), s.grid.download_all(st[None])[0], s.grid.download_all(it[None])[0])
+    s.close()
+    (qf, sf, itf), (qp, sp, itp) = out["fused"], out["planes"]
+    assert (sf == 0).all() and (sp == 0).all()
+    scale = np.maximum(np.abs(qp).max(axis=(1, 2)), 1e-300)[:, None, None]
+    assert np.all(np.abs(qf - qp) <= 1e-10 * scale + 1e-300)
+    same = float((itf == itp).mean())
+    print(f"cells with equal Newton counts: {same:.4f}", flush=True)
+    assert same >= 0.9

@@ -354,13 +354,16 @@ def test_khi_small_ragged_tiles_100_steps(R, O):
 def test_newton_cap_queue_agrees_with_uninterrupted_solve(R, O, model):
     """The stage's first pass with a cap of 1 or 2 unconverged Newton steps plus the queue
     drain, against the uncapped single pass and the oracle: same cells, same iteration
-    maximum, no failures, results within the step-parity bar."""
+    maximum, no failures, results within the step-parity bar.  With a fresh Jacobian at
+    every unconverged iterate (Jacobian reuse off), so that a queued cell resuming with a
+    fresh Jacobian takes the steps the uninterrupted solve takes."""
     banner(f"newton cap queue model={model}")
     wl = (WL.kelvin_helmholtz_2d(70, 37, steps=6, seed=13, sigma=1e5) if model == 0 else
           WL.two_fluid_sheet_2d(40, 28, steps=6, seed=14, sigma_range=(1e2, 1e6)))
     out = {}
     for cap in (1, 2, 1000):
         s = gpu_solver(R, wl)
+        s.set_jacobian_reuse(0.0)
         s.set_newton_cap(cap)
         s.set_stats_detail(True)
         cons, prims = s.initial_state(wl.prims, wl.EB)
@@ -387,6 +390,45 @@ def test_newton_cap_queue_agrees_with_uninterrupted_solve(R, O, model):
         assert abs(st["newton_max"] - ref[2]["newton_max"]) <= 1
         assert np.all(rel_linf(c, ref[0]) < 1e-9) and np.all(rel_linf(p, ref[1]) < 1e-9)
         assert np.all(rel_linf(c, oc) < 1e-9)
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_jacobian_reuse_agrees_with_fresh_jacobians(R, O, model):
+    """Newton with the Jacobian reused after a step that cut the residual tenfold (the
+    default) against a fresh Jacobian at every unconverged iterate (keep = 0) and the oracle,
+    on stiff grids: no failures, every cell below the stopping tolerance, fewer Jacobian
+    evaluations per cell and stage, results within the step-parity bar of both."""
+    banner(f"jacobian reuse model={model}")
+    wl = (WL.kelvin_helmholtz_2d(70, 37, steps=6, seed=13, sigma=1e5) if model == 0 else
+          WL.two_fluid_sheet_2d(40, 28, steps=6, seed=14, sigma_range=(1e2, 1e6)))
+    out = {}
+    for keep in (0.0, None, 0.5):
+        s = gpu_solver(R, wl)
+        if keep is not None:
+            s.set_jacobian_reuse(keep)
+        s.set_stats_detail(True)
+        cons, prims = s.initial_state(wl.prims, wl.EB)
+        dt = s.dt()
+        for _ in range(wl.steps):
+            s.step(dt, cons, prims)
+        out[keep] = (s.grid.download_all(cons), s.grid.download_all(prims), s.stats())
+        s.close()
+    g, oc, op = initial_state(wl)
+    advance(g, oc, op, O.dt(g, wl.cfl), steps=wl.steps)
+    fresh = out[0.0]
+    for keep in (None, 0.5):
+        c, p, st = out[keep]
+        assert st["failures"] == 0 and 0.0 < st["residual_max"] <= 1e-12
+        assert st["stage_cells"] == fresh[2]["stage_cells"]
+        assert st["jacobian_evals"] <= fresh[2]["jacobian_evals"]
+        print(f"keep {keep}: Jacobians per cell and stage {st['jacobian_evals'] / st['stage_cells']:.3f} "
+              f"(fresh {fresh[2]['jacobian_evals'] / fresh[2]['stage_cells']:.3f}), Newton steps "
+              f"{st['newton_iters'] / st['stage_cells']:.3f} ({fresh[2]['newton_iters'] / fresh[2]['stage_cells']:.3f})",
+              flush=True)
+        assert np.all(rel_linf(c, fresh[0]) < 1e-9) and np.all(rel_linf(p, fresh[1]) < 1e-9)
+        assert np.all(rel_linf(c, oc) < 1e-9)
+    if model == 1:   # the stiff two-fluid stage: most second steps become chord steps
+        assert out[None][2]["jacobian_evals"] < fresh[2]["jacobian_evals"]
 
 
 @pytest.mark.parametrize("case", ["brio_wu", "khi", "sheet"])
