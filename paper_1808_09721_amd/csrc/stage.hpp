@@ -18,6 +18,7 @@
 // afresh at the current iterate.
 #pragma once
 
+#include "lu.hpp"
 #include "physics.hpp"
 
 namespace rmhd {
@@ -29,65 +30,6 @@ __device__ __forceinline__ double maxabs(const double (&g)[N])
 #pragma unroll
     for (int i = 0; i < N; ++i) m = fmax(m, fabs(g[i]));
     return m;
-}
-
-// LU factorisation of a small dense A held in registers, partial pivoting.  Pivot rows are
-// bubbled into place with compile-time indices (conditional swaps, recorded bit k*N+r of
-// *swaps*), so nothing is indexed dynamically and nothing spills to scratch memory.  The
-// multipliers are kept below the diagonal so the factors can be reused for a new right-hand
-// side.
-template <int N>
-__device__ __forceinline__ bool lu_factor(double (&A)[N][N], unsigned long long &swaps)
-{
-    swaps = 0ull;
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-#pragma unroll
-        for (int r = k + 1; r < N; ++r) {
-            const bool sw = fabs(A[r][k]) > fabs(A[k][k]);
-            swaps |= (unsigned long long)sw << (k * N + r);
-#pragma unroll
-            for (int c = 0; c < N; ++c) {
-                const double t = A[k][c];
-                A[k][c] = sw ? A[r][c] : t;
-                A[r][c] = sw ? t : A[r][c];
-            }
-        }
-        if (!(A[k][k] != 0.0) || !isfinite(A[k][k])) return false;
-        const double inv = 1.0 / A[k][k];
-#pragma unroll
-        for (int r = k + 1; r < N; ++r) {
-            const double m = A[r][k] * inv;
-            A[r][k] = m;
-#pragma unroll
-            for (int c = k + 1; c < N; ++c) A[r][c] -= m * A[k][c];
-        }
-    }
-    return true;
-}
-
-template <int N>
-__device__ __forceinline__ void lu_solve(const double (&A)[N][N], unsigned long long swaps, double (&b)[N])
-{
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-#pragma unroll
-        for (int r = k + 1; r < N; ++r) {
-            const bool sw = (swaps >> (k * N + r)) & 1ull;
-            const double t = b[k];
-            b[k] = sw ? b[r] : t;
-            b[r] = sw ? t : b[r];
-        }
-#pragma unroll
-        for (int r = k + 1; r < N; ++r) b[r] -= A[r][k] * b[k];
-    }
-#pragma unroll
-    for (int r = N - 1; r >= 0; --r) {
-        double acc = b[r];
-#pragma unroll
-        for (int c = r + 1; c < N; ++c) acc -= A[r][c] * b[c];
-        b[r] = acc / A[r][r];
-    }
 }
 
 // ---------------------------------------------------------------------------------------
