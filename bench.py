@@ -69,7 +69,7 @@ def cpu_baseline(budget_s: float = 10.0) -> dict:
 
 
 # sources of the single-grid kernels (the headline workload's kernels)
-SINGLE_GRID_SOURCES = ("physics.hpp", "stage.hpp", "kernels.hpp", "rmhd.hip", "mlp.hip", "mlp_net.hpp")
+SINGLE_GRID_SOURCES = ("physics.hpp", "stage.hpp", "lu.hpp", "kernels.hpp", "rmhd.hip", "mlp.hip", "mlp_net.hpp")
 
 
 def source_hash() -> str:

@@ -219,9 +219,10 @@ int rmhd_set_newton_cap(rmhd_ctx *ctx, int cap);
  * must lie in [0, 1). */
 int rmhd_set_jacobian_reuse(rmhd_ctx *ctx, double keep);
 
-/* Rows of the 2-D flux-pass thread block: 16 (12 interior rows per 64 x 16 block) or 8
- * (4 interior rows, more blocks and more halo work); 0 (default) = 16.  Results do not
- * depend on it.  (3-D grids always use 16.) */
+/* Rows of the 2-D flux-pass thread block: 16 (12 interior rows per 64 x 16 block), 12 (8
+ * interior rows) or 8 (4 interior rows, more blocks and more halo work); 0 (default) = 12
+ * for two-fluid grids with at least four 16-row tiles per compute unit, 16 otherwise.
+ * Results do not depend on it.  (3-D grids always use 16.) */
 int rmhd_set_flux_rows(rmhd_ctx *ctx, int rows);
 
 /* Enable (1) or disable (0) per-kernel event timing of rmhd_imex_step.  While enabled each

@@ -784,15 +784,15 @@ __device__ __forceinline__ void weno3_pair(double ap, double bp, double cp, doub
 // rows span several wavefronts); every thread of the block must call it (it holds
 // barriers).  (bx, by) is the tile position in units of interior tiles; zoff is the offset of
 // the z plane (0 below 3-D, where a 2-D tile forms the x and y terms of one plane).
-template <int M, int NDIM, int BX, int BY, int NO>
+template <int M, int NDIM, int BX, int BY, int NO, int GV = 1>
 __device__ __forceinline__ void flux_tile_lds(const FluxArgs &A, int bx, int by, long zoff)
 {
     constexpr int NC = Model<M>::NC, NP = Model<M>::NP;
     constexpr int TX = BX - 4, TY = NDIM == 2 ? BY - 4 : 1;
     // split fluxes f+ / f- per direction, then the half reconstructions: cell i holds
-    // f+ at its right face (i+1/2) and f- at its left face (i-1/2)
-    __shared__ double sfp[NDIM][BY][BX], sfm[NDIM][BY][BX];
-    __shared__ double shp[NDIM][BY][BX], shm[NDIM][BY][BX];
+    // f+ at its right face (i+1/2) and f- at its left face (i-1/2); GV variables per round
+    __shared__ double sfp[GV][NDIM][BY][BX], sfm[GV][NDIM][BY][BX];
+    __shared__ double shp[GV][NDIM][BY][BX], shm[GV][NDIM][BY][BX];
     const Geo &g = A.g;
     const int tx = threadIdx.x, ty = NDIM == 2 ? threadIdx.y : 0;
     const int ii = bx * TX + tx - 2;
@@ -820,54 +820,73 @@ __device__ __forceinline__ void flux_tile_lds(const FluxArgs &A, int bx, int by,
     const bool img = xi[1] >= 0 || xi[2] >= 0 || yj[1] >= 0 || yj[2] >= 0;
 
 #pragma unroll
-    for (int v = 0; v < NC; ++v) {
+    for (int v0 = 0; v0 < NC; v0 += GV) {
         // base terms first, so that their loads overlap the reconstruction
-        double bv[NO];
+        double bv[GV][NO];
 #pragma unroll
-        for (int k = 0; k < NO; ++k) bv[k] = (interior && A.o[k].base.p[0]) ? plane_at(A.o[k].base, v, g)[idx] : 0.0;
-        sfp[0][ty][tx] = 0.5 * (fx[v] + q[v]);
-        sfm[0][ty][tx] = 0.5 * (fx[v] - q[v]);
-        if constexpr (NDIM == 2) {
-            sfp[NDIM - 1][ty][tx] = 0.5 * (fy[v] + q[v]);
-            sfm[NDIM - 1][ty][tx] = 0.5 * (fy[v] - q[v]);
+        for (int gv = 0; gv < GV; ++gv)
+#pragma unroll
+            for (int k = 0; k < NO; ++k)
+                bv[gv][k] = (v0 + gv < NC && interior && A.o[k].base.p[0]) ? plane_at(A.o[k].base, v0 + gv, g)[idx] : 0.0;
+#pragma unroll
+        for (int gv = 0; gv < GV; ++gv) {
+            const int v = v0 + gv;
+            if (v >= NC) break;
+            sfp[gv][0][ty][tx] = 0.5 * (fx[v] + q[v]);
+            sfm[gv][0][ty][tx] = 0.5 * (fx[v] - q[v]);
+            if constexpr (NDIM == 2) {
+                sfp[gv][NDIM - 1][ty][tx] = 0.5 * (fy[v] + q[v]);
+                sfm[gv][NDIM - 1][ty][tx] = 0.5 * (fy[v] - q[v]);
+            }
         }
         __syncthreads();
-        if (do_x) {
-            double vp, vm;
-            weno3_pair(sfp[0][ty][tx - 1], sfp[0][ty][tx], sfp[0][ty][tx + 1], sfm[0][ty][tx + 1], sfm[0][ty][tx],
-                       sfm[0][ty][tx - 1], vp, vm);
-            shp[0][ty][tx] = vp;
-            shm[0][ty][tx] = vm;
-        }
-        if constexpr (NDIM == 2) {
-            if (do_y) {
+#pragma unroll
+        for (int gv = 0; gv < GV; ++gv) {
+            if (v0 + gv >= NC) break;
+            if (do_x) {
                 double vp, vm;
-                weno3_pair(sfp[NDIM - 1][ty - 1][tx], sfp[NDIM - 1][ty][tx], sfp[NDIM - 1][ty + 1][tx],
-                           sfm[NDIM - 1][ty + 1][tx], sfm[NDIM - 1][ty][tx], sfm[NDIM - 1][ty - 1][tx], vp, vm);
-                shp[NDIM - 1][ty][tx] = vp;
-                shm[NDIM - 1][ty][tx] = vm;
+                weno3_pair(sfp[gv][0][ty][tx - 1], sfp[gv][0][ty][tx], sfp[gv][0][ty][tx + 1], sfm[gv][0][ty][tx + 1],
+                           sfm[gv][0][ty][tx], sfm[gv][0][ty][tx - 1], vp, vm);
+                shp[gv][0][ty][tx] = vp;
+                shm[gv][0][ty][tx] = vm;
+            }
+            if constexpr (NDIM == 2) {
+                if (do_y) {
+                    double vp, vm;
+                    weno3_pair(sfp[gv][NDIM - 1][ty - 1][tx], sfp[gv][NDIM - 1][ty][tx], sfp[gv][NDIM - 1][ty + 1][tx],
+                               sfm[gv][NDIM - 1][ty + 1][tx], sfm[gv][NDIM - 1][ty][tx], sfm[gv][NDIM - 1][ty - 1][tx],
+                               vp, vm);
+                    shp[gv][NDIM - 1][ty][tx] = vp;
+                    shm[gv][NDIM - 1][ty][tx] = vm;
+                }
             }
         }
         __syncthreads();
         if (interior) {
-            double L = -((shp[0][ty][tx] + shm[0][ty][tx + 1]) - (shp[0][ty][tx - 1] + shm[0][ty][tx])) * g.idx;
-            if constexpr (NDIM == 2)
-                L -= ((shp[NDIM - 1][ty][tx] + shm[NDIM - 1][ty + 1][tx]) -
-                      (shp[NDIM - 1][ty - 1][tx] + shm[NDIM - 1][ty][tx])) * g.idy;
-            const double S = has_source(M, v) ? src[v] : 0.0;
-            double o0 = 0.0;
 #pragma unroll
-            for (int k = 0; k < NO; ++k) {
-                const FluxOut &F = A.o[k];
-                const double o = bv[k] + F.cL * L + F.cS * S;
-                if (k == 0) {
-                    o0 = o;
-                    store_with_images(plane_at(F.out, v, g), zoff, g.pitch, xi, yj, NDIM == 2 ? 3 : 1, img, o);
-                } else {
-                    plane_at(F.out, v, g)[idx] = o;
+            for (int gv = 0; gv < GV; ++gv) {
+                const int v = v0 + gv;
+                if (v >= NC) break;
+                double L = -((shp[gv][0][ty][tx] + shm[gv][0][ty][tx + 1]) - (shp[gv][0][ty][tx - 1] + shm[gv][0][ty][tx])) *
+                           g.idx;
+                if constexpr (NDIM == 2)
+                    L -= ((shp[gv][NDIM - 1][ty][tx] + shm[gv][NDIM - 1][ty + 1][tx]) -
+                          (shp[gv][NDIM - 1][ty - 1][tx] + shm[gv][NDIM - 1][ty][tx])) * g.idy;
+                const double S = has_source(M, v) ? src[v] : 0.0;
+                double o0 = 0.0;
+#pragma unroll
+                for (int k = 0; k < NO; ++k) {
+                    const FluxOut &F = A.o[k];
+                    const double o = bv[gv][k] + F.cL * L + F.cS * S;
+                    if (k == 0) {
+                        o0 = o;
+                        store_with_images(plane_at(F.out, v, g), zoff, g.pitch, xi, yj, NDIM == 2 ? 3 : 1, img, o);
+                    } else {
+                        plane_at(F.out, v, g)[idx] = o;
+                    }
                 }
+                q[v] = o0;   // this thread's own q[v] is not read again
             }
-            q[v] = o0;   // this thread's own q[v] is not read again
         }
     }
     // the two-fluid step recovers in a separate kernel, so its flux pass does not carry the code
@@ -1011,14 +1030,18 @@ __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by
 
 // One tile of the flux pass: single-fluid and ideal 2-D tiles with 64-wide rows use the
 // wavefront-row form, everything else the LDS form (measured: for the two-fluid model the
-// row form's extra live registers cost more than its saved LDS traffic).
+// row form's extra live registers cost more than its saved LDS traffic: with the whole flux
+// vectors formed up front and the x stencil read from neighbouring lanes, the 1024^2 sheet's
+// pass took 238-257 us against 227 us, spilling 76-240 bytes per lane at 16 rows).  The
+// two-fluid 2-D tile stages two variables per pair of barriers (239 against 253 us per pass
+// on the 1024^2 sheet at 16 rows, 221 against 245 us at 12 rows; 64 against 67 us on 512^2).
 // NO: outputs used (o[0..NO-1]), fixed at compile time so unused ones cost no registers.
 template <int M, int NDIM, int BX, int BY, int NO>
 __device__ __forceinline__ void flux_tile(const FluxArgs &A, int bx, int by, long zoff = 0)
 {
     static_assert(NO >= 1 && NO <= FLUX_MAXOUT, "outputs");
     if constexpr (M != 1 && NDIM == 2 && BX == 64) flux_tile_rows<M, BY, NO>(A, bx, by, zoff);
-    else flux_tile_lds<M, NDIM, BX, BY, NO>(A, bx, by, zoff);
+    else flux_tile_lds<M, NDIM, BX, BY, NO, (M == 1 && NDIM == 2) ? 2 : 1>(A, bx, by, zoff);
 }
 
 // Workgroups are dealt to the 8 XCDs in turn (linear id mod 8), each XCD with its own L2.

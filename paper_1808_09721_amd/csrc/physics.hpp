@@ -101,7 +101,7 @@ __device__ __forceinline__ dual recip(dual a)
 __device__ __forceinline__ dual dsqrt(dual a)
 {
     const double s = sqrt(a.v);
-    return {s, 0.5 * a.d / s};
+    return {s, 0.5 * a.d * frcp(s)};
 }
 // three tangents at once: one forward pass yields a whole 3x3 Jacobian
 struct dual3 {
@@ -127,7 +127,7 @@ __device__ __forceinline__ dual3 recip(dual3 a)
 }
 __device__ __forceinline__ dual3 dsqrt(dual3 a)
 {
-    const double s = sqrt(a.v), h = 0.5 / s;
+    const double s = sqrt(a.v), h = 0.5 * frcp(s);
     return {s, a.d0 * h, a.d1 * h, a.d2 * h};
 }
 

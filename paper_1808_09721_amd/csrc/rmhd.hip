@@ -23,6 +23,7 @@ struct rmhd_ctx {
     Geo geo;
     Phys phys;
     int device;
+    int cus;          // compute units of the device
     // scratch owned by the library
     double *q1src;    // stage-1 source-carrying components (NX + 2 planes)
     double *w1;       // stage-1 primitives (nprim planes)
@@ -165,6 +166,8 @@ extern "C" int rmhd_create(const rmhd_params *p, void *stream, rmhd_ctx **out)
     const rmhd_layout &L = c->lay;
     c->geo = geo_from(p, L);
     c->phys = phys_from(p);
+    if (hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || c->cus < 1)
+        c->cus = 256;
     const size_t pl = (size_t)L.plane * sizeof(double);
     const int nsrc = p->model == RMHD_SINGLE_FLUID ? 5 : p->model == RMHD_TWO_FLUID ? 9 : 1;
     hipError_t e = hipSuccess;
@@ -330,14 +333,20 @@ static void launch_flux_mo(rmhd_ctx *c, const FluxArgs &A)
         dim3 grid((c->prm.nx + (BX - 4) - 1) / (BX - 4));
         hipLaunchKernelGGL((k_flux<M, 1, BX, 1, NO>), grid, dim3(BX, 1), 0, c->stream, A);
     } else {
-        // 64 x 16 tiles (12 interior rows); 64 x 8 (4 rows) on request.  Measured on the
-        // 256 x 512 grid, whose 16-row tiles leave some CUs idle, 16 rows are still faster
-        // (30 us against 41 us): the 8-row tile's halo work costs more than the idle CUs.
+        // 64 x 16 tiles (12 interior rows) by default; 64 x 12 (8 rows) for two-fluid grids
+        // with at least four 16-row tiles per CU, whose 768-thread blocks fit the two-fluid
+        // tile's registers without spills (measured on the 1024^2 sheet: 221 against 239 us
+        // per pass; on 512^2, 1.5 tiles per CU, 70 against 64 us); 64 x 8 (4 rows) on request.
+        // Measured on the 256 x 512 single-fluid grid, whose 16-row tiles leave some CUs idle,
+        // 16 rows are still faster (30 us against 41 us at 8 rows, 40 us at 12).
         constexpr int BX = 64;
         const unsigned gx = (unsigned)((c->prm.nx + (BX - 4) - 1) / (BX - 4));
-        const int rows = c->flux_rows ? c->flux_rows : 16;
+        const long tiles16 = (long)gx * ((c->prm.ny + 11) / 12);
+        const int rows = c->flux_rows ? c->flux_rows : (M == 1 && tiles16 >= 4L * c->cus ? 12 : 16);
         if (rows == 8)
             hipLaunchKernelGGL((k_flux<M, 2, BX, 8, NO>), dim3(gx, (c->prm.ny + 3) / 4), dim3(BX, 8), 0, c->stream, A);
+        else if (rows == 12)
+            hipLaunchKernelGGL((k_flux<M, 2, BX, 12, NO>), dim3(gx, (c->prm.ny + 7) / 8), dim3(BX, 12), 0, c->stream, A);
         else
             hipLaunchKernelGGL((k_flux<M, 2, BX, 16, NO>), dim3(gx, (c->prm.ny + 11) / 12), dim3(BX, 16), 0,
                                c->stream, A);
@@ -825,7 +834,8 @@ extern "C" int rmhd_set_jacobian_reuse(rmhd_ctx *c, double keep)
 extern "C" int rmhd_set_flux_rows(rmhd_ctx *c, int rows)
 {
     if (!c) return fail(c, RMHD_EINVAL, "rmhd_set_flux_rows: NULL context");
-    if (rows != 0 && rows != 8 && rows != 16) return fail(c, RMHD_EINVAL, "rmhd_set_flux_rows: rows must be 0, 8 or 16");
+    if (rows != 0 && rows != 8 && rows != 12 && rows != 16)
+        return fail(c, RMHD_EINVAL, "rmhd_set_flux_rows: rows must be 0, 8, 12 or 16");
     c->flux_rows = rows;
     free_graph(c);   // kernel arguments changed: capture again
     return RMHD_OK;
@@ -923,6 +933,8 @@ extern "C" int rmhd_imex_step_noalloc(const rmhd_params *p, void *hip_stream, do
     c.geo = geo_from(p, c.lay);
     c.phys = phys_from(p);
     hipGetDevice(&c.device);
+    if (hipDeviceGetAttribute(&c.cus, hipDeviceAttributeMultiprocessorCount, c.device) != hipSuccess || c.cus < 1)
+        c.cus = 256;
     const size_t pl = ((size_t)c.lay.plane * sizeof(double) + 255) & ~(size_t)255;
     unsigned char *s = (unsigned char *)base;
     auto take = [&](int nplanes) {

@@ -210,7 +210,7 @@ __device__ inline int sf_stage(const double *R, double a, double sig, const Phys
 // two fluid
 // ---------------------------------------------------------------------------------------
 struct TFCell {
-    double D, tau, B2, a, eta, sc, Ds[2], rhoe;
+    double D, tau, B2, a, eta, sc, isc, i12, Ds[2], rhoe;
     vec3<double> S, B, RSb, RE;
     double Rtb;
 };
@@ -226,7 +226,7 @@ __device__ __forceinline__ void tf_split(const TFCell &c, const T (&x)[7], const
     const auto ExB = cross(E, c.B);
     const vec3<T> St = v3<T>(c.S.x - ExB.x, c.S.y - ExB.y, c.S.z - ExB.z);
     const T tt = c.tau - 0.5 * (dot(E, E) + c.B2);
-    const double i12 = 1.0 / (P.mu1 - P.mu2);
+    const double i12 = c.i12;
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         const double m = s == 0 ? P.mu2 : P.mu1, sg = s == 0 ? i12 : -i12;
@@ -251,7 +251,7 @@ __device__ __forceinline__ void tf_finish(const TFCell &c, const T (&x)[7], cons
     }
     const vec3<T> E = v3<T>(x[4], x[5], x[6]);
     const TFSource<T> src = tf_source_terms<T>(Dw, rho, v, E, c.B, c.eta, P);
-    const double isc = 1.0 / c.sc;
+    const double isc = c.isc;
     G[0] = x[0] - (c.RSb.x + c.a * src.Sb.x) * isc;
     G[1] = x[1] - (c.RSb.y + c.a * src.Sb.y) * isc;
     G[2] = x[2] - (c.RSb.z + c.a * src.Sb.z) * isc;
@@ -329,7 +329,9 @@ __device__ inline int tf_stage(const double *R, double a, double sig, const Phys
     c.a = a;
     c.eta = 1.0 / sig;
     c.sc = fabs(P.mu1);
-    const double i12 = 1.0 / (P.mu1 - P.mu2);
+    c.isc = 1.0 / c.sc;
+    c.i12 = 1.0 / (P.mu1 - P.mu2);
+    const double i12 = c.i12;
     c.Ds[0] = (R[tf::DB] - P.mu2 * c.D) * i12;
     c.Ds[1] = -(R[tf::DB] - P.mu1 * c.D) * i12;
     c.rhoe = R[tf::DB];
@@ -356,8 +358,8 @@ __device__ inline int tf_stage(const double *R, double a, double sig, const Phys
         }
     }
     double rx = 0.0;
-    rx = fmax(rx, fabs(c.RSb.x / c.sc)); rx = fmax(rx, fabs(c.RSb.y / c.sc)); rx = fmax(rx, fabs(c.RSb.z / c.sc));
-    rx = fmax(rx, fabs(c.Rtb / c.sc));
+    rx = fmax(rx, fabs(c.RSb.x * c.isc)); rx = fmax(rx, fabs(c.RSb.y * c.isc)); rx = fmax(rx, fabs(c.RSb.z * c.isc));
+    rx = fmax(rx, fabs(c.Rtb * c.isc));
     rx = fmax(rx, fabs(c.RE.x)); rx = fmax(rx, fabs(c.RE.y)); rx = fmax(rx, fabs(c.RE.z));
     const double gscale = fmax(1.0, rx);
     if (st == CELL_OK) {

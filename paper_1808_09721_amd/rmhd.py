@@ -415,6 +415,10 @@ class Solver:
         """Newton steps from unconverged iterates before a cell is queued (>= max: no queue)."""
         rmhd_set_newton_cap(self.ctx, cap)
 
+    def set_flux_rows(self, rows: int):
+        """Rows of the 2-D flux tile block (0: the library's choice, 8, 12 or 16)."""
+        rmhd_set_flux_rows(self.ctx, rows)
+
     def set_jacobian_reuse(self, keep: float):
         """Reuse the factorised Jacobian after a step that cut the residual by at least keep."""
         rmhd_set_jacobian_reuse(self.ctx, keep)

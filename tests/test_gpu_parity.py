@@ -431,6 +431,27 @@ def test_jacobian_reuse_agrees_with_fresh_jacobians(R, O, model):
         assert out[None][2]["jacobian_evals"] < fresh[2]["jacobian_evals"]
 
 
+@pytest.mark.parametrize("model", [0, 1])
+def test_flux_tile_rows_do_not_change_results(R, model):
+    """The 2-D flux tile's height (8, 12 or 16 thread rows, and the library's own choice) only
+    changes which block computes a cell: three steps give the same state bit for bit."""
+    banner(f"flux tile rows model={model}")
+    wl = (WL.kelvin_helmholtz_2d(70, 37, steps=3, seed=15) if model == 0 else
+          WL.two_fluid_sheet_2d(70, 37, steps=3, seed=16, sigma_range=(1e2, 1e6)))
+    out = []
+    for rows in (0, 8, 12, 16):
+        s = gpu_solver(R, wl)
+        s.set_flux_rows(rows)
+        cons, prims = s.initial_state(wl.prims, wl.EB)
+        for _ in range(wl.steps):
+            s.step(s.dt(), cons, prims)
+        out.append((s.grid.download_all(cons), s.grid.download_all(prims)))
+        s.close()
+    for c, p in out[1:]:
+        np.testing.assert_array_equal(c, out[0][0])
+        np.testing.assert_array_equal(p, out[0][1])
+
+
 @pytest.mark.parametrize("case", ["brio_wu", "khi", "sheet"])
 def test_ssp3_steps_match_oracle(R, O, case):
     """SSP3(332) (Table 3) on the GPU against the oracle's SSP3 step: Brio-Wu and ragged KHI
