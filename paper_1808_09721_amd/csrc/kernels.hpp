@@ -784,7 +784,7 @@ __device__ __forceinline__ void weno3_pair(double ap, double bp, double cp, doub
 // rows span several wavefronts); every thread of the block must call it (it holds
 // barriers).  (bx, by) is the tile position in units of interior tiles; zoff is the offset of
 // the z plane (0 below 3-D, where a 2-D tile forms the x and y terms of one plane).
-template <int M, int NDIM, int BX, int BY, int NO, int GV = 1>
+template <int M, int NDIM, int BX, int BY, int NO, int GV = 1, bool RECOVER = true>
 __device__ __forceinline__ void flux_tile_lds(const FluxArgs &A, int bx, int by, long zoff)
 {
     constexpr int NC = Model<M>::NC, NP = Model<M>::NP;
@@ -889,8 +889,7 @@ __device__ __forceinline__ void flux_tile_lds(const FluxArgs &A, int bx, int by,
             }
         }
     }
-    // the two-fluid step recovers in a separate kernel, so its flux pass does not carry the code
-    if constexpr (M != 1)
+    if constexpr (RECOVER)
         if (A.wnew.p[0] && interior) flux_recover<M>(A, q, w, xi, yj, NDIM == 2 ? 3 : 1, zoff);
 }
 
@@ -924,7 +923,7 @@ __device__ __forceinline__ double from_right(double v) { return __shfl_down(v, 1
 // the x stencil is read from neighbouring lanes (no LDS, no barrier) and only the y stencil
 // goes through LDS, G variables per pair of barriers.  The arithmetic per face and cell is
 // that of flux_tile_lds.  Every thread of the block must call it.
-template <int M, int BY, int NO>
+template <int M, int BY, int NO, bool RECOVER = true>
 __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by, long zoff)
 {
     constexpr int NC = Model<M>::NC, NP = Model<M>::NP;
@@ -1018,7 +1017,7 @@ __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by
         // the next round rewrites sfp/sfm only after every thread has passed the barrier
         // above, and shp/shm only after the next round's first barrier
     }
-    if constexpr (M != 1)
+    if constexpr (RECOVER)
         if (A.wnew.p[0] && interior) {
             // the new state, read back from output 0 (written above by this thread)
             double qn[NC];
@@ -1036,12 +1035,14 @@ __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by
 // two-fluid 2-D tile stages two variables per pair of barriers (239 against 253 us per pass
 // on the 1024^2 sheet at 16 rows, 221 against 245 us at 12 rows; 64 against 67 us on 512^2).
 // NO: outputs used (o[0..NO-1]), fixed at compile time so unused ones cost no registers.
-template <int M, int NDIM, int BX, int BY, int NO>
+// RECOVER = false: the tile never recovers primitives (the x-y tiles of a 3-D pass, whose z
+// kernel completes the outputs), so the recovery's registers are not reserved.
+template <int M, int NDIM, int BX, int BY, int NO, bool RECOVER = true>
 __device__ __forceinline__ void flux_tile(const FluxArgs &A, int bx, int by, long zoff = 0)
 {
     static_assert(NO >= 1 && NO <= FLUX_MAXOUT, "outputs");
-    if constexpr (M != 1 && NDIM == 2 && BX == 64) flux_tile_rows<M, BY, NO>(A, bx, by, zoff);
-    else flux_tile_lds<M, NDIM, BX, BY, NO, (M == 1 && NDIM == 2) ? 2 : 1>(A, bx, by, zoff);
+    if constexpr (M != 1 && NDIM == 2 && BX == 64) flux_tile_rows<M, BY, NO, RECOVER>(A, bx, by, zoff);
+    else flux_tile_lds<M, NDIM, BX, BY, NO, (M == 1 && NDIM == 2) ? 2 : 1, RECOVER>(A, bx, by, zoff);
 }
 
 // Workgroups are dealt to the 8 XCDs in turn (linear id mod 8), each XCD with its own L2.
@@ -1078,10 +1079,12 @@ __global__ __launch_bounds__(BX *BY) void k_flux(FluxArgs A)
     if constexpr (NDIM == 3) {
         int bz;
         xcd_tile3(bx, by, bz);
-        flux_tile<M, 2, BX, BY, NO>(A, bx, by, (long)(bz + 2) * A.g.slab);
+        flux_tile<M, 2, BX, BY, NO, false>(A, bx, by, (long)(bz + 2) * A.g.slab);
     } else {
         if constexpr (NDIM == 2) xcd_tile(bx, by);
-        flux_tile<M, NDIM, BX, BY, NO>(A, bx, by);
+        // only a step's last pass (one output) recovers primitives, except in the ideal
+        // model's explicit steps, whose every pass does; the others reserve no registers for it
+        flux_tile<M, NDIM, BX, BY, NO, NO == 1 || M == 2>(A, bx, by);
     }
 }
 
@@ -1175,8 +1178,8 @@ __global__ __launch_bounds__(1024) void k_flux_z(FluxArgs A)
         // sfp/sfm are rewritten only after every thread has passed the second barrier above,
         // shp/shm only after the next round's first barrier
     }
-    // primitives of output 0 (guess: w), with their ghost images; the two-fluid step never
-    // asks for them here (its primitives come from the implicit stage)
+    // primitives of output 0 (guess: w), with their ghost images; a 3-D two-fluid step
+    // recovers in a kernel of its own (the recovery would make this kernel spill)
     if (M != 1 && A.wnew.p[0] && interior) {
         double wn[NP];
 #pragma unroll

@@ -313,6 +313,14 @@ static int launch_stage(rmhd_ctx *c, const StageArgs &A)
     return launch_stage_m<1>(c, B);
 }
 
+// Thread rows of a 2-D flux tile block.
+static int flux_rows_2d(const rmhd_ctx *c)
+{
+    if (c->flux_rows) return c->flux_rows;
+    const long tiles16 = (long)((c->prm.nx + 59) / 60) * ((c->prm.ny + 11) / 12);
+    return c->prm.model == RMHD_TWO_FLUID && tiles16 >= 4L * c->cus ? 12 : 16;
+}
+
 template <int M, int NO>
 static void launch_flux_mo(rmhd_ctx *c, const FluxArgs &A)
 {
@@ -341,8 +349,7 @@ static void launch_flux_mo(rmhd_ctx *c, const FluxArgs &A)
         // 16 rows are still faster (30 us against 41 us at 8 rows, 40 us at 12).
         constexpr int BX = 64;
         const unsigned gx = (unsigned)((c->prm.nx + (BX - 4) - 1) / (BX - 4));
-        const long tiles16 = (long)gx * ((c->prm.ny + 11) / 12);
-        const int rows = c->flux_rows ? c->flux_rows : (M == 1 && tiles16 >= 4L * c->cus ? 12 : 16);
+        const int rows = flux_rows_2d(c);
         if (rows == 8)
             hipLaunchKernelGGL((k_flux<M, 2, BX, 8, NO>), dim3(gx, (c->prm.ny + 3) / 4), dim3(BX, 8), 0, c->stream, A);
         else if (rows == 12)
@@ -603,8 +610,11 @@ static int enqueue_imex(rmhd_ctx *c, double dt, double *cons, double *prims)
     const double gm = SSP2_GAMMA;
     const int M = c->prm.model;
     const bool ssp3 = c->prm.integrator == RMHD_SSP3_332;
-    // single fluid: the last flux pass also recovers the primitives
-    const bool fused = M == RMHD_SINGLE_FLUID;
+    // the last flux pass also recovers the primitives, except in two-fluid steps on 3-D grids
+    // and with 16-row 2-D tiles, which run a separate recovery kernel: the recovery's
+    // registers make those tiles spill.  Measured: 1024^2 sheet (12-row tiles) 1.118 ->
+    // 1.099 ms per step fused; 512^2 sheet (16-row tiles) 0.321 -> 0.328 ms fused
+    const bool fused = M == RMHD_SINGLE_FLUID || c->prm.ndim == 1 || (c->prm.ndim == 2 && flux_rows_2d(c) == 12);
     // event pairs: stages, flux passes, recovery (kinds 0, 1, 2)
     int nev = 0, kinds[7];
     auto begin = [&]() {
