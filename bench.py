@@ -175,8 +175,8 @@ def measure_form(wl, steps: int, warmup: int, runs: int = 5, timing_steps: int =
                                    "flops_per_cell": PM.stage_flops_of(wl.model, st2) / max(1, st2["stage_cells"]),
                                    "ms_per_launch": stage_ms}
     fb = 0.5 * (PM.flux_bytes_per_cell(wl.model, "first") + PM.flux_bytes_per_cell(wl.model, "second"))
-    if wl.model == 1:   # the two-fluid step recovers its primitives in a separate kernel
-        fb -= 0.5 * 8 * PM.NPRIM[1]
+    if tm["c2p_launches"]:   # the new primitives come from a separate recovery kernel
+        fb -= 0.5 * 8 * PM.NPRIM[wl.model]
     gbs = fb * wl.cells / (flux_ms / 1e3) / 1e9
     out["kernels"]["flux"] = {"bound": "hbm", "achieved": gbs, "peak": PM.PEAK_HBM_GBS, "unit": "GB/s",
                               "frac": gbs / PM.PEAK_HBM_GBS, "bytes_per_cell": fb,
