@@ -77,33 +77,9 @@ __device__ __forceinline__ double frsqrt(double x)
 }
 
 // ---------------------------------------------------------------------------------------
-// forward-mode dual number (one tangent) for the exact stage Jacobian
+// forward-mode dual number with three tangents for the exact single-fluid stage Jacobian: one
+// forward pass yields the whole 3x3 Jacobian
 // ---------------------------------------------------------------------------------------
-struct dual {
-    double v, d;
-};
-__device__ __forceinline__ dual mk(double v, double d = 0.0) { return dual{v, d}; }
-__device__ __forceinline__ dual operator+(dual a, dual b) { return {a.v + b.v, a.d + b.d}; }
-__device__ __forceinline__ dual operator-(dual a, dual b) { return {a.v - b.v, a.d - b.d}; }
-__device__ __forceinline__ dual operator-(dual a) { return {-a.v, -a.d}; }
-__device__ __forceinline__ dual operator*(dual a, dual b) { return {a.v * b.v, a.v * b.d + a.d * b.v}; }
-__device__ __forceinline__ dual operator+(dual a, double b) { return {a.v + b, a.d}; }
-__device__ __forceinline__ dual operator+(double b, dual a) { return {a.v + b, a.d}; }
-__device__ __forceinline__ dual operator-(dual a, double b) { return {a.v - b, a.d}; }
-__device__ __forceinline__ dual operator-(double b, dual a) { return {b - a.v, -a.d}; }
-__device__ __forceinline__ dual operator*(dual a, double b) { return {a.v * b, a.d * b}; }
-__device__ __forceinline__ dual operator*(double b, dual a) { return {a.v * b, a.d * b}; }
-__device__ __forceinline__ dual recip(dual a)
-{
-    const double r = frcp(a.v);
-    return {r, -a.d * r * r};
-}
-__device__ __forceinline__ dual dsqrt(dual a)
-{
-    const double s = sqrt(a.v);
-    return {s, 0.5 * a.d * frcp(s)};
-}
-// three tangents at once: one forward pass yields a whole 3x3 Jacobian
 struct dual3 {
     double v, d0, d1, d2;
 };
@@ -133,11 +109,6 @@ __device__ __forceinline__ dual3 dsqrt(dual3 a)
 
 // 1/sqrt for scalars and duals
 __device__ __forceinline__ double rsqrt_t(double a) { return frsqrt(a); }
-__device__ __forceinline__ dual rsqrt_t(dual a)
-{
-    const double r = frsqrt(a.v);
-    return {r, -0.5 * a.d * r * r * r};
-}
 __device__ __forceinline__ dual3 rsqrt_t(dual3 a)
 {
     const double r = frsqrt(a.v), m = -0.5 * r * r * r;
@@ -149,13 +120,9 @@ __device__ __forceinline__ T lift(double v);
 template <>
 __device__ __forceinline__ double lift<double>(double v) { return v; }
 template <>
-__device__ __forceinline__ dual lift<dual>(double v) { return dual{v, 0.0}; }
-template <>
 __device__ __forceinline__ dual3 lift<dual3>(double v) { return dual3{v, 0.0, 0.0, 0.0}; }
 __device__ __forceinline__ double recip(double a) { return frcp(a); }
 __device__ __forceinline__ double dsqrt(double a) { return sqrt(a); }
-__device__ __forceinline__ double value(double a) { return a; }
-__device__ __forceinline__ double value(dual a) { return a.v; }
 
 template <class T>
 struct vec3 {
@@ -294,23 +261,27 @@ __device__ __forceinline__ Root fluid_root(double D, double s2, double Eh, doubl
 }
 
 // Tangent of the root z through the implicit-function theorem: with z fixed at the root,
-// dg = dg/ds2 ds2 + dg/dEh dEh, and dz = -(dg/ds2 ds2 + dg/dEh dEh) / (dg/dz).
-__device__ __forceinline__ dual root_tangent(const Root &r, double D, dual s2, dual Eh, const Phys &P)
+// dg = dg/ds2 ds2 + dg/dEh dEh, and dz = -(dg/ds2 ds2 + dg/dEh dEh) / (dg/dz).  Since
+// dg/dEh = -1, dz = (dEh - dg/ds2 ds2) / (dg/dz); root_partials gives dg/ds2 and 1/(dg/dz)
+// at the root (iz = 1/z).
+struct RootPartials {
+    double iz, dgds2, idgdz;
+};
+__device__ __forceinline__ RootPartials root_partials(const Root &r, double D, double s2, const Phys &P)
 {
-    const double z = r.z, iz = frcp(z), W = frcp(r.iW);
-    const double v2 = s2.v * iz * iz;
-    const double idgdz = frcp(1.0 - P.gk * (1.0 + v2 - D * v2 * iz * W));
-    const double dgds2 = P.gk * (iz - 0.5 * D * iz * iz * W);
-    return dual{z, (Eh.d - dgds2 * s2.d) * idgdz};
+    RootPartials q;
+    const double iz = frcp(r.z), W = frcp(r.iW);
+    const double v2 = s2 * iz * iz;
+    q.iz = iz;
+    q.idgdz = frcp(1.0 - P.gk * (1.0 + v2 - D * v2 * iz * W));
+    q.dgds2 = P.gk * (iz - 0.5 * D * iz * iz * W);
+    return q;
 }
 __device__ __forceinline__ dual3 root_tangent(const Root &r, double D, dual3 s2, dual3 Eh, const Phys &P)
 {
-    const double z = r.z, iz = frcp(z), W = frcp(r.iW);
-    const double v2 = s2.v * iz * iz;
-    const double idgdz = frcp(1.0 - P.gk * (1.0 + v2 - D * v2 * iz * W));
-    const double dgds2 = P.gk * (iz - 0.5 * D * iz * iz * W);
-    return dual3{z, (Eh.d0 - dgds2 * s2.d0) * idgdz, (Eh.d1 - dgds2 * s2.d1) * idgdz,
-                 (Eh.d2 - dgds2 * s2.d2) * idgdz};
+    const RootPartials q = root_partials(r, D, s2.v, P);
+    return dual3{r.z, (Eh.d0 - q.dgds2 * s2.d0) * q.idgdz, (Eh.d1 - q.dgds2 * s2.d1) * q.idgdz,
+                 (Eh.d2 - q.dgds2 * s2.d2) * q.idgdz};
 }
 __device__ __forceinline__ double root_tangent(const Root &r, double, double, double, const Phys &) { return r.z; }
 

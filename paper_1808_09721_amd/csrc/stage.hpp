@@ -5,9 +5,10 @@
 // runs the nested primitive recovery:
 //   single fluid  x = E                              (3 unknowns)
 //   two fluid     x = (Sbar/|mu1|, taubar/|mu1|, E)   (7 unknowns, barred parts scaled to O(1))
-// Newton with the exact Jacobian: forward-mode (dual-number) passes through the residual, in
-// which the recovery root z = rho h W^2 is differentiated by the implicit-function theorem at
-// the converged root instead of iterating in dual arithmetic.  Steps are halved (up to 30
+// Newton with the exact Jacobian (single fluid: one forward pass of three-tangent dual numbers;
+// two fluid: the chain rule written out through the residual's structure), in which the
+// recovery root z = rho h W^2 is differentiated by the implicit-function theorem at the
+// converged root instead of iterating in tangent arithmetic.  Steps are halved (up to 30
 // times) until the primitives stay physical and ||G||_inf drops; at ||G||_inf <= tol max(1,
 // ||R_x||_inf) one further Newton step is taken with the last Jacobian (it changed by the
 // order of the last step only), so the answer sits at round-off whatever the starting point.
@@ -283,29 +284,121 @@ __device__ __forceinline__ int tf_residual(const TFCell &c, const double (&x)[7]
     return CELL_OK;
 }
 
+// Exact Jacobian dG/dx by the chain rule through the residual's structure, the primal values
+// formed once and the seven directions propagated as plain tangents (no dual arithmetic, no
+// products with structurally zero tangents).  Per species s (mass-to-charge weight m, sign
+// sg = +-1/(mu1 - mu2) as in tf_split):
+//   dSs   = sg (sc dx_{0..2} - m B x dE)         ds2 = 2 Ss.dSs
+//   dEh   = sg (sc dx_3 + m E.dE)                dz  = (dEh - dg/ds2 ds2) / (dg/dz)
+//   dv    = (dSs - v dz) / z                     drho = -D_s (v.dv) / sqrt(1 - v^2)
+// and through the source terms (D_s W-weights fixed): d(omega_p^2), dU, dJ, d rho_0, then
+//   dPsi(Sbar) = M2 dE + dU x B - eta (d(omega_p^2) J + omega_p^2 dJ - dfr U - fr dU)
+//   dPsi(taubar) = dU.E + U.dE - eta (d(omega_p^2) rho_e - d rho_0 M2)
+// r: the recovery roots at x (from the residual evaluation at x).
 __device__ __forceinline__ void tf_jacobian(const TFCell &c, const double (&x)[7], const Root (&r)[2], const Phys &P,
                                             double (&A)[7][7])
 {
-    // the seven passes are independent: unrolled, they overlap in the instruction stream,
-    // which is what hides latency at one wavefront per SIMD (the stage needs ~450
-    // registers); measured 19 % off the two-fluid stage against one pass at a time
+    const vec3<double> E = v3(x[4], x[5], x[6]);
+    const vec3<double> &B = c.B;
+    vec3<double> Ss[2];
+    double s2[2], Eh[2];
+    tf_split(c, x, P, Ss, s2, Eh);
+    const double mu[2] = {P.mu1, P.mu2};
+    vec3<double> v[2], SxB[2];
+    double rho[2], kr[2], sgsc[2], sgm[2];
+    RootPartials q[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const double m = s == 0 ? P.mu2 : P.mu1, sg = s == 0 ? c.i12 : -c.i12;
+        q[s] = root_partials(r[s], c.Ds[s], s2[s], P);
+        v[s] = v3(Ss[s].x * q[s].iz, Ss[s].y * q[s].iz, Ss[s].z * q[s].iz);
+        const double sq = sqrt(1.0 - dot(v[s], v[s]));
+        rho[s] = c.Ds[s] * sq;
+        kr[s] = -c.Ds[s] * frcp(sq);
+        sgsc[s] = sg * c.sc;
+        sgm[s] = sg * m;
+        SxB[s] = cross(Ss[s], B);
+    }
+    const double cU[2] = {mu[0] * mu[0] * c.Ds[0], mu[1] * mu[1] * c.Ds[1]};
+    const double cJ[2] = {mu[0] * c.Ds[0], mu[1] * c.Ds[1]};
+    const double wp2 = mu[0] * mu[0] * rho[0] + mu[1] * mu[1] * rho[1];
+    const double iwp2 = frcp(wp2);
+    const double M2 = cU[0] + cU[1];
+    const double rhoe = cJ[0] + cJ[1];
+    const vec3<double> U = v3(cU[0] * v[0].x + cU[1] * v[1].x, cU[0] * v[0].y + cU[1] * v[1].y,
+                              cU[0] * v[0].z + cU[1] * v[1].z);
+    const vec3<double> J = v3(cJ[0] * v[0].x + cJ[1] * v[1].x, cJ[0] * v[0].y + cJ[1] * v[1].y,
+                              cJ[0] * v[0].z + cJ[1] * v[1].z);
+    const double rho0 = (M2 * rhoe - dot(J, U)) * iwp2;
+    const bool cov = P.friction_covariant;
+    const double fr = cov ? rho0 : rhoe;
+    const double eta = c.eta, ka = c.a * c.isc;
 #pragma unroll
     for (int k = 0; k < 7; ++k) {
-        dual xd[7];
+        // tangents of v_s and rho_s along x_k
+        vec3<double> dv[2];
+        double drho[2];
 #pragma unroll
-        for (int i = 0; i < 7; ++i) xd[i] = mk(x[i], i == k ? 1.0 : 0.0);
-        vec3<dual> Ss[2];
-        dual s2[2], Eh[2], z[2], G[7];
-        tf_split(c, xd, P, Ss, s2, Eh);
+        for (int s = 0; s < 2; ++s) {
+            const double vs[3] = {v[s].x, v[s].y, v[s].z};
+            double dS[3];      // dSs, entries flagged false are structurally zero
+            bool nz[3];
+            double ds2, dz;
+            if (k < 3) {
 #pragma unroll
-        for (int s = 0; s < 2; ++s) z[s] = root_tangent(r[s], c.Ds[s], s2[s], Eh[s], P);
-        tf_finish(c, xd, Ss, z, P, G);
+                for (int i = 0; i < 3; ++i) { nz[i] = i == k; dS[i] = sgsc[s]; }
+                const double Sk = k == 0 ? Ss[s].x : k == 1 ? Ss[s].y : Ss[s].z;
+                ds2 = 2.0 * sgsc[s] * Sk;
+                dz = -(q[s].dgds2 * ds2) * q[s].idgdz;
+            } else if (k == 3) {
+#pragma unroll
+                for (int i = 0; i < 3; ++i) { nz[i] = false; dS[i] = 0.0; }
+                dz = sgsc[s] * q[s].idgdz;
+            } else {
+                // -sg m (B x e_l), l = k - 4
+                const int l = k - 4;
+                const double bx[3][3] = {{0.0, B.z, -B.y}, {-B.z, 0.0, B.x}, {B.y, -B.x, 0.0}};
+#pragma unroll
+                for (int i = 0; i < 3; ++i) { nz[i] = i != l; dS[i] = -sgm[s] * bx[l][i]; }
+                const double SxBl = l == 0 ? SxB[s].x : l == 1 ? SxB[s].y : SxB[s].z;
+                const double El = l == 0 ? E.x : l == 1 ? E.y : E.z;
+                ds2 = -2.0 * sgm[s] * SxBl;
+                dz = (sgm[s] * El - q[s].dgds2 * ds2) * q[s].idgdz;
+            }
+            double d[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) d[i] = (nz[i] ? dS[i] - vs[i] * dz : -(vs[i] * dz)) * q[s].iz;
+            dv[s] = v3(d[0], d[1], d[2]);
+            drho[s] = kr[s] * dot(v[s], dv[s]);
+        }
+        const double dwp2 = mu[0] * mu[0] * drho[0] + mu[1] * mu[1] * drho[1];
+        const vec3<double> dU = v3(cU[0] * dv[0].x + cU[1] * dv[1].x, cU[0] * dv[0].y + cU[1] * dv[1].y,
+                                   cU[0] * dv[0].z + cU[1] * dv[1].z);
+        const vec3<double> dJ = v3(cJ[0] * dv[0].x + cJ[1] * dv[1].x, cJ[0] * dv[0].y + cJ[1] * dv[1].y,
+                                   cJ[0] * dv[0].z + cJ[1] * dv[1].z);
+        const double drho0 = -(dot(dJ, U) + dot(J, dU) + rho0 * dwp2) * iwp2;
+        const double dfr = cov ? drho0 : 0.0;
+        const vec3<double> dUxB = cross(dU, B);
+        const double Jc[3] = {J.x, J.y, J.z}, Uc[3] = {U.x, U.y, U.z};
+        const double dJc[3] = {dJ.x, dJ.y, dJ.z}, dUc[3] = {dU.x, dU.y, dU.z}, dUxBc[3] = {dUxB.x, dUxB.y, dUxB.z};
+        double dtaub = dot(dU, E) - eta * (dwp2 * rhoe - drho0 * M2);
+        if (k >= 4) dtaub += Uc[k - 4];
+        double col[7];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            double dSb = dUxBc[i] - eta * (dwp2 * Jc[i] + wp2 * dJc[i] - dfr * Uc[i] - fr * dUc[i]);
+            if (k == 4 + i) dSb += M2;
+            col[i] = -ka * dSb;
+            col[4 + i] = c.a * dJc[i];
+        }
+        col[3] = -ka * dtaub;
+        col[k] += 1.0;
 #pragma unroll
         for (int i = 0; i < 7; ++i) {
             // column k, selected without dynamic register indexing
 #pragma unroll
             for (int kk = 0; kk < 7; ++kk)
-                if (kk == k) A[i][kk] = G[i].d;
+                if (kk == k) A[i][kk] = col[i];
         }
     }
 }

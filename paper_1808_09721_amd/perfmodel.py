@@ -4,15 +4,15 @@ FLOPs are counted from the kernel source with +, -, *, /, sqrt each one FLOP and
 multiply-add two (divisions and square roots are therefore undercounted relative to their
 hardware cost, which only lowers the reported fraction).
 
-A Jacobian evaluation is counted as forward-mode differentiation needs it: the tangent
-propagation of each of its columns (7 two-fluid, 3 single-fluid), at the tangent-only cost
-of every elementary operation (add/sub 1, product with a constant 1, product of two
-varying values 3, reciprocal 3, square root 2), the primal values being those of the
-residual evaluation at the same iterate; plus the factorisation.  The kernel recomputes
-the primal in every pass (which overlaps the passes at one wavefront per SIMD), so it
-executes more than this; the counted figure stays below the FP64 operations the hardware
-counters report for the same dispatch (two-fluid 1024^2 sheet: 3.9 kFLOP counted against
-4.5 kFLOP executed on active lanes per cell and stage).
+A Jacobian evaluation is counted as its derivative work alone, the primal values being those
+of the residual evaluation at the same iterate.  Single fluid (forward-mode dual numbers): the
+tangent propagation of its 3 columns at the tangent-only cost of every elementary operation
+(add/sub 1, product with a constant 1, product of two varying values 3, reciprocal 3, square
+root 2), plus the inverse.  Two fluid (the chain rule written out): the tangent set-up shared
+by the 7 columns, each column's tangents, and the factorisation.  The kernels recompute the
+primal values the Jacobian needs instead of keeping them from the residual evaluation, so
+they execute somewhat more than this; the counted figure stays below the FP64 operations the
+hardware counters report for the same dispatch.
 
 Single-fluid implicit stage, per cell (stage.hpp, physics.hpp):
   primitive-recovery Newton iteration (fluid_root loop body)          22
@@ -28,10 +28,13 @@ Two-fluid implicit stage, per cell:
   primitive-recovery Newton iteration                                 22
   residual evaluation without the recovery iterations
     (split 62 + two recovery set-ups/finals 14 + finish 148)          224
-  Jacobian evaluation: 7 tangent columns of
-    (split 137 + two root tangents 38 + finish 371 as dual arithmetic, 546,
-     less the primal split 62 and finish 148) = 7 x 336 = 2352,
-    7x7 LU factorisation with pivoting 210                            2562
+  Jacobian evaluation by the chain rule (stage.hpp, tf_jacobian):
+    shared set-up: root partials 2 x 18, d rho / d(v.dv) 2 x 2,
+      species signs 2 x 2, S_s x B 2 x 9, mu_s^2 2, a/|mu1| 1        65
+    columns: species tangents 2 x (17, 17, 17, 13, 22, 22, 22)
+      + source tangents (89, 89, 89, 89, 91, 91, 91)                  889
+    7x7 LU factorisation with pivoting                                210
+                                                                      1164
   Newton step (LU solve 91, step update 15)                           106
   per-cell set-up, closed forms and final primitives                  110
 A Newton step counts every step a cell takes, the polishing step after convergence
@@ -48,7 +51,7 @@ from __future__ import annotations
 
 STAGE_FLOPS = {
     0: {"c2p_iter": 22, "residual": 87, "jacobian": 474, "newton": 21, "cell": 41},
-    1: {"c2p_iter": 22, "residual": 224, "jacobian": 2562, "newton": 106, "cell": 110},
+    1: {"c2p_iter": 22, "residual": 224, "jacobian": 1164, "newton": 106, "cell": 110},
 }
 
 NCONS = {0: 14, 1: 18}
