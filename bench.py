@@ -420,7 +420,7 @@ def main() -> int:
     k = plain["kernels"]
     dominant = "stage" if k["stage"]["ms_per_launch"] >= k["flux"]["ms_per_launch"] else "flux"
     roof = {kk: k[dominant][kk] for kk in ("bound", "achieved", "peak", "unit", "frac")}
-    roof["kernel"] = "implicit stage k_stage<1>" if dominant == "stage" else "flux pass k_flux<1, 2, 64, 16, *>"
+    roof["kernel"] = "implicit stage k_stage<1>" if dominant == "stage" else "flux pass k_flux<1, 2, 64, 12, *>"
     roof["traffic"] = measured_traffic("two_fluid_sheet_1024",
                                        "rmhd::k_stage<1>" if dominant == "stage" else "rmhd::k_flux<1, 2")
     value = plain["value"]

@@ -1046,7 +1046,10 @@ __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by
 // vectors formed up front and the x stencil read from neighbouring lanes, the 1024^2 sheet's
 // pass took 238-257 us against 227 us, spilling 76-240 bytes per lane at 16 rows).  The
 // two-fluid 2-D tile stages two variables per pair of barriers (239 against 253 us per pass
-// on the 1024^2 sheet at 16 rows, 221 against 245 us at 12 rows; 64 against 67 us on 512^2).
+// on the 1024^2 sheet at 16 rows, 221 against 245 us at 12 rows; 64 against 67 us on 512^2),
+// three in the 12-row tile, whose three rounds' arrays (147 KB) still fit the CU's LDS
+// (1024^2 sheet 226 against 232 us per pass); measured no better in the two-fluid row form
+// either (x stencil from neighbouring lanes, flux components formed per round: 236 us).
 // NO: outputs used (o[0..NO-1]), fixed at compile time so unused ones cost no registers.
 // RECOVER = false: the tile never recovers primitives (the x-y tiles of a 3-D pass, whose z
 // kernel completes the outputs), so the recovery's registers are not reserved.
@@ -1055,7 +1058,7 @@ __device__ __forceinline__ void flux_tile(const FluxArgs &A, int bx, int by, lon
 {
     static_assert(NO >= 1 && NO <= FLUX_MAXOUT, "outputs");
     if constexpr (M != 1 && NDIM == 2 && BX == 64) flux_tile_rows<M, BY, NO, RECOVER>(A, bx, by, zoff);
-    else flux_tile_lds<M, NDIM, BX, BY, NO, (M == 1 && NDIM == 2) ? 2 : 1, RECOVER>(A, bx, by, zoff);
+    else flux_tile_lds<M, NDIM, BX, BY, NO, (M == 1 && NDIM == 2) ? (BY <= 12 ? 3 : 2) : 1, RECOVER>(A, bx, by, zoff);
 }
 
 // Workgroups are dealt to the 8 XCDs in turn (linear id mod 8), each XCD with its own L2.

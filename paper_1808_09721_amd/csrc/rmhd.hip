@@ -323,23 +323,28 @@ static int launch_stage(rmhd_ctx *c, const StageArgs &A)
 static int flux_rows_2d(const rmhd_ctx *c)
 {
     if (c->flux_rows) return c->flux_rows;
-    const long tiles16 = (long)((c->prm.nx + 59) / 60) * ((c->prm.ny + 11) / 12);
-    return c->prm.model == RMHD_TWO_FLUID && tiles16 >= 4L * c->cus ? 12 : 16;
+    const long tiles12 = (long)((c->prm.nx + 59) / 60) * ((c->prm.ny + 7) / 8);
+    return c->prm.model == RMHD_TWO_FLUID && tiles12 >= 2L * c->cus ? 12 : 16;
 }
 
 template <int M, int NO>
 static void launch_flux_mo(rmhd_ctx *c, const FluxArgs &A)
 {
     if (c->prm.ndim == 3) {
-        // x and y terms per interior z plane (64 x 16 tiles), then the z term added in place;
+        // x and y terms per interior z plane (64 x 16 tiles, two fluid 64 x 12), then the z term
+        // added in place;
         // the z kernel completes output 0, so it alone writes the ghost images and recovers
         constexpr int BX = 64;
         FluxArgs Axy = A;
         Axy.fuse_bc = 0;
         Axy.wnew = Planes{};
-        const dim3 gxy((unsigned)((c->prm.nx + (BX - 4) - 1) / (BX - 4)), (unsigned)((c->prm.ny + 11) / 12),
-                       (unsigned)c->prm.nz);
-        hipLaunchKernelGGL((k_flux<M, 3, BX, 16, NO>), gxy, dim3(BX, 16), 0, c->stream, Axy);
+        const unsigned gx = (unsigned)((c->prm.nx + (BX - 4) - 1) / (BX - 4));
+        if constexpr (M == RMHD_TWO_FLUID)   // 64 x 12 tiles: the two-fluid tile's registers without spills
+            hipLaunchKernelGGL((k_flux<M, 3, BX, 12, NO>), dim3(gx, (unsigned)((c->prm.ny + 7) / 8), (unsigned)c->prm.nz),
+                               dim3(BX, 12), 0, c->stream, Axy);
+        else
+            hipLaunchKernelGGL((k_flux<M, 3, BX, 16, NO>), dim3(gx, (unsigned)((c->prm.ny + 11) / 12), (unsigned)c->prm.nz),
+                               dim3(BX, 16), 0, c->stream, Axy);
         const dim3 gz((unsigned)((c->prm.nx + BX - 1) / BX), (unsigned)c->prm.ny, (unsigned)((c->prm.nz + 11) / 12));
         hipLaunchKernelGGL((k_flux_z<M, NO>), gz, dim3(BX, 16), 0, c->stream, A);
     } else if (c->prm.ndim == 1) {
@@ -348,9 +353,12 @@ static void launch_flux_mo(rmhd_ctx *c, const FluxArgs &A)
         hipLaunchKernelGGL((k_flux<M, 1, BX, 1, NO>), grid, dim3(BX, 1), 0, c->stream, A);
     } else {
         // 64 x 16 tiles (12 interior rows) by default; 64 x 12 (8 rows) for two-fluid grids
-        // with at least four 16-row tiles per CU, whose 768-thread blocks fit the two-fluid
-        // tile's registers without spills (measured on the 1024^2 sheet: 221 against 239 us
-        // per pass; on 512^2, 1.5 tiles per CU, 70 against 64 us); 64 x 8 (4 rows) on request.
+        // with at least two 12-row tiles per CU, whose 768-thread blocks fit the two-fluid
+        // tile's registers without spills and let the last pass recover the primitives
+        // (measured on the 1024^2 sheet: 221 against 239 us per pass; on 512^2 the 12-row pass
+        // with the recovery, 70 us, against 66 + 14 us for 16 rows and a recovery kernel: step
+        // 0.310 against 0.316 ms; on 1024 x 128, 1.1 tiles per CU, 50 against 36 us per pass:
+        // a second, nearly empty round of blocks); 64 x 8 (4 rows) on request.
         // Measured on the 256 x 512 single-fluid grid, whose 16-row tiles leave some CUs idle,
         // 16 rows are still faster (30 us against 41 us at 8 rows, 40 us at 12).
         constexpr int BX = 64;

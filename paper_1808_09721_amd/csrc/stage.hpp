@@ -41,6 +41,23 @@ struct SFCell {
     vec3<double> S, B, RE;
 };
 
+// The cell's constants from its right-hand side R (14 conserved values), stage coefficient a
+// and conductivity sig.
+__device__ __forceinline__ SFCell sf_cell(const double *R, double a, double sig)
+{
+    SFCell c;
+    c.D = R[sf::D];
+    c.tau = R[sf::TAU];
+    c.rhoe = R[sf::RHOE];
+    c.S = v3(R[sf::SX], R[sf::SY], R[sf::SZ]);
+    c.B = v3(R[sf::BX], R[sf::BY], R[sf::BZ]);
+    c.B2 = dot(c.B, c.B);
+    c.RE = v3(R[sf::EX], R[sf::EY], R[sf::EZ]);
+    c.a = a;
+    c.sig = sig;
+    return c;
+}
+
 // Hydrodynamic inputs of the recovery at field E: St = S - E x B, Eh = tau - (E^2 + B^2)/2 + D.
 template <class T>
 __device__ __forceinline__ void sf_split(const SFCell &c, const vec3<T> &E, vec3<T> &St, T &s2, T &Eh)
@@ -129,16 +146,7 @@ __device__ inline int sf_stage(const double *R, double a, double sig, const Phys
                                int &newton_it, int &c2p_it, int &res_it, int cap = 1 << 30, double *gres = nullptr,
                                int *jac_it = nullptr)
 {
-    SFCell c;
-    c.D = R[sf::D];
-    c.tau = R[sf::TAU];
-    c.rhoe = R[sf::RHOE];
-    c.S = v3(R[sf::SX], R[sf::SY], R[sf::SZ]);
-    c.B = v3(R[sf::BX], R[sf::BY], R[sf::BZ]);
-    c.B2 = dot(c.B, c.B);
-    c.RE = v3(R[sf::EX], R[sf::EY], R[sf::EZ]);
-    c.a = a;
-    c.sig = sig;
+    const SFCell c = sf_cell(R, a, sig);
     newton_it = 0;
     double G[3], Eh;
     Root r;
@@ -215,6 +223,30 @@ struct TFCell {
     vec3<double> S, B, RSb, RE;
     double Rtb;
 };
+
+// The cell's constants from its right-hand side R (18 conserved values), stage coefficient a
+// and conductivity sig; D_s = rho_s W_s of each species from D and Dbar (Sec. 2.1.3).
+__device__ __forceinline__ TFCell tf_cell(const double *R, double a, double sig, const Phys &P)
+{
+    TFCell c;
+    c.D = R[tf::D];
+    c.tau = R[tf::TAU];
+    c.S = v3(R[tf::SX], R[tf::SY], R[tf::SZ]);
+    c.B = v3(R[tf::BX], R[tf::BY], R[tf::BZ]);
+    c.B2 = dot(c.B, c.B);
+    c.RSb = v3(R[tf::SBX], R[tf::SBY], R[tf::SBZ]);
+    c.Rtb = R[tf::TAUB];
+    c.RE = v3(R[tf::EX], R[tf::EY], R[tf::EZ]);
+    c.a = a;
+    c.eta = 1.0 / sig;
+    c.sc = fabs(P.mu1);
+    c.isc = 1.0 / c.sc;
+    c.i12 = 1.0 / (P.mu1 - P.mu2);
+    c.Ds[0] = (R[tf::DB] - P.mu2 * c.D) * c.i12;
+    c.Ds[1] = -(R[tf::DB] - P.mu1 * c.D) * c.i12;
+    c.rhoe = R[tf::DB];
+    return c;
+}
 
 // Species recovery inputs at unknowns x (Sec. 2.1.3, Eqs. 7-8).
 template <class T>
@@ -410,24 +442,7 @@ __device__ inline int tf_stage(const double *R, double a, double sig, const Phys
                                int &newton_it, int &c2p_it, int &res_it, const double *alt = nullptr,
                                int cap = 1 << 30, double *gres = nullptr, int *jac_it = nullptr)
 {
-    TFCell c;
-    c.D = R[tf::D];
-    c.tau = R[tf::TAU];
-    c.S = v3(R[tf::SX], R[tf::SY], R[tf::SZ]);
-    c.B = v3(R[tf::BX], R[tf::BY], R[tf::BZ]);
-    c.B2 = dot(c.B, c.B);
-    c.RSb = v3(R[tf::SBX], R[tf::SBY], R[tf::SBZ]);
-    c.Rtb = R[tf::TAUB];
-    c.RE = v3(R[tf::EX], R[tf::EY], R[tf::EZ]);
-    c.a = a;
-    c.eta = 1.0 / sig;
-    c.sc = fabs(P.mu1);
-    c.isc = 1.0 / c.sc;
-    c.i12 = 1.0 / (P.mu1 - P.mu2);
-    const double i12 = c.i12;
-    c.Ds[0] = (R[tf::DB] - P.mu2 * c.D) * i12;
-    c.Ds[1] = -(R[tf::DB] - P.mu1 * c.D) * i12;
-    c.rhoe = R[tf::DB];
+    const TFCell c = tf_cell(R, a, sig, P);
     newton_it = 0;
     double G[7], Eh[2];
     Root r[2];
