@@ -462,7 +462,7 @@ __device__ __forceinline__ void stage_start(const StageArgs &A, long idx, bool g
     if constexpr (M == 0) {
         x[0] = X0.p[sf::EX][idx]; x[1] = X0.p[sf::EY][idx]; x[2] = X0.p[sf::EZ][idx];
     } else {
-        const double isc = 1.0 / fabs(A.P.mu1);
+        const double isc = frcp(fabs(A.P.mu1));
         x[0] = X0.p[tf::SBX][idx] * isc; x[1] = X0.p[tf::SBY][idx] * isc; x[2] = X0.p[tf::SBZ][idx] * isc;
         x[3] = X0.p[tf::TAUB][idx] * isc;
         x[4] = X0.p[tf::EX][idx]; x[5] = X0.p[tf::EY][idx]; x[6] = X0.p[tf::EZ][idx];
@@ -480,7 +480,7 @@ __device__ __forceinline__ int stage_solve(const double *R, const StageArgs &A, 
         (void)alt;
         st = sf_stage(R, A.a, sig, P, x, w, n, c, r, cap, &gres, &jit);
     } else {
-        const double isc = 1.0 / fabs(P.mu1);
+        const double isc = frcp(fabs(P.mu1));
         const double rx[7] = {R[tf::SBX] * isc, R[tf::SBY] * isc, R[tf::SBZ] * isc, R[tf::TAUB] * isc,
                               R[tf::EX], R[tf::EY], R[tf::EZ]};
         st = tf_stage(R, A.a, sig, P, x, w, n, c, r, alt ? rx : nullptr, cap, &gres, &jit);
@@ -500,13 +500,13 @@ __device__ __forceinline__ void stage_write(const StageArgs &A, long idx, int i,
 {
     constexpr int NC = Model<M>::NC, NP = Model<M>::NP;
     const Geo &g = A.g;
-    const double aK = 1.0 / (1.0 + A.a * A.P.kappa);
+    const double aK = frcp(1.0 + A.a * A.P.kappa);
     if constexpr (M == 0) {
         A.Q.p[sf::EX][idx] = x[0]; A.Q.p[sf::EY][idx] = x[1]; A.Q.p[sf::EZ][idx] = x[2];
         A.Q.p[sf::PHI][idx] = R[sf::PHI] * aK;
         A.Q.p[sf::PSI][idx] = (R[sf::PSI] + A.a * R[sf::RHOE]) * aK;
     } else {
-        const double sc = fabs(A.P.mu1), isc = 1.0 / sc;
+        const double sc = fabs(A.P.mu1), isc = frcp(sc);
         A.Q.p[tf::SBX][idx] = x[0] * sc; A.Q.p[tf::SBY][idx] = x[1] * sc; A.Q.p[tf::SBZ][idx] = x[2] * sc;
         A.Q.p[tf::TAUB][idx] = x[3] * sc;
         A.Q.p[tf::EX][idx] = x[4]; A.Q.p[tf::EY][idx] = x[5]; A.Q.p[tf::EZ][idx] = x[6];

@@ -75,6 +75,13 @@ __device__ __forceinline__ double frsqrt(double x)
     e = fma(-h * r, r, 0.5);
     return fma(r, e, r);
 }
+// square root as x / sqrt(x) from the refined reciprocal square root (about two ulp): 0 at 0,
+// NaN below 0, where the state is unphysical anyway
+__device__ __forceinline__ double fsqrt(double x)
+{
+    const double r = x * frsqrt(x);
+    return x > 0.0 ? r : (x == 0.0 ? 0.0 : __builtin_nan(""));
+}
 
 // ---------------------------------------------------------------------------------------
 // forward-mode dual number with three tangents for the exact single-fluid stage Jacobian: one
@@ -103,7 +110,7 @@ __device__ __forceinline__ dual3 recip(dual3 a)
 }
 __device__ __forceinline__ dual3 dsqrt(dual3 a)
 {
-    const double s = sqrt(a.v), h = 0.5 * frcp(s);
+    const double s = fsqrt(a.v), h = 0.5 * frcp(s);
     return {s, a.d0 * h, a.d1 * h, a.d2 * h};
 }
 
@@ -122,7 +129,7 @@ __device__ __forceinline__ double lift<double>(double v) { return v; }
 template <>
 __device__ __forceinline__ dual3 lift<dual3>(double v) { return dual3{v, 0.0, 0.0, 0.0}; }
 __device__ __forceinline__ double recip(double a) { return frcp(a); }
-__device__ __forceinline__ double dsqrt(double a) { return sqrt(a); }
+__device__ __forceinline__ double dsqrt(double a) { return fsqrt(a); }
 
 template <class T>
 struct vec3 {
@@ -160,7 +167,7 @@ __device__ __forceinline__ Root fluid_root_z(double D, double s2, double Eh, dou
     r.iters = 0;
     r.z = zguess;
     r.iW = 1.0;
-    const double s = sqrt(s2);
+    const double s = fsqrt(s2);
     double lo = fmax(s, Eh);
     double hi = P.gamma * Eh;
     if (!(D > 0.0) || !(Eh > 0.0) || !(hi > lo)) {
@@ -209,7 +216,7 @@ __device__ __forceinline__ Root fluid_root_p(double D, double s2, double Eh, dou
     Root r;
     r.iters = 0;
     r.iW = 1.0;
-    const double s = sqrt(s2);
+    const double s = fsqrt(s2);
     double lo = fmax(s - Eh, 0.0), hi = (P.gamma - 1.0) * Eh;
     r.z = Eh + pguess;
     if (!(D > 0.0) || !(Eh > 0.0) || !(hi > lo)) {
@@ -540,7 +547,7 @@ __device__ inline void tf_flux_source(const double *q, const double *w, double s
     fy[tf::EX] = -B.z; fy[tf::EY] = q[tf::PSI]; fy[tf::EZ] = B.x;
     fx[tf::PSI] = E.x; fx[tf::PHI] = B.x;
     fy[tf::PSI] = E.y; fy[tf::PHI] = B.y;
-    const TFSource<double> S = tf_source_terms<double>(Dw, rho, v, E, B, 1.0 / sig, P);
+    const TFSource<double> S = tf_source_terms<double>(Dw, rho, v, E, B, frcp(sig), P);
     for (int k = 0; k < tf::NC; ++k) src[k] = 0.0;
     src[tf::SBX] = S.Sb.x; src[tf::SBY] = S.Sb.y; src[tf::SBZ] = S.Sb.z;
     src[tf::TAUB] = S.taub;
@@ -606,7 +613,7 @@ struct IdealSys {
 __device__ __forceinline__ void id_residual(const IdealSys &s, double Z, double y, double &F1, double &F2,
                                             double J[4])
 {
-    const double iZ = frcp(Z), u = 1.0 - y, su = sqrt(u);
+    const double iZ = frcp(Z), u = 1.0 - y, su = fsqrt(u);
     const double ZB = Z + s.B2;
     const double p = s.gk * (Z * u - s.D * su);
     F1 = y * ZB * ZB - s.SB2 * (s.B2 + 2.0 * Z) * iZ * iZ - s.S2;
@@ -629,7 +636,7 @@ __device__ inline int id_root_1d(const IdealSys &s, double &Z, double &y, int &i
         yy = (s.S2 * z * z + s.SB2 * (2.0 * z + s.B2)) * iz * iz * frcp(zb * zb);
         if (!(yy < 1.0)) return false;
         const double u = 1.0 - yy;
-        f = zb - s.gk * (z * u - s.D * sqrt(u)) - 0.5 * s.B2 * u - 0.5 * s.SB2 * iz * iz - s.Et;
+        f = zb - s.gk * (z * u - s.D * fsqrt(u)) - 0.5 * s.B2 * u - 0.5 * s.SB2 * iz * iz - s.Et;
         return true;
     };
     double lo = 0.0, hi = 2.0 * s.Et + 1.0, yy = 0.0, f = 0.0;
@@ -703,7 +710,7 @@ __device__ inline int id_cons2prim(const double *q, double *w, const Phys &P, in
     w[3] = (S.z + sZ * B.z) * iZB;
     // rho and p from the velocity actually returned, so that (rho, v, p) are consistent
     const double uw = 1.0 - (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]);
-    w[0] = s.D * sqrt(uw);
+    w[0] = s.D * fsqrt(uw);
     w[4] = P.gk * (Z * uw - w[0]);
     if (!(w[0] > 0.0) || !(w[4] > 0.0) || !(uw > 0.0)) return CELL_C2P_UNPHYS;
     return CELL_OK;

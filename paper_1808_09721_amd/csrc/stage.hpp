@@ -123,7 +123,7 @@ __device__ __forceinline__ bool inverse3(const double (&A)[3][3], double (&Ai)[3
     const double c02 = A[1][0] * A[2][1] - A[1][1] * A[2][0];
     const double det = A[0][0] * c00 + A[0][1] * c01 + A[0][2] * c02;
     if (!(det != 0.0) || !isfinite(det)) return false;
-    const double id = 1.0 / det;
+    const double id = frcp(det);
     Ai[0][0] = c00 * id;
     Ai[1][0] = c01 * id;
     Ai[2][0] = c02 * id;
@@ -193,7 +193,7 @@ __device__ inline int sf_stage(const double *R, double a, double sig, const Phys
             }
             if (!ok && !fresh && !conv) { ratio = 1.0; continue; }   // form the Jacobian afresh
             if (!ok) { st = conv ? CELL_OK : CELL_LINESEARCH; break; }
-            ratio = nrm > 0.0 ? maxabs(Gt) / nrm : 0.0;
+            ratio = nrm > 0.0 ? maxabs(Gt) * frcp(nrm) : 0.0;
 #pragma unroll
             for (int i = 0; i < 3; ++i) { x[i] = xt[i]; G[i] = Gt[i]; }
             r = rt;
@@ -202,13 +202,13 @@ __device__ inline int sf_stage(const double *R, double a, double sig, const Phys
             if (conv) { st = CELL_OK; break; }
         }
     }
-    if (gres) *gres = st == CELL_OK ? maxabs(G) / gscale : 0.0;
+    if (gres) *gres = st == CELL_OK ? maxabs(G) * frcp(gscale) : 0.0;
     // primitives at the final point
     const vec3<double> E = v3(x[0], x[1], x[2]);
     vec3<double> St;
     double s2;
     sf_split(c, E, St, s2, Eh);
-    const double iz = 1.0 / r.z;
+    const double iz = frcp(r.z);
     w[0] = c.D * r.iW;
     w[1] = St.x * iz; w[2] = St.y * iz; w[3] = St.z * iz;
     w[4] = r.z - Eh;
@@ -238,10 +238,10 @@ __device__ __forceinline__ TFCell tf_cell(const double *R, double a, double sig,
     c.Rtb = R[tf::TAUB];
     c.RE = v3(R[tf::EX], R[tf::EY], R[tf::EZ]);
     c.a = a;
-    c.eta = 1.0 / sig;
+    c.eta = frcp(sig);
     c.sc = fabs(P.mu1);
-    c.isc = 1.0 / c.sc;
-    c.i12 = 1.0 / (P.mu1 - P.mu2);
+    c.isc = frcp(c.sc);
+    c.i12 = frcp(P.mu1 - P.mu2);
     c.Ds[0] = (R[tf::DB] - P.mu2 * c.D) * c.i12;
     c.Ds[1] = -(R[tf::DB] - P.mu1 * c.D) * c.i12;
     c.rhoe = R[tf::DB];
@@ -344,9 +344,9 @@ __device__ __forceinline__ void tf_jacobian(const TFCell &c, const double (&x)[7
         const double m = s == 0 ? P.mu2 : P.mu1, sg = s == 0 ? c.i12 : -c.i12;
         q[s] = root_partials(r[s], c.Ds[s], s2[s], P);
         v[s] = v3(Ss[s].x * q[s].iz, Ss[s].y * q[s].iz, Ss[s].z * q[s].iz);
-        const double sq = sqrt(1.0 - dot(v[s], v[s]));
-        rho[s] = c.Ds[s] * sq;
-        kr[s] = -c.Ds[s] * frcp(sq);
+        const double u = 1.0 - dot(v[s], v[s]), rs = frsqrt(u);
+        rho[s] = c.Ds[s] * (u * rs);
+        kr[s] = -c.Ds[s] * rs;
         sgsc[s] = sg * c.sc;
         sgm[s] = sg * m;
         SxB[s] = cross(Ss[s], B);
@@ -510,7 +510,7 @@ __device__ inline int tf_stage(const double *R, double a, double sig, const Phys
             }
             if (!ok && !fresh && !conv) { ratio = 1.0; continue; }   // form the Jacobian afresh
             if (!ok) { st = conv ? CELL_OK : CELL_LINESEARCH; break; }
-            ratio = nrm > 0.0 ? maxabs(Gt) / nrm : 0.0;
+            ratio = nrm > 0.0 ? maxabs(Gt) * frcp(nrm) : 0.0;
 #pragma unroll
             for (int i = 0; i < 7; ++i) { x[i] = xt[i]; G[i] = Gt[i]; }
             r[0] = rt[0]; r[1] = rt[1];
@@ -519,13 +519,13 @@ __device__ inline int tf_stage(const double *R, double a, double sig, const Phys
             if (conv) { st = CELL_OK; break; }
         }
     }
-    if (gres) *gres = st == CELL_OK ? maxabs(G) / gscale : 0.0;
+    if (gres) *gres = st == CELL_OK ? maxabs(G) * frcp(gscale) : 0.0;
     vec3<double> Ss[2];
     double s2[2];
     tf_split(c, x, P, Ss, s2, Eh);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-        const double iz = 1.0 / r[s].z;
+        const double iz = frcp(r[s].z);
         double *ws = w + 5 * s;
         ws[0] = c.Ds[s] * r[s].iW;
         ws[1] = Ss[s].x * iz; ws[2] = Ss[s].y * iz; ws[3] = Ss[s].z * iz;
