@@ -70,10 +70,10 @@ __device__ __forceinline__ int cons2prim_m(const double *q, double *w, const Phy
 }
 template <int M>
 __device__ __forceinline__ void flux_source_m(const double *q, const double *w, double sig, const Phys &P, double *fx,
-                                              double *fy, double *src)
+                                              double *fy, double *src, bool need_src = true)
 {
     if constexpr (M == 0) sf_flux_source(q, w, sig, P, fx, fy, src);
-    else if constexpr (M == 1) tf_flux_source(q, w, sig, P, fx, fy, src);
+    else if constexpr (M == 1) tf_flux_source(q, w, sig, P, fx, fy, src, need_src);
     else id_flux_source(q, w, P, fx, fy, src);
 }
 template <int M>
@@ -808,7 +808,8 @@ __device__ __forceinline__ void flux_tile_lds(const FluxArgs &A, int bx, int by,
 #pragma unroll
     for (int v = 0; v < NP; ++v) w[v] = plane_at(A.w, v, g)[idx];
     const double sig = cell_sigma(A.P, idx);
-    flux_source_m<M>(q, w, sig, A.P, fx, fy, src);
+    // the halo rows' cells (whole wavefronts when a tile row is one wavefront) need no source
+    flux_source_m<M>(q, w, sig, A.P, fx, fy, src, NDIM == 1 || BX != 64 || (ty >= 2 && ty < BY - 2));
 
     const bool interior = tx >= 2 && tx < BX - 2 && ii < g.nx &&
                           (NDIM == 1 || (ty >= 2 && ty < BY - 2 && jj < g.ny));

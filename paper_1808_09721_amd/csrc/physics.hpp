@@ -505,8 +505,10 @@ __device__ __forceinline__ TFSource<T> tf_source_terms(const T Dw[2], const T rh
     return s;
 }
 
+// need_src false: the source terms are not wanted (left zero), e.g. for the halo rows of a flux
+// tile, whose cells only contribute face fluxes.
 __device__ inline void tf_flux_source(const double *q, const double *w, double sig, const Phys &P, double *fx,
-                                      double *fy, double *src)
+                                      double *fy, double *src, bool need_src = true)
 {
     const vec3<double> B = v3(q[tf::BX], q[tf::BY], q[tf::BZ]), E = v3(q[tf::EX], q[tf::EY], q[tf::EZ]);
     const double mu[2] = {P.mu1, P.mu2};
@@ -547,11 +549,13 @@ __device__ inline void tf_flux_source(const double *q, const double *w, double s
     fy[tf::EX] = -B.z; fy[tf::EY] = q[tf::PSI]; fy[tf::EZ] = B.x;
     fx[tf::PSI] = E.x; fx[tf::PHI] = B.x;
     fy[tf::PSI] = E.y; fy[tf::PHI] = B.y;
-    const TFSource<double> S = tf_source_terms<double>(Dw, rho, v, E, B, frcp(sig), P);
     for (int k = 0; k < tf::NC; ++k) src[k] = 0.0;
-    src[tf::SBX] = S.Sb.x; src[tf::SBY] = S.Sb.y; src[tf::SBZ] = S.Sb.z;
-    src[tf::TAUB] = S.taub;
-    src[tf::EX] = -S.J.x; src[tf::EY] = -S.J.y; src[tf::EZ] = -S.J.z;
+    if (need_src) {
+        const TFSource<double> S = tf_source_terms<double>(Dw, rho, v, E, B, frcp(sig), P);
+        src[tf::SBX] = S.Sb.x; src[tf::SBY] = S.Sb.y; src[tf::SBZ] = S.Sb.z;
+        src[tf::TAUB] = S.taub;
+        src[tf::EX] = -S.J.x; src[tf::EY] = -S.J.y; src[tf::EZ] = -S.J.z;
+    }
     src[tf::PSI] = q[tf::DB] - P.kappa * q[tf::PSI];
     src[tf::PHI] = -P.kappa * q[tf::PHI];
 }
