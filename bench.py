@@ -14,7 +14,7 @@ default); the learned form (the network's starting guess, the same FP64 Newton t
 trained on the device before its timed region.  The other configurations (1-D Brio-Wu tube, 2-D Kelvin-Helmholtz
 256 x 512, two-fluid sheet 512^2, the 64-domain batch) are reported as secondary fields.
 
-Prints one JSON line.  ``--gpus`` above 1 is refused: this build measures one GPU.
+Prints one JSON line.  ``--gpus`` above 1 is refused: the benchmark measures one GPU.
 """
 from __future__ import annotations
 
@@ -392,7 +392,8 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures a single GPU; --gpus {args.gpus} is not supported "
-              "(the path shards by domain slabs, see DESIGN.md)", file=sys.stderr)
+              "(the multi-GPU form would shard the grid into slabs with a halo exchange per flux pass; it is not built)",
+              file=sys.stderr)
         return 2
 
     import torch
