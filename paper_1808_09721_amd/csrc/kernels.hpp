@@ -9,8 +9,8 @@
 //   k_stage   implicit-stage Newton solve per cell, ghosts included (Sec. 2.2.1 Eq. 10)
 //   k_flux    FVS + WENO3 flux divergence L (Sec. 2.2.2 Eq. 12), fused with the SSP2 stage
 //             combiners (Eqs. 10-11, Table 2), with the ghost fill of its first output and
-//             (single fluid, ideal) the recovery of that output's primitives; on 3-D grids
-//             k_flux forms the x and y terms and k_flux_z adds the z term and does the rest
+//             the recovery of that output's primitives; on 3-D grids k_flux_z forms the z
+//             term first and the x-y tiles of k_flux add it and do the rest
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -703,6 +703,9 @@ struct FluxArgs {
     // (guess: w) and write them, with their ghost images, to wnew, which must not alias w
     // (halo cells of other tiles still read w)
     Planes wnew;
+    // 3-D: the z term L_z of every variable at the interior cells, formed by k_flux_z before
+    // the x-y tiles, which add it and complete the outputs
+    Planes lz;
 };
 
 // Plane v of a set whose planes lie g.plane doubles apart, as the outputs, bases and
@@ -747,7 +750,8 @@ __device__ __forceinline__ void store_with_images3(double *plane, const Geo &g, 
 // Primitives of a cell's new state q (guess w), written with the ghost images of the cell.
 template <int M>
 __device__ __forceinline__ void flux_recover(const FluxArgs &A, const double *q, const double *w,
-                                            const int (&xi)[3], const int (&yj)[3], int ny_img, long zoff)
+                                            const int (&xi)[3], const int (&yj)[3], const int (&zk)[3], bool img_xy,
+                                            bool img)
 {
     constexpr int NP = Model<M>::NP;
     double wn[NP];
@@ -755,9 +759,8 @@ __device__ __forceinline__ void flux_recover(const FluxArgs &A, const double *q,
     for (int v = 0; v < NP; ++v) wn[v] = w[v];
     int it = 0;
     cons2prim_m<M>(q, wn, A.P, it);
-    const bool img = xi[1] >= 0 || xi[2] >= 0 || yj[1] >= 0 || yj[2] >= 0;
 #pragma unroll
-    for (int v = 0; v < NP; ++v) store_with_images(plane_at(A.wnew, v, A.g), zoff, A.g.pitch, xi, yj, ny_img, img, wn[v]);
+    for (int v = 0; v < NP; ++v) store_with_images3(plane_at(A.wnew, v, A.g), A.g, xi, yj, zk, img_xy, img, wn[v]);
 }
 
 // WENO3 value at the downwind face of b from the upwind-ordered stencil (a, b, c):
@@ -785,7 +788,7 @@ __device__ __forceinline__ void weno3_pair(double ap, double bp, double cp, doub
 // rows span several wavefronts); every thread of the block must call it (it holds
 // barriers).  (bx, by) is the tile position in units of interior tiles; zoff is the offset of
 // the z plane (0 below 3-D, where a 2-D tile forms the x and y terms of one plane).
-template <int M, int NDIM, int BX, int BY, int NO, int GV = 1, bool RECOVER = true>
+template <int M, int NDIM, int BX, int BY, int NO, int GV = 1, bool RECOVER = true, bool Z3 = false>
 __device__ __forceinline__ void flux_tile_lds(const FluxArgs &A, int bx, int by, long zoff)
 {
     constexpr int NC = Model<M>::NC, NP = Model<M>::NP;
@@ -816,20 +819,27 @@ __device__ __forceinline__ void flux_tile_lds(const FluxArgs &A, int bx, int by,
     const bool do_x = tx >= 1 && tx <= BX - 2 && (NDIM == 1 || (ty >= 2 && ty <= BY - 3));
     const bool do_y = NDIM == 2 && ty >= 1 && ty <= BY - 2 && tx >= 2 && tx <= BX - 3;
 
-    // ghost images of this interior cell (fused boundary fill of output 0)
-    int xi[3] = {i, -1, -1}, yj[3] = {j, -1, -1};
-    if (A.fuse_bc && interior) ghost_images(g, ii, jj, NDIM == 2, xi, yj);
-    const bool img = xi[1] >= 0 || xi[2] >= 0 || yj[1] >= 0 || yj[2] >= 0;
+    // ghost images of this interior cell (fused boundary fill of output 0; on a 3-D grid in z
+    // as well, the tile completing the outputs there)
+    int xi[3] = {i, -1, -1}, yj[3] = {j, -1, -1}, zk[3] = {Z3 ? (int)(zoff / g.slab) : 0, -1, -1};
+    if (A.fuse_bc && interior) {
+        ghost_images(g, ii, jj, NDIM == 2, xi, yj);
+        if constexpr (Z3) images_1d(g.bc, g.nz, zk[0] - 2, zk);
+    }
+    const bool img_xy = xi[1] >= 0 || xi[2] >= 0 || yj[1] >= 0 || yj[2] >= 0;
+    const bool img = img_xy || zk[1] >= 0 || zk[2] >= 0;
 
 #pragma unroll
     for (int v0 = 0; v0 < NC; v0 += GV) {
-        // base terms first, so that their loads overlap the reconstruction
-        double bv[GV][NO];
+        // base terms (and the z term) first, so that their loads overlap the reconstruction
+        double bv[GV][NO], lzv[GV];
 #pragma unroll
-        for (int gv = 0; gv < GV; ++gv)
+        for (int gv = 0; gv < GV; ++gv) {
 #pragma unroll
             for (int k = 0; k < NO; ++k)
                 bv[gv][k] = (v0 + gv < NC && interior && A.o[k].base.p[0]) ? plane_at(A.o[k].base, v0 + gv, g)[idx] : 0.0;
+            lzv[gv] = (Z3 && v0 + gv < NC && interior) ? plane_at(A.lz, v0 + gv, g)[idx] : 0.0;
+        }
 #pragma unroll
         for (int gv = 0; gv < GV; ++gv) {
             const int v = v0 + gv;
@@ -874,6 +884,7 @@ __device__ __forceinline__ void flux_tile_lds(const FluxArgs &A, int bx, int by,
                 if constexpr (NDIM == 2)
                     L -= ((shp[gv][NDIM - 1][ty][tx] + shm[gv][NDIM - 1][ty + 1][tx]) -
                           (shp[gv][NDIM - 1][ty - 1][tx] + shm[gv][NDIM - 1][ty][tx])) * g.idy;
+                if constexpr (Z3) L += lzv[gv];
                 const double S = has_source(M, v) ? src[v] : 0.0;
                 double o0 = 0.0;
 #pragma unroll
@@ -882,7 +893,7 @@ __device__ __forceinline__ void flux_tile_lds(const FluxArgs &A, int bx, int by,
                     const double o = bv[gv][k] + F.cL * L + F.cS * S;
                     if (k == 0) {
                         o0 = o;
-                        store_with_images(plane_at(F.out, v, g), zoff, g.pitch, xi, yj, NDIM == 2 ? 3 : 1, img, o);
+                        store_with_images3(plane_at(F.out, v, g), g, xi, yj, zk, img_xy, img, o);
                     } else {
                         plane_at(F.out, v, g)[idx] = o;
                     }
@@ -892,7 +903,7 @@ __device__ __forceinline__ void flux_tile_lds(const FluxArgs &A, int bx, int by,
         }
     }
     if constexpr (RECOVER)
-        if (A.wnew.p[0] && interior) flux_recover<M>(A, q, w, xi, yj, NDIM == 2 ? 3 : 1, zoff);
+        if (A.wnew.p[0] && interior) flux_recover<M>(A, q, w, xi, yj, zk, img_xy, img);
 }
 
 // Row-form flux components per model (single fluid and ideal; the two-fluid model uses the
@@ -937,7 +948,7 @@ __device__ __forceinline__ double from_right(double v) { return dpp_shift<0x130>
 // the x stencil is read from neighbouring lanes (no LDS, no barrier) and only the y stencil
 // goes through LDS, G variables per pair of barriers.  The arithmetic per face and cell is
 // that of flux_tile_lds.  Every thread of the block must call it.
-template <int M, int BY, int NO, bool RECOVER = true>
+template <int M, int BY, int NO, bool RECOVER = true, bool Z3 = false>
 __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by, long zoff)
 {
     constexpr int NC = Model<M>::NC, NP = Model<M>::NP;
@@ -963,22 +974,29 @@ __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by
     const bool interior = tx >= 2 && tx < BX - 2 && ii < g.nx && ty >= 2 && ty < BY - 2 && jj < g.ny;
     const bool do_y = ty >= 1 && ty <= BY - 2 && tx >= 2 && tx <= BX - 3;
 
-    // ghost images of this interior cell (fused boundary fill of output 0)
-    int xi[3] = {i, -1, -1}, yj[3] = {j, -1, -1};
-    if (A.fuse_bc && interior) ghost_images(g, ii, jj, true, xi, yj);
-    const bool img = xi[1] >= 0 || xi[2] >= 0 || yj[1] >= 0 || yj[2] >= 0;
+    // ghost images of this interior cell (fused boundary fill of output 0; on a 3-D grid in z
+    // as well, the tile completing the outputs there)
+    int xi[3] = {i, -1, -1}, yj[3] = {j, -1, -1}, zk[3] = {Z3 ? (int)(zoff / g.slab) : 0, -1, -1};
+    if (A.fuse_bc && interior) {
+        ghost_images(g, ii, jj, true, xi, yj);
+        if constexpr (Z3) images_1d(g.bc, g.nz, zk[0] - 2, zk);
+    }
+    const bool img_xy = xi[1] >= 0 || xi[2] >= 0 || yj[1] >= 0 || yj[2] >= 0;
+    const bool img = img_xy || zk[1] >= 0 || zk[2] >= 0;
 
 #pragma unroll
     for (int v0 = 0; v0 < NC; v0 += G) {
         // the base terms of this round's outputs, loaded first so that their latency is
         // spent on the x reconstructions below (base is read only at interior cells, ghost
         // images are written only at ghost cells, so no store of this pass can change them)
-        double bv[G][NO];
+        double bv[G][NO], lzv[G];
 #pragma unroll
-        for (int k = 0; k < G; ++k)
+        for (int k = 0; k < G; ++k) {
 #pragma unroll
             for (int kk = 0; kk < NO; ++kk)
                 bv[k][kk] = (v0 + k < NC && interior && A.o[kk].base.p[0]) ? plane_at(A.o[kk].base, v0 + k, g)[idx] : 0.0;
+            lzv[k] = (Z3 && v0 + k < NC && interior) ? plane_at(A.lz, v0 + k, g)[idx] : 0.0;
+        }
         double Lx[G];
 #pragma unroll
         for (int k = 0; k < G; ++k) {
@@ -1015,13 +1033,14 @@ __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by
                 if (v >= NC) break;
                 double L = Lx[k];
                 L -= ((shp[k][ty][tx] + shm[k][ty + 1][tx]) - (shp[k][ty - 1][tx] + shm[k][ty][tx])) * g.idy;
+                if constexpr (Z3) L += lzv[k];
                 const double S = row_source<M>(v, q, I, A.P);
 #pragma unroll
                 for (int kk = 0; kk < NO; ++kk) {
                     const FluxOut &F = A.o[kk];
                     const double o = bv[k][kk] + F.cL * L + F.cS * S;
                     if (kk == 0) {
-                        store_with_images(plane_at(F.out, v, g), zoff, g.pitch, xi, yj, 3, img, o);
+                        store_with_images3(plane_at(F.out, v, g), g, xi, yj, zk, img_xy, img, o);
                     } else {
                         plane_at(F.out, v, g)[idx] = o;
                     }
@@ -1037,7 +1056,7 @@ __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by
             double qn[NC];
 #pragma unroll
             for (int v = 0; v < NC; ++v) qn[v] = plane_at(A.o[0].out, v, g)[idx];
-            flux_recover<M>(A, qn, w, xi, yj, 3, zoff);
+            flux_recover<M>(A, qn, w, xi, yj, zk, img_xy, img);
         }
 }
 
@@ -1054,12 +1073,14 @@ __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by
 // NO: outputs used (o[0..NO-1]), fixed at compile time so unused ones cost no registers.
 // RECOVER = false: the tile never recovers primitives (the x-y tiles of a 3-D pass, whose z
 // kernel completes the outputs), so the recovery's registers are not reserved.
-template <int M, int NDIM, int BX, int BY, int NO, bool RECOVER = true>
+template <int M, int NDIM, int BX, int BY, int NO, bool RECOVER = true, bool Z3 = false>
 __device__ __forceinline__ void flux_tile(const FluxArgs &A, int bx, int by, long zoff = 0)
 {
     static_assert(NO >= 1 && NO <= FLUX_MAXOUT, "outputs");
-    if constexpr (M != 1 && NDIM == 2 && BX == 64) flux_tile_rows<M, BY, NO, RECOVER>(A, bx, by, zoff);
-    else flux_tile_lds<M, NDIM, BX, BY, NO, (M == 1 && NDIM == 2) ? (BY <= 12 ? 3 : 2) : 1, RECOVER>(A, bx, by, zoff);
+    if constexpr (M != 1 && NDIM == 2 && BX == 64) flux_tile_rows<M, BY, NO, RECOVER, Z3>(A, bx, by, zoff);
+    else
+        flux_tile_lds<M, NDIM, BX, BY, NO, (M == 1 && NDIM == 2) ? (BY <= 12 ? 3 : 2) : 1, RECOVER, Z3>(A, bx, by,
+                                                                                                         zoff);
 }
 
 // Workgroups are dealt to the 8 XCDs in turn (linear id mod 8), each XCD with its own L2.
@@ -1090,7 +1111,7 @@ __device__ __forceinline__ void xcd_tile3(int &bx, int &by, int &bz)
 }
 
 // Flux pass.  NDIM = 3: one 2-D tile of an interior z plane (blockIdx.z), forming
-// out_k = base_k + c_kL (Lx + Ly) + c_kS Psi; k_flux_z then adds c_kL Lz.
+// out_k = base_k + c_kL (Lx + Ly + Lz) + c_kS Psi with Lz from k_flux_z (launched first).
 template <int M, int NDIM, int BX, int BY, int NO>
 __global__ __launch_bounds__(BX *BY) void k_flux(FluxArgs A)
 {
@@ -1098,7 +1119,7 @@ __global__ __launch_bounds__(BX *BY) void k_flux(FluxArgs A)
     if constexpr (NDIM == 3) {
         int bz;
         xcd_tile3(bx, by, bz);
-        flux_tile<M, 2, BX, BY, NO, false>(A, bx, by, (long)(bz + 2) * A.g.slab);
+        flux_tile<M, 2, BX, BY, NO, NO == 1 || M == 2, true>(A, bx, by, (long)(bz + 2) * A.g.slab);
     } else {
         if constexpr (NDIM == 2) xcd_tile(bx, by);
         // only a step's last pass (one output) recovers primitives, except in the ideal
@@ -1107,14 +1128,14 @@ __global__ __launch_bounds__(BX *BY) void k_flux(FluxArgs A)
     }
 }
 
-// z term of a 3-D flux pass, after k_flux: out_k += c_kL Lz on every interior cell, with
-// Lz = -(H_{k+1/2} - H_{k-1/2}) / dz from the split z fluxes reconstructed as in x and y.
-// Blocks of 64 (x) x 16 (z) threads: one x row of one y row per wavefront, the z stencil
-// through LDS with two halo planes on each side (12 interior planes per block, no x halo).
-// This kernel completes output 0, so it also writes that output's ghost images in all three
-// directions (fuse_bc) and recovers its primitives (wnew), as the 2-D tile kernels do.
-// Every thread of the block reaches every barrier.
-template <int M, int NO>
+// z term of a 3-D flux pass, before k_flux: Lz = -(H_{k+1/2} - H_{k-1/2}) / dz at every
+// interior cell, from the split z fluxes reconstructed as in x and y, written to A.lz; the
+// x-y tiles then add it to L and complete the outputs (ghost images in all three directions,
+// recovery), so no output is read back and written again.  Blocks of 64 (x) x 16 (z) threads:
+// one x row of one y row per wavefront, the z stencil through LDS with two halo planes on each
+// side (12 interior planes per block, no x halo).  Every thread of the block reaches every
+// barrier.
+template <int M>
 __global__ __launch_bounds__(1024) void k_flux_z(FluxArgs A)
 {
     constexpr int NC = Model<M>::NC, NP = Model<M>::NP;
@@ -1139,22 +1160,8 @@ __global__ __launch_bounds__(1024) void k_flux_z(FluxArgs A)
 
     const bool interior = ii < g.nx && tz >= 2 && tz < BZ - 2 && kk < g.nz;
     const bool do_z = tz >= 1 && tz <= BZ - 2;
-    // ghost images of this interior cell (output 0 and the recovered primitives)
-    int xi[3] = {i, -1, -1}, yj[3] = {by + 2, -1, -1}, zk[3] = {k, -1, -1};
-    if (A.fuse_bc && interior) {
-        ghost_images(g, ii, by, true, xi, yj);
-        images_1d(g.bc, g.nz, kk, zk);
-    }
-    const bool img_xy = xi[1] >= 0 || xi[2] >= 0 || yj[1] >= 0 || yj[2] >= 0;
-    const bool img = img_xy || zk[1] >= 0 || zk[2] >= 0;
 #pragma unroll
     for (int v0 = 0; v0 < NC; v0 += G) {
-        // this round's outputs, read first so that the loads overlap the reconstruction
-        double ov[G][NO];
-#pragma unroll
-        for (int c = 0; c < G; ++c)
-#pragma unroll
-            for (int o = 0; o < NO; ++o) ov[c][o] = (v0 + c < NC && interior) ? plane_at(A.o[o].out, v0 + c, g)[idx] : 0.0;
 #pragma unroll
         for (int c = 0; c < G; ++c) {
             const int v = v0 + c;
@@ -1180,33 +1187,12 @@ __global__ __launch_bounds__(1024) void k_flux_z(FluxArgs A)
             for (int c = 0; c < G; ++c) {
                 const int v = v0 + c;
                 if (v >= NC) break;
-                const double Lz =
+                plane_at(A.lz, v, g)[idx] =
                     -((shp[c][tz][tx] + shm[c][tz + 1][tx]) - (shp[c][tz - 1][tx] + shm[c][tz][tx])) * g.idz;
-#pragma unroll
-                for (int o = 0; o < NO; ++o) {
-                    const double val = ov[c][o] + A.o[o].cL * Lz;
-                    if (o == 0) {
-                        store_with_images3(plane_at(A.o[0].out, v, g), g, xi, yj, zk, img_xy, img, val);
-                        q[v] = val;   // this thread's own q[v] is not read again
-                    } else {
-                        plane_at(A.o[o].out, v, g)[idx] = val;
-                    }
-                }
             }
         }
         // sfp/sfm are rewritten only after every thread has passed the second barrier above,
         // shp/shm only after the next round's first barrier
-    }
-    // primitives of output 0 (guess: w), with their ghost images; a 3-D two-fluid step
-    // recovers in a kernel of its own (the recovery would make this kernel spill)
-    if (M != 1 && A.wnew.p[0] && interior) {
-        double wn[NP];
-#pragma unroll
-        for (int v = 0; v < NP; ++v) wn[v] = w[v];
-        int it = 0;
-        cons2prim_m<M>(q, wn, A.P, it);
-#pragma unroll
-        for (int v = 0; v < NP; ++v) store_with_images3(plane_at(A.wnew, v, g), g, xi, yj, zk, img_xy, img, wn[v]);
     }
 }
 

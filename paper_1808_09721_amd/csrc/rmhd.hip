@@ -31,6 +31,7 @@ struct rmhd_ctx {
     double *acc;      // q^n + sum_j w_j dt [L(Q_j) + Psi(Q_j)], accumulated (ncons planes)
     double *r3, *w2;  // SSP3(332): third-stage right-hand side, solved in place (ncons planes);
                       // second-stage primitives (nprim planes)
+    double *lz;       // 3-D: the z term of a flux pass (ncons planes)
     int8_t *status;   // one plane
     int32_t *iters;   // one plane
     unsigned long long *stats;  // STATS_SLOTS x STATS_STRIDE counters
@@ -177,6 +178,7 @@ extern "C" int rmhd_create(const rmhd_params *p, void *stream, rmhd_ctx **out)
     if (e == hipSuccess) e = hipMalloc((void **)&c->acc, pl * L.ncons);
     if (e == hipSuccess && p->integrator == RMHD_SSP3_332) e = hipMalloc((void **)&c->r3, pl * L.ncons);
     if (e == hipSuccess && p->integrator == RMHD_SSP3_332) e = hipMalloc((void **)&c->w2, pl * L.nprim);
+    if (e == hipSuccess && p->ndim == 3) e = hipMalloc((void **)&c->lz, pl * L.ncons);
     if (e == hipSuccess) e = hipMalloc((void **)&c->status, (size_t)L.plane);
     if (e == hipSuccess) e = hipMalloc((void **)&c->iters, (size_t)L.plane * sizeof(int32_t));
     const int nx_unk = p->model == RMHD_TWO_FLUID ? 7 : 3;
@@ -239,6 +241,7 @@ extern "C" void rmhd_destroy(rmhd_ctx *c)
     hipFree(c->r2);
     hipFree(c->acc);
     hipFree(c->r3);
+    hipFree(c->lz);
     hipFree(c->w2);
     hipFree(c->status);
     hipFree(c->iters);
@@ -331,22 +334,21 @@ template <int M, int NO>
 static void launch_flux_mo(rmhd_ctx *c, const FluxArgs &A)
 {
     if (c->prm.ndim == 3) {
-        // x and y terms per interior z plane (64 x 16 tiles, two fluid 64 x 12), then the z term
-        // added in place;
-        // the z kernel completes output 0, so it alone writes the ghost images and recovers
+        // the z term of every interior cell first, then the x and y terms per interior z plane
+        // (64 x 16 tiles, two fluid 64 x 12), which add it, complete the outputs, write their
+        // ghost images in all three directions and recover the primitives
         constexpr int BX = 64;
-        FluxArgs Axy = A;
-        Axy.fuse_bc = 0;
-        Axy.wnew = Planes{};
+        FluxArgs Az = A;
+        Az.lz = planes_of(c->lz, c->lay, c->lay.ncons);
+        const dim3 gz((unsigned)((c->prm.nx + BX - 1) / BX), (unsigned)c->prm.ny, (unsigned)((c->prm.nz + 11) / 12));
+        hipLaunchKernelGGL((k_flux_z<M>), gz, dim3(BX, 16), 0, c->stream, Az);
         const unsigned gx = (unsigned)((c->prm.nx + (BX - 4) - 1) / (BX - 4));
         if constexpr (M == RMHD_TWO_FLUID)   // 64 x 12 tiles: the two-fluid tile's registers without spills
             hipLaunchKernelGGL((k_flux<M, 3, BX, 12, NO>), dim3(gx, (unsigned)((c->prm.ny + 7) / 8), (unsigned)c->prm.nz),
-                               dim3(BX, 12), 0, c->stream, Axy);
+                               dim3(BX, 12), 0, c->stream, Az);
         else
             hipLaunchKernelGGL((k_flux<M, 3, BX, 16, NO>), dim3(gx, (unsigned)((c->prm.ny + 11) / 12), (unsigned)c->prm.nz),
-                               dim3(BX, 16), 0, c->stream, Axy);
-        const dim3 gz((unsigned)((c->prm.nx + BX - 1) / BX), (unsigned)c->prm.ny, (unsigned)((c->prm.nz + 11) / 12));
-        hipLaunchKernelGGL((k_flux_z<M, NO>), gz, dim3(BX, 16), 0, c->stream, A);
+                               dim3(BX, 16), 0, c->stream, Az);
     } else if (c->prm.ndim == 1) {
         constexpr int BX = 256;
         dim3 grid((c->prm.nx + (BX - 4) - 1) / (BX - 4));
@@ -628,7 +630,7 @@ static int enqueue_imex(rmhd_ctx *c, double dt, double *cons, double *prims)
     // and with 16-row 2-D tiles, which run a separate recovery kernel: the recovery's
     // registers make those tiles spill.  Measured: 1024^2 sheet (12-row tiles) 1.118 ->
     // 1.099 ms per step fused; 512^2 sheet (16-row tiles) 0.321 -> 0.328 ms fused
-    const bool fused = M == RMHD_SINGLE_FLUID || c->prm.ndim == 1 || (c->prm.ndim == 2 && flux_rows_2d(c) == 12);
+    const bool fused = M == RMHD_SINGLE_FLUID || c->prm.ndim != 2 || flux_rows_2d(c) == 12;
     // event pairs: stages, flux passes, recovery (kinds 0, 1, 2)
     int nev = 0, kinds[7];
     auto begin = [&]() {
@@ -922,6 +924,7 @@ static size_t noalloc_bytes(const rmhd_params *p, const rmhd_layout &L)
     const int nsrc = p->model == RMHD_SINGLE_FLUID ? 5 : p->model == RMHD_TWO_FLUID ? 9 : 1;
     size_t n = (size_t)nsrc + L.nprim + 2 * (size_t)L.ncons;
     if (p->integrator == RMHD_SSP3_332) n += (size_t)L.ncons + L.nprim;
+    if (p->ndim == 3) n += L.ncons;
     return n * pl;
 }
 
@@ -978,6 +981,7 @@ extern "C" int rmhd_imex_step_noalloc(const rmhd_params *p, void *hip_stream, do
         c.r3 = take(c.lay.ncons);
         c.w2 = take(c.lay.nprim);
     }
+    if (p->ndim == 3) c.lz = take(c.lay.ncons);
     rc = enqueue_imex(&c, dt, cons, prims);
     if (rc) g_err = c.err;
     return rc;
