@@ -96,6 +96,19 @@ def measured_traffic(tag: str, kernel_prefix: str):
     return sum(vals) / len(vals) if vals else None
 
 
+def copy_calibration(mib: int) -> None:
+    """A fill and a plain device copy of ``mib`` MiB: kernels of known traffic against which
+    the HBM counters of a profiled run are scaled (nothing when mib is 0)."""
+    if not mib:
+        return
+    import torch
+    src = torch.empty(mib << 17, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+
+
 def timed_steps(step, steps: int) -> float:
     """Milliseconds per step of ``steps`` calls of step(), between HIP events on torch's
     current stream (the library's), synchronised on both sides."""
@@ -387,6 +400,8 @@ def main() -> int:
     ap.add_argument("--no-ssp3", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--no-ideal", action="store_true")
+    ap.add_argument("--only-3d", action="store_true",
+                    help="print the 3-D grid measurements alone (for profiling the 3-D flux pass)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (traffic calibration)")
     args = ap.parse_args()
@@ -403,6 +418,10 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     R.lib()
+    if args.only_3d:
+        copy_calibration(args.copy_mib)
+        print(json.dumps({"grid3d": grid3d_measure(max(3, args.steps // 20), args.warmup)}), flush=True)
+        return 0
     wall0 = time.perf_counter()
     # the network, trained on the device on rows harvested from 512^2 sheets at seeds 1-4
     # (outside every timed region)
@@ -411,13 +430,7 @@ def main() -> int:
     plain = measure_form(wl, args.steps, args.warmup, timing_steps=args.timing_steps)
     learned = measure_form(wl, args.steps, args.warmup, timing_steps=args.timing_steps, net=net)
     wall = time.perf_counter() - wall0
-    if args.copy_mib:
-        src = torch.empty(args.copy_mib << 17, dtype=torch.float64, device="cuda").fill_(1.0)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    copy_calibration(args.copy_mib)
     k = plain["kernels"]
     dominant = "stage" if k["stage"]["ms_per_launch"] >= k["flux"]["ms_per_launch"] else "flux"
     roof = {kk: k[dominant][kk] for kk in ("bound", "achieved", "peak", "unit", "frac")}
