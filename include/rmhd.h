@@ -219,11 +219,14 @@ int rmhd_set_newton_cap(rmhd_ctx *ctx, int cap);
  * must lie in [0, 1). */
 int rmhd_set_jacobian_reuse(rmhd_ctx *ctx, double keep);
 
-/* Rows of the 2-D flux-pass thread block: 16 (12 interior rows per 64 x 16 block), 12 (8
- * interior rows) or 8 (4 interior rows, more blocks and more halo work); 0 (default) = 12
- * for two-fluid grids with at least two 12-row tiles per compute unit, 16 otherwise.  Results
- * do not depend on it.  (The x-y tiles of 3-D grids always use 12 rows for two-fluid grids
- * and 16 otherwise.) */
+/* Shape of the 2-D flux-pass thread block: 16 (64 x 16 threads, 60 x 12 interior cells), 12
+ * (64 x 12, 60 x 8), 8 (64 x 8, 60 x 4: more blocks and more halo work) or, for the two-fluid
+ * model only, 24 (32 x 24 threads, 28 x 20 interior cells; RMHD_EINVAL for other models).
+ * 0 (default): 16 for the single-fluid and ideal models; for two-fluid grids whichever of 12,
+ * 24 and 16 needs the fewest tile rounds over the compute units, weighted by each tile's
+ * measured time.  Results do not depend on it.  The x-y tiles of 3-D grids use 16 rows for
+ * the single-fluid and ideal models; for two-fluid grids 12 or 24 (a requested 12 or 24 is
+ * kept, otherwise chosen as in 2-D). */
 int rmhd_set_flux_rows(rmhd_ctx *ctx, int rows);
 
 /* Enable (1) or disable (0) per-kernel event timing of rmhd_imex_step.  While enabled each
@@ -286,7 +289,7 @@ typedef struct rmhd_batch_tuning {
                                    the compacted queue (a cell converged by then still takes its
                                    polishing step)
                                    (>= max_newton_iter: no queue) */
-    int32_t flux_rows;          /* rows of a 2-D flux tile block: 8, 12 or 16 */
+    int32_t flux_rows;          /* rows of a 2-D flux tile block: 8 or 16 */
     int32_t use_graph;          /* 1: capture the step in a HIP graph and replay it */
     double step_ms;             /* set by rmhd_batch_autotune: time of the chosen shape for one
                                    implicit stage plus one flux pass (half an SSP2 step; the

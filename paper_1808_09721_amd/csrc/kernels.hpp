@@ -811,8 +811,10 @@ __device__ __forceinline__ void flux_tile_lds(const FluxArgs &A, int bx, int by,
 #pragma unroll
     for (int v = 0; v < NP; ++v) w[v] = plane_at(A.w, v, g)[idx];
     const double sig = cell_sigma(A.P, idx);
-    // the halo rows' cells (whole wavefronts when a tile row is one wavefront) need no source
-    flux_source_m<M>(q, w, sig, A.P, fx, fy, src, NDIM == 1 || BX != 64 || (ty >= 2 && ty < BY - 2));
+    // the halo rows' cells (whole wavefronts when a wavefront holds one or two tile rows) need
+    // no source
+    flux_source_m<M>(q, w, sig, A.P, fx, fy, src,
+                     NDIM == 1 || (BX != 64 && BX != 32) || (ty >= 2 && ty < BY - 2));
 
     const bool interior = tx >= 2 && tx < BX - 2 && ii < g.nx &&
                           (NDIM == 1 || (ty >= 2 && ty < BY - 2 && jj < g.ny));
@@ -1079,8 +1081,8 @@ __device__ __forceinline__ void flux_tile(const FluxArgs &A, int bx, int by, lon
     static_assert(NO >= 1 && NO <= FLUX_MAXOUT, "outputs");
     if constexpr (M != 1 && NDIM == 2 && BX == 64) flux_tile_rows<M, BY, NO, RECOVER, Z3>(A, bx, by, zoff);
     else
-        flux_tile_lds<M, NDIM, BX, BY, NO, (M == 1 && NDIM == 2) ? (BY <= 12 ? 3 : 2) : 1, RECOVER, Z3>(A, bx, by,
-                                                                                                         zoff);
+        flux_tile_lds<M, NDIM, BX, BY, NO, (M == 1 && NDIM == 2) ? (BX * BY <= 768 ? 3 : 2) : 1, RECOVER, Z3>(
+            A, bx, by, zoff);
 }
 
 // Workgroups are dealt to the 8 XCDs in turn (linear id mod 8), each XCD with its own L2.

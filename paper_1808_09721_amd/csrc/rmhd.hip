@@ -322,12 +322,38 @@ static int launch_stage(rmhd_ctx *c, const StageArgs &A)
     return launch_stage_m<1>(c, B);
 }
 
-// Thread rows of a 2-D flux tile block.
+// Two-fluid flux tiles: a CU holds one tile block at a time (register and LDS bound), so a
+// pass takes (rounds of tiles over the CUs) x (time per tile).  Measured per-tile times,
+// relative to the 64 x 12 tile (60 x 8 interior cells): 32 x 24 (28 x 20) 1.19, 64 x 16
+// (60 x 12; spills, and the step then needs a separate recovery kernel) 1.45.  Cost of a pass
+// in those units (x100) with tiles of tx x ty interior cells over `planes` z planes.
+static long tf_tile_cost(const rmhd_ctx *c, int tx, int ty, long planes, long rel)
+{
+    const long tiles = (long)((c->prm.nx + tx - 1) / tx) * ((c->prm.ny + ty - 1) / ty) * planes;
+    return rel * ((tiles + c->cus - 1) / c->cus);
+}
+
+// Thread rows of a 2-D flux tile block (24: the 32-column two-fluid tile).  Two-fluid grids
+// take the cheapest of 64 x 12, 32 x 24 and 64 x 16 by tf_tile_cost; measured: 1024^2 sheet
+// 64 x 12 (9 rounds) 223 us per pass, 32 x 24 (7.5 rounds) 235 us; 512^2 sheet 64 x 12 (2.25
+// rounds) 70 us, 32 x 24 (1.9 rounds) 59 us; 1024 x 128, 64 x 16 (one round) 36 us, 64 x 12
+// (1.1 rounds) 50 us.
 static int flux_rows_2d(const rmhd_ctx *c)
 {
     if (c->flux_rows) return c->flux_rows;
-    const long tiles12 = (long)((c->prm.nx + 59) / 60) * ((c->prm.ny + 7) / 8);
-    return c->prm.model == RMHD_TWO_FLUID && tiles12 >= 2L * c->cus ? 12 : 16;
+    if (c->prm.model != RMHD_TWO_FLUID) return 16;
+    const long c12 = tf_tile_cost(c, 60, 8, 1, 100), c24 = tf_tile_cost(c, 28, 20, 1, 119),
+               c16 = tf_tile_cost(c, 60, 12, 1, 145);
+    if (c16 < c12 && c16 < c24) return 16;
+    return c24 < c12 ? 24 : 12;
+}
+
+// The same choice for the x-y tiles of a 3-D two-fluid grid, between 64 x 12 and 32 x 24
+// (a requested 12 or 24 is kept).
+static int flux_rows_3d_tf(const rmhd_ctx *c)
+{
+    if (c->flux_rows == 12 || c->flux_rows == 24) return c->flux_rows;
+    return tf_tile_cost(c, 28, 20, c->prm.nz, 119) < tf_tile_cost(c, 60, 8, c->prm.nz, 100) ? 24 : 12;
 }
 
 template <int M, int NO>
@@ -335,7 +361,7 @@ static void launch_flux_mo(rmhd_ctx *c, const FluxArgs &A)
 {
     if (c->prm.ndim == 3) {
         // the z term of every interior cell first, then the x and y terms per interior z plane
-        // (64 x 16 tiles, two fluid 64 x 12), which add it, complete the outputs, write their
+        // (64 x 16 tiles, two fluid 64 x 12 or 32 x 24), which add it, complete the outputs, write their
         // ghost images in all three directions and recover the primitives
         constexpr int BX = 64;
         FluxArgs Az = A;
@@ -343,10 +369,17 @@ static void launch_flux_mo(rmhd_ctx *c, const FluxArgs &A)
         const dim3 gz((unsigned)((c->prm.nx + BX - 1) / BX), (unsigned)c->prm.ny, (unsigned)((c->prm.nz + 11) / 12));
         hipLaunchKernelGGL((k_flux_z<M>), gz, dim3(BX, 16), 0, c->stream, Az);
         const unsigned gx = (unsigned)((c->prm.nx + (BX - 4) - 1) / (BX - 4));
-        if constexpr (M == RMHD_TWO_FLUID)   // 64 x 12 tiles: the two-fluid tile's registers without spills
-            hipLaunchKernelGGL((k_flux<M, 3, BX, 12, NO>), dim3(gx, (unsigned)((c->prm.ny + 7) / 8), (unsigned)c->prm.nz),
-                               dim3(BX, 12), 0, c->stream, Az);
-        else
+        if constexpr (M == RMHD_TWO_FLUID) {   // 64 x 12 or 32 x 24: the two-fluid tile's registers without spills
+            if (flux_rows_3d_tf(c) == 24)
+                hipLaunchKernelGGL((k_flux<M, 3, 32, 24, NO>),
+                                   dim3((unsigned)((c->prm.nx + 27) / 28), (unsigned)((c->prm.ny + 19) / 20),
+                                        (unsigned)c->prm.nz),
+                                   dim3(32, 24), 0, c->stream, Az);
+            else
+                hipLaunchKernelGGL((k_flux<M, 3, BX, 12, NO>),
+                                   dim3(gx, (unsigned)((c->prm.ny + 7) / 8), (unsigned)c->prm.nz), dim3(BX, 12), 0,
+                                   c->stream, Az);
+        } else
             hipLaunchKernelGGL((k_flux<M, 3, BX, 16, NO>), dim3(gx, (unsigned)((c->prm.ny + 11) / 12), (unsigned)c->prm.nz),
                                dim3(BX, 16), 0, c->stream, Az);
     } else if (c->prm.ndim == 1) {
@@ -354,13 +387,10 @@ static void launch_flux_mo(rmhd_ctx *c, const FluxArgs &A)
         dim3 grid((c->prm.nx + (BX - 4) - 1) / (BX - 4));
         hipLaunchKernelGGL((k_flux<M, 1, BX, 1, NO>), grid, dim3(BX, 1), 0, c->stream, A);
     } else {
-        // 64 x 16 tiles (12 interior rows) by default; 64 x 12 (8 rows) for two-fluid grids
-        // with at least two 12-row tiles per CU, whose 768-thread blocks fit the two-fluid
-        // tile's registers without spills and let the last pass recover the primitives
-        // (measured on the 1024^2 sheet: 221 against 239 us per pass; on 512^2 the 12-row pass
-        // with the recovery, 70 us, against 66 + 14 us for 16 rows and a recovery kernel: step
-        // 0.310 against 0.316 ms; on 1024 x 128, 1.1 tiles per CU, 50 against 36 us per pass:
-        // a second, nearly empty round of blocks); 64 x 8 (4 rows) on request.
+        // 64 x 16 tiles (12 interior rows) by default; two-fluid grids choose between 64 x 12,
+        // 32 x 24 and 64 x 16 (flux_rows_2d): the 768-thread blocks fit the two-fluid tile's
+        // registers without spills and let the last pass recover the primitives (1024^2 sheet:
+        // 221 against 239 us per pass for 64 x 16); 64 x 8 (4 rows) on request.
         // Measured on the 256 x 512 single-fluid grid, whose 16-row tiles leave some CUs idle,
         // 16 rows are still faster (30 us against 41 us at 8 rows, 40 us at 12).
         constexpr int BX = 64;
@@ -370,6 +400,9 @@ static void launch_flux_mo(rmhd_ctx *c, const FluxArgs &A)
             hipLaunchKernelGGL((k_flux<M, 2, BX, 8, NO>), dim3(gx, (c->prm.ny + 3) / 4), dim3(BX, 8), 0, c->stream, A);
         else if (rows == 12)
             hipLaunchKernelGGL((k_flux<M, 2, BX, 12, NO>), dim3(gx, (c->prm.ny + 7) / 8), dim3(BX, 12), 0, c->stream, A);
+        else if (M == RMHD_TWO_FLUID && rows == 24)
+            hipLaunchKernelGGL((k_flux<RMHD_TWO_FLUID, 2, 32, 24, NO>),
+                               dim3((c->prm.nx + 27) / 28, (c->prm.ny + 19) / 20), dim3(32, 24), 0, c->stream, A);
         else
             hipLaunchKernelGGL((k_flux<M, 2, BX, 16, NO>), dim3(gx, (c->prm.ny + 11) / 12), dim3(BX, 16), 0,
                                c->stream, A);
@@ -630,7 +663,7 @@ static int enqueue_imex(rmhd_ctx *c, double dt, double *cons, double *prims)
     // and with 16-row 2-D tiles, which run a separate recovery kernel: the recovery's
     // registers make those tiles spill.  Measured: 1024^2 sheet (12-row tiles) 1.118 ->
     // 1.099 ms per step fused; 512^2 sheet (16-row tiles) 0.321 -> 0.328 ms fused
-    const bool fused = M == RMHD_SINGLE_FLUID || c->prm.ndim != 2 || flux_rows_2d(c) == 12;
+    const bool fused = M == RMHD_SINGLE_FLUID || c->prm.ndim != 2 || flux_rows_2d(c) == 12 || flux_rows_2d(c) == 24;
     // event pairs: stages, flux passes, recovery (kinds 0, 1, 2)
     int nev = 0, kinds[7];
     auto begin = [&]() {
@@ -860,8 +893,10 @@ extern "C" int rmhd_set_jacobian_reuse(rmhd_ctx *c, double keep)
 extern "C" int rmhd_set_flux_rows(rmhd_ctx *c, int rows)
 {
     if (!c) return fail(c, RMHD_EINVAL, "rmhd_set_flux_rows: NULL context");
-    if (rows != 0 && rows != 8 && rows != 12 && rows != 16)
-        return fail(c, RMHD_EINVAL, "rmhd_set_flux_rows: rows must be 0, 8, 12 or 16");
+    if (rows != 0 && rows != 8 && rows != 12 && rows != 16 && rows != 24)
+        return fail(c, RMHD_EINVAL, "rmhd_set_flux_rows: rows must be 0, 8, 12, 16 or 24");
+    if (rows == 24 && c->prm.model != RMHD_TWO_FLUID)
+        return fail(c, RMHD_EINVAL, "rmhd_set_flux_rows: 32 x 24 tiles are for the two-fluid model only");
     c->flux_rows = rows;
     free_graph(c);   // kernel arguments changed: capture again
     return RMHD_OK;

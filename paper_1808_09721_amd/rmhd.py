@@ -416,7 +416,8 @@ class Solver:
         rmhd_set_newton_cap(self.ctx, cap)
 
     def set_flux_rows(self, rows: int):
-        """Rows of the 2-D flux tile block (0: the library's choice, 8, 12 or 16)."""
+        """Shape of the 2-D flux tile block (0: the library's choice; 8, 12 or 16 rows of 64
+        threads; 24: 32 x 24 threads, two-fluid model only)."""
         rmhd_set_flux_rows(self.ctx, rows)
 
     def set_jacobian_reuse(self, keep: float):

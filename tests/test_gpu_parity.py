@@ -433,13 +433,13 @@ def test_jacobian_reuse_agrees_with_fresh_jacobians(R, O, model):
 
 @pytest.mark.parametrize("model", [0, 1])
 def test_flux_tile_rows_do_not_change_results(R, model):
-    """The 2-D flux tile's height (8, 12 or 16 thread rows, and the library's own choice) only
+    """The 2-D flux tile's shape (64 x 8, 12 or 16 threads, two fluid also 32 x 24, and the library's own choice) only
     changes which block computes a cell: three steps give the same state bit for bit."""
     banner(f"flux tile rows model={model}")
     wl = (WL.kelvin_helmholtz_2d(70, 37, steps=3, seed=15) if model == 0 else
           WL.two_fluid_sheet_2d(70, 37, steps=3, seed=16, sigma_range=(1e2, 1e6)))
     out = []
-    for rows in (0, 8, 12, 16):
+    for rows in (0, 8, 12, 16) + ((24,) if model == 1 else ()):
         s = gpu_solver(R, wl)
         s.set_flux_rows(rows)
         cons, prims = s.initial_state(wl.prims, wl.EB)
