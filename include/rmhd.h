@@ -220,13 +220,16 @@ int rmhd_set_newton_cap(rmhd_ctx *ctx, int cap);
 int rmhd_set_jacobian_reuse(rmhd_ctx *ctx, double keep);
 
 /* Shape of the 2-D flux-pass thread block: 16 (64 x 16 threads, 60 x 12 interior cells), 12
- * (64 x 12, 60 x 8), 8 (64 x 8, 60 x 4: more blocks and more halo work) or, for the two-fluid
- * model only, 24 (32 x 24 threads, 28 x 20 interior cells; RMHD_EINVAL for other models).
- * 0 (default): 16 for the single-fluid and ideal models; for two-fluid grids whichever of 12,
- * 24 and 16 needs the fewest tile rounds over the compute units, weighted by each tile's
- * measured time.  Results do not depend on it.  The x-y tiles of 3-D grids use 16 rows for
- * the single-fluid and ideal models; for two-fluid grids 12 or 24 (a requested 12 or 24 is
- * kept, otherwise chosen as in 2-D). */
+ * (64 x 12, 60 x 8), 8 (64 x 8, 60 x 4: more blocks and more halo work); for the two-fluid
+ * model only 24 (32 x 24 threads, 28 x 20 interior cells), for the single-fluid and ideal
+ * models only 32 (32 x 32 threads, 28 x 28 interior cells); RMHD_EINVAL otherwise.
+ * 0 (default): whichever of the model's shapes (single fluid and ideal 16 and 32; two fluid
+ * 12, 24 and 16) needs the fewest tile rounds over the compute units, weighted by each tile's
+ * measured time.  Results do not depend on it beyond rounding (the two-fluid shapes, and 8,
+ * 12 and 16 among themselves, give identical results; 32 forms the x stencil through LDS
+ * instead of across lanes, which changes the last bits).  The x-y tiles of 3-D grids: two
+ * fluid 12 or 24, the other models 16 or 32 (a requested one of those is kept, otherwise
+ * chosen as in 2-D). */
 int rmhd_set_flux_rows(rmhd_ctx *ctx, int rows);
 
 /* Enable (1) or disable (0) per-kernel event timing of rmhd_imex_step.  While enabled each

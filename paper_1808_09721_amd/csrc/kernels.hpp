@@ -1081,7 +1081,7 @@ __device__ __forceinline__ void flux_tile(const FluxArgs &A, int bx, int by, lon
     static_assert(NO >= 1 && NO <= FLUX_MAXOUT, "outputs");
     if constexpr (M != 1 && NDIM == 2 && BX == 64) flux_tile_rows<M, BY, NO, RECOVER, Z3>(A, bx, by, zoff);
     else
-        flux_tile_lds<M, NDIM, BX, BY, NO, (M == 1 && NDIM == 2) ? (BX * BY <= 768 ? 3 : 2) : 1, RECOVER, Z3>(
+        flux_tile_lds<M, NDIM, BX, BY, NO, (M == 1 && NDIM == 2) ? (BX * BY <= 768 ? 3 : 2) : (NDIM == 2 && BX == 32 ? 2 : 1), RECOVER, Z3>(
             A, bx, by, zoff);
 }
 

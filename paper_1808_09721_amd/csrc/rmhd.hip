@@ -322,38 +322,52 @@ static int launch_stage(rmhd_ctx *c, const StageArgs &A)
     return launch_stage_m<1>(c, B);
 }
 
-// Two-fluid flux tiles: a CU holds one tile block at a time (register and LDS bound), so a
-// pass takes (rounds of tiles over the CUs) x (time per tile).  Measured per-tile times,
-// relative to the 64 x 12 tile (60 x 8 interior cells): 32 x 24 (28 x 20) 1.19, 64 x 16
-// (60 x 12; spills, and the step then needs a separate recovery kernel) 1.45.  Cost of a pass
-// in those units (x100) with tiles of tx x ty interior cells over `planes` z planes.
-static long tf_tile_cost(const rmhd_ctx *c, int tx, int ty, long planes, long rel)
+// Flux tiles: a CU holds one tile block at a time (register and LDS bound), so a pass takes
+// (rounds of tiles over the CUs) x (time per tile).  Cost of a pass, in units of a reference
+// tile's time (x100), with tiles of tx x ty interior cells over `planes` z planes.
+static long tile_cost(const rmhd_ctx *c, int tx, int ty, long planes, long rel)
 {
     const long tiles = (long)((c->prm.nx + tx - 1) / tx) * ((c->prm.ny + ty - 1) / ty) * planes;
     return rel * ((tiles + c->cus - 1) / c->cus);
 }
 
-// Thread rows of a 2-D flux tile block (24: the 32-column two-fluid tile).  Two-fluid grids
-// take the cheapest of 64 x 12, 32 x 24 and 64 x 16 by tf_tile_cost; measured: 1024^2 sheet
-// 64 x 12 (9 rounds) 223 us per pass, 32 x 24 (7.5 rounds) 235 us; 512^2 sheet 64 x 12 (2.25
-// rounds) 70 us, 32 x 24 (1.9 rounds) 59 us; 1024 x 128, 64 x 16 (one round) 36 us, 64 x 12
-// (1.1 rounds) 50 us.
+// Single-fluid and ideal tiles: 64 x 16 (the x stencil across the lanes of a row) or 32 x 32
+// (both stencils through LDS, 28 x 28 interior cells), whose tile takes 1.18 times as long
+// but wastes less of a narrow grid's last column of tiles: Kelvin-Helmholtz 128 x 256 x 128,
+// x-y kernel 33 rounds of 64 x 16 tiles 870 us per pass, 25 rounds of 32 x 32 777 us; on
+// 256 x 512 (one round either way) 27 against 29 us.
+static int sf_rows(const rmhd_ctx *c, long planes)
+{
+    return tile_cost(c, 28, 28, planes, 118) < tile_cost(c, 60, 12, planes, 100) ? 32 : 16;
+}
+
+// Thread rows of a 2-D flux tile block (24: the 32-column two-fluid tile, 32: the 32 x 32
+// single-fluid and ideal tile).  Two-fluid grids take the cheapest of 64 x 12, 32 x 24 and
+// 64 x 16 with per-tile times relative to 64 x 12 (60 x 8 interior cells) of 1.19 for 32 x 24
+// (28 x 20) and 1.45 for 64 x 16 (60 x 12; spills, and the step then needs a separate
+// recovery kernel); measured: 1024^2 sheet 64 x 12 (9 rounds) 223 us per pass, 32 x 24 (7.5
+// rounds) 235 us; 512^2 sheet 64 x 12 (2.25 rounds) 70 us, 32 x 24 (1.9 rounds) 59 us;
+// 1024 x 128, 64 x 16 (one round) 36 us, 64 x 12 (1.1 rounds) 50 us.
 static int flux_rows_2d(const rmhd_ctx *c)
 {
     if (c->flux_rows) return c->flux_rows;
-    if (c->prm.model != RMHD_TWO_FLUID) return 16;
-    const long c12 = tf_tile_cost(c, 60, 8, 1, 100), c24 = tf_tile_cost(c, 28, 20, 1, 119),
-               c16 = tf_tile_cost(c, 60, 12, 1, 145);
+    if (c->prm.model != RMHD_TWO_FLUID) return sf_rows(c, 1);
+    const long c12 = tile_cost(c, 60, 8, 1, 100), c24 = tile_cost(c, 28, 20, 1, 119),
+               c16 = tile_cost(c, 60, 12, 1, 145);
     if (c16 < c12 && c16 < c24) return 16;
     return c24 < c12 ? 24 : 12;
 }
 
-// The same choice for the x-y tiles of a 3-D two-fluid grid, between 64 x 12 and 32 x 24
-// (a requested 12 or 24 is kept).
-static int flux_rows_3d_tf(const rmhd_ctx *c)
+// The same choices for the x-y tiles of a 3-D grid: two fluid 64 x 12 or 32 x 24, the other
+// models 64 x 16 or 32 x 32 (a requested shape among those is kept).
+static int flux_rows_3d(const rmhd_ctx *c)
 {
-    if (c->flux_rows == 12 || c->flux_rows == 24) return c->flux_rows;
-    return tf_tile_cost(c, 28, 20, c->prm.nz, 119) < tf_tile_cost(c, 60, 8, c->prm.nz, 100) ? 24 : 12;
+    if (c->prm.model == RMHD_TWO_FLUID) {
+        if (c->flux_rows == 12 || c->flux_rows == 24) return c->flux_rows;
+        return tile_cost(c, 28, 20, c->prm.nz, 119) < tile_cost(c, 60, 8, c->prm.nz, 100) ? 24 : 12;
+    }
+    if (c->flux_rows == 16 || c->flux_rows == 32) return c->flux_rows;
+    return sf_rows(c, c->prm.nz);
 }
 
 template <int M, int NO>
@@ -361,7 +375,7 @@ static void launch_flux_mo(rmhd_ctx *c, const FluxArgs &A)
 {
     if (c->prm.ndim == 3) {
         // the z term of every interior cell first, then the x and y terms per interior z plane
-        // (64 x 16 tiles, two fluid 64 x 12 or 32 x 24), which add it, complete the outputs, write their
+        // (64 x 16 or 32 x 32 tiles, two fluid 64 x 12 or 32 x 24), which add it, complete the outputs, write their
         // ghost images in all three directions and recover the primitives
         constexpr int BX = 64;
         FluxArgs Az = A;
@@ -370,7 +384,7 @@ static void launch_flux_mo(rmhd_ctx *c, const FluxArgs &A)
         hipLaunchKernelGGL((k_flux_z<M>), gz, dim3(BX, 16), 0, c->stream, Az);
         const unsigned gx = (unsigned)((c->prm.nx + (BX - 4) - 1) / (BX - 4));
         if constexpr (M == RMHD_TWO_FLUID) {   // 64 x 12 or 32 x 24: the two-fluid tile's registers without spills
-            if (flux_rows_3d_tf(c) == 24)
+            if (flux_rows_3d(c) == 24)
                 hipLaunchKernelGGL((k_flux<M, 3, 32, 24, NO>),
                                    dim3((unsigned)((c->prm.nx + 27) / 28), (unsigned)((c->prm.ny + 19) / 20),
                                         (unsigned)c->prm.nz),
@@ -379,7 +393,12 @@ static void launch_flux_mo(rmhd_ctx *c, const FluxArgs &A)
                 hipLaunchKernelGGL((k_flux<M, 3, BX, 12, NO>),
                                    dim3(gx, (unsigned)((c->prm.ny + 7) / 8), (unsigned)c->prm.nz), dim3(BX, 12), 0,
                                    c->stream, Az);
-        } else
+        } else if (flux_rows_3d(c) == 32)
+            hipLaunchKernelGGL((k_flux<M == RMHD_TWO_FLUID ? RMHD_SINGLE_FLUID : M, 3, 32, 32, NO>),
+                               dim3((unsigned)((c->prm.nx + 27) / 28), (unsigned)((c->prm.ny + 27) / 28),
+                                    (unsigned)c->prm.nz),
+                               dim3(32, 32), 0, c->stream, Az);
+        else
             hipLaunchKernelGGL((k_flux<M, 3, BX, 16, NO>), dim3(gx, (unsigned)((c->prm.ny + 11) / 12), (unsigned)c->prm.nz),
                                dim3(BX, 16), 0, c->stream, Az);
     } else if (c->prm.ndim == 1) {
@@ -387,10 +406,11 @@ static void launch_flux_mo(rmhd_ctx *c, const FluxArgs &A)
         dim3 grid((c->prm.nx + (BX - 4) - 1) / (BX - 4));
         hipLaunchKernelGGL((k_flux<M, 1, BX, 1, NO>), grid, dim3(BX, 1), 0, c->stream, A);
     } else {
-        // 64 x 16 tiles (12 interior rows) by default; two-fluid grids choose between 64 x 12,
-        // 32 x 24 and 64 x 16 (flux_rows_2d): the 768-thread blocks fit the two-fluid tile's
-        // registers without spills and let the last pass recover the primitives (1024^2 sheet:
-        // 221 against 239 us per pass for 64 x 16); 64 x 8 (4 rows) on request.
+        // 64 x 16 or 32 x 32 tiles for the single-fluid and ideal models; two-fluid grids
+        // choose between 64 x 12, 32 x 24 and 64 x 16 (flux_rows_2d): the 768-thread blocks fit
+        // the two-fluid tile's registers without spills and let the last pass recover the
+        // primitives (1024^2 sheet: 221 against 239 us per pass for 64 x 16); 64 x 8 (4 rows)
+        // on request.
         // Measured on the 256 x 512 single-fluid grid, whose 16-row tiles leave some CUs idle,
         // 16 rows are still faster (30 us against 41 us at 8 rows, 40 us at 12).
         constexpr int BX = 64;
@@ -403,6 +423,9 @@ static void launch_flux_mo(rmhd_ctx *c, const FluxArgs &A)
         else if (M == RMHD_TWO_FLUID && rows == 24)
             hipLaunchKernelGGL((k_flux<RMHD_TWO_FLUID, 2, 32, 24, NO>),
                                dim3((c->prm.nx + 27) / 28, (c->prm.ny + 19) / 20), dim3(32, 24), 0, c->stream, A);
+        else if (M != RMHD_TWO_FLUID && rows == 32)
+            hipLaunchKernelGGL((k_flux<M == RMHD_TWO_FLUID ? RMHD_SINGLE_FLUID : M, 2, 32, 32, NO>),
+                               dim3((c->prm.nx + 27) / 28, (c->prm.ny + 27) / 28), dim3(32, 32), 0, c->stream, A);
         else
             hipLaunchKernelGGL((k_flux<M, 2, BX, 16, NO>), dim3(gx, (c->prm.ny + 11) / 12), dim3(BX, 16), 0,
                                c->stream, A);
@@ -893,10 +916,12 @@ extern "C" int rmhd_set_jacobian_reuse(rmhd_ctx *c, double keep)
 extern "C" int rmhd_set_flux_rows(rmhd_ctx *c, int rows)
 {
     if (!c) return fail(c, RMHD_EINVAL, "rmhd_set_flux_rows: NULL context");
-    if (rows != 0 && rows != 8 && rows != 12 && rows != 16 && rows != 24)
-        return fail(c, RMHD_EINVAL, "rmhd_set_flux_rows: rows must be 0, 8, 12, 16 or 24");
+    if (rows != 0 && rows != 8 && rows != 12 && rows != 16 && rows != 24 && rows != 32)
+        return fail(c, RMHD_EINVAL, "rmhd_set_flux_rows: rows must be 0, 8, 12, 16, 24 or 32");
     if (rows == 24 && c->prm.model != RMHD_TWO_FLUID)
         return fail(c, RMHD_EINVAL, "rmhd_set_flux_rows: 32 x 24 tiles are for the two-fluid model only");
+    if (rows == 32 && c->prm.model == RMHD_TWO_FLUID)
+        return fail(c, RMHD_EINVAL, "rmhd_set_flux_rows: 32 x 32 tiles are for the single-fluid and ideal models");
     c->flux_rows = rows;
     free_graph(c);   // kernel arguments changed: capture again
     return RMHD_OK;

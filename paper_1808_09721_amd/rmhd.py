@@ -417,7 +417,8 @@ class Solver:
 
     def set_flux_rows(self, rows: int):
         """Shape of the 2-D flux tile block (0: the library's choice; 8, 12 or 16 rows of 64
-        threads; 24: 32 x 24 threads, two-fluid model only)."""
+        threads; 24: 32 x 24 threads, two-fluid model only; 32: 32 x 32 threads, single-fluid
+        and ideal models only)."""
         rmhd_set_flux_rows(self.ctx, rows)
 
     def set_jacobian_reuse(self, keep: float):
