@@ -280,7 +280,8 @@ __global__ __launch_bounds__(BX *BY) void kb_flux(BatchFluxArgs B)
         A.o[0].cL = 0.5 * dt;
         A.o[0].cS = 0.5 * dt;
     }
-    if (B.pass == 1) flux_tile<0, NDIM, BX, BY, 2>(A, t.y, t.z);
+    // pass 1: both outputs have q^n as base, whose source-free planes q shares
+    if (B.pass == 1) flux_tile<0, NDIM, BX, BY, 2, false, false, true>(A, t.y, t.z);
     else flux_tile<0, NDIM, BX, BY, 1>(A, t.y, t.z);
 }
 

@@ -717,6 +717,30 @@ __device__ __forceinline__ auto plane_at(const P &s, int v, const Geo &g)
     return s.p[0] + (long)v * g.plane;
 }
 
+// The base terms of component v for the NO outputs at this cell (zero away from the interior).
+// BQ: every output has the same base, whose source-free planes are q's (the first pass of a
+// step, which reads q^n both as its state's source-free part and as the base): the base of a
+// source-free component is the cell's own q[v], and one value serves every output.  The
+// values are those a load would give.
+// (Loading the two-fluid source components' base values with the state instead, so that no
+// round of the first pass waits for a load, measured slower: 227 against 223 us per pass on
+// the 1024^2 sheet.)
+template <int M, int NO, bool BQ, int NC>
+__device__ __forceinline__ void base_terms(const FluxArgs &A, const double (&q)[NC], int v, bool interior, long idx,
+                                           double (&b)[NO])
+{
+    const int vc = v < NC ? v : NC - 1;
+    if constexpr (BQ) {
+        b[0] = (v < NC && interior) ? (has_source(M, vc) ? plane_at(A.o[0].base, vc, A.g)[idx] : q[vc]) : 0.0;
+#pragma unroll
+        for (int k = 1; k < NO; ++k) b[k] = b[0];
+    } else {
+#pragma unroll
+        for (int k = 0; k < NO; ++k)
+            b[k] = (v < NC && interior && A.o[k].base.p[0]) ? plane_at(A.o[k].base, vc, A.g)[idx] : 0.0;
+    }
+}
+
 // Store a cell's value and, where the cell has ghost images (img), the images too: the
 // image loop sits behind one branch, which whole wavefronts away from the boundary skip.
 __device__ __forceinline__ void store_with_images(double *plane, long zoff, int pitch, const int (&xi)[3],
@@ -788,7 +812,7 @@ __device__ __forceinline__ void weno3_pair(double ap, double bp, double cp, doub
 // rows span several wavefronts); every thread of the block must call it (it holds
 // barriers).  (bx, by) is the tile position in units of interior tiles; zoff is the offset of
 // the z plane (0 below 3-D, where a 2-D tile forms the x and y terms of one plane).
-template <int M, int NDIM, int BX, int BY, int NO, int GV = 1, bool RECOVER = true, bool Z3 = false>
+template <int M, int NDIM, int BX, int BY, int NO, int GV = 1, bool RECOVER = true, bool Z3 = false, bool BQ = false>
 __device__ __forceinline__ void flux_tile_lds(const FluxArgs &A, int bx, int by, long zoff)
 {
     constexpr int NC = Model<M>::NC, NP = Model<M>::NP;
@@ -837,9 +861,7 @@ __device__ __forceinline__ void flux_tile_lds(const FluxArgs &A, int bx, int by,
         double bv[GV][NO], lzv[GV];
 #pragma unroll
         for (int gv = 0; gv < GV; ++gv) {
-#pragma unroll
-            for (int k = 0; k < NO; ++k)
-                bv[gv][k] = (v0 + gv < NC && interior && A.o[k].base.p[0]) ? plane_at(A.o[k].base, v0 + gv, g)[idx] : 0.0;
+            base_terms<M, NO, BQ>(A, q, v0 + gv, interior, idx, bv[gv]);
             lzv[gv] = (Z3 && v0 + gv < NC && interior) ? plane_at(A.lz, v0 + gv, g)[idx] : 0.0;
         }
 #pragma unroll
@@ -950,7 +972,7 @@ __device__ __forceinline__ double from_right(double v) { return dpp_shift<0x130>
 // the x stencil is read from neighbouring lanes (no LDS, no barrier) and only the y stencil
 // goes through LDS, G variables per pair of barriers.  The arithmetic per face and cell is
 // that of flux_tile_lds.  Every thread of the block must call it.
-template <int M, int BY, int NO, bool RECOVER = true, bool Z3 = false>
+template <int M, int BY, int NO, bool RECOVER = true, bool Z3 = false, bool BQ = false>
 __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by, long zoff)
 {
     constexpr int NC = Model<M>::NC, NP = Model<M>::NP;
@@ -994,9 +1016,7 @@ __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by
         double bv[G][NO], lzv[G];
 #pragma unroll
         for (int k = 0; k < G; ++k) {
-#pragma unroll
-            for (int kk = 0; kk < NO; ++kk)
-                bv[k][kk] = (v0 + k < NC && interior && A.o[kk].base.p[0]) ? plane_at(A.o[kk].base, v0 + k, g)[idx] : 0.0;
+            base_terms<M, NO, BQ>(A, q, v0 + k, interior, idx, bv[k]);
             lzv[k] = (Z3 && v0 + k < NC && interior) ? plane_at(A.lz, v0 + k, g)[idx] : 0.0;
         }
         double Lx[G];
@@ -1073,16 +1093,17 @@ __device__ __forceinline__ void flux_tile_rows(const FluxArgs &A, int bx, int by
 // (1024^2 sheet 226 against 232 us per pass); measured no better in the two-fluid row form
 // either (x stencil from neighbouring lanes, flux components formed per round: 236 us).
 // NO: outputs used (o[0..NO-1]), fixed at compile time so unused ones cost no registers.
-// RECOVER = false: the tile never recovers primitives (the x-y tiles of a 3-D pass, whose z
-// kernel completes the outputs), so the recovery's registers are not reserved.
-template <int M, int NDIM, int BX, int BY, int NO, bool RECOVER = true, bool Z3 = false>
+// RECOVER = false: the tile never recovers primitives (every pass but a step's last, except in
+// the ideal model's explicit steps), so the recovery's registers are not reserved.  BQ: see
+// base_terms.
+template <int M, int NDIM, int BX, int BY, int NO, bool RECOVER = true, bool Z3 = false, bool BQ = false>
 __device__ __forceinline__ void flux_tile(const FluxArgs &A, int bx, int by, long zoff = 0)
 {
     static_assert(NO >= 1 && NO <= FLUX_MAXOUT, "outputs");
-    if constexpr (M != 1 && NDIM == 2 && BX == 64) flux_tile_rows<M, BY, NO, RECOVER, Z3>(A, bx, by, zoff);
+    if constexpr (M != 1 && NDIM == 2 && BX == 64) flux_tile_rows<M, BY, NO, RECOVER, Z3, BQ>(A, bx, by, zoff);
     else
-        flux_tile_lds<M, NDIM, BX, BY, NO, (M == 1 && NDIM == 2) ? (BX * BY <= 768 ? 3 : 2) : (NDIM == 2 && BX == 32 ? 2 : 1), RECOVER, Z3>(
-            A, bx, by, zoff);
+        flux_tile_lds<M, NDIM, BX, BY, NO, (M == 1 && NDIM == 2) ? (BX * BY <= 768 ? 3 : 2) : (NDIM == 2 && BX == 32 ? 2 : 1), RECOVER, Z3,
+                      BQ>(A, bx, by, zoff);
 }
 
 // Workgroups are dealt to the 8 XCDs in turn (linear id mod 8), each XCD with its own L2.
@@ -1114,19 +1135,19 @@ __device__ __forceinline__ void xcd_tile3(int &bx, int &by, int &bz)
 
 // Flux pass.  NDIM = 3: one 2-D tile of an interior z plane (blockIdx.z), forming
 // out_k = base_k + c_kL (Lx + Ly + Lz) + c_kS Psi with Lz from k_flux_z (launched first).
-template <int M, int NDIM, int BX, int BY, int NO>
+template <int M, int NDIM, int BX, int BY, int NO, bool BQ = false>
 __global__ __launch_bounds__(BX *BY) void k_flux(FluxArgs A)
 {
     int bx = blockIdx.x, by = blockIdx.y;
     if constexpr (NDIM == 3) {
         int bz;
         xcd_tile3(bx, by, bz);
-        flux_tile<M, 2, BX, BY, NO, NO == 1 || M == 2, true>(A, bx, by, (long)(bz + 2) * A.g.slab);
+        flux_tile<M, 2, BX, BY, NO, NO == 1 || M == 2, true, BQ>(A, bx, by, (long)(bz + 2) * A.g.slab);
     } else {
         if constexpr (NDIM == 2) xcd_tile(bx, by);
         // only a step's last pass (one output) recovers primitives, except in the ideal
         // model's explicit steps, whose every pass does; the others reserve no registers for it
-        flux_tile<M, NDIM, BX, BY, NO, NO == 1 || M == 2>(A, bx, by);
+        flux_tile<M, NDIM, BX, BY, NO, NO == 1 || M == 2, false, BQ>(A, bx, by);
     }
 }
 

@@ -370,8 +370,8 @@ static int flux_rows_3d(const rmhd_ctx *c)
     return sf_rows(c, c->prm.nz);
 }
 
-template <int M, int NO>
-static void launch_flux_mo(rmhd_ctx *c, const FluxArgs &A)
+template <int M, int NO, bool BQ>
+static void launch_flux_shape(rmhd_ctx *c, const FluxArgs &A)
 {
     if (c->prm.ndim == 3) {
         // the z term of every interior cell first, then the x and y terms per interior z plane
@@ -385,26 +385,26 @@ static void launch_flux_mo(rmhd_ctx *c, const FluxArgs &A)
         const unsigned gx = (unsigned)((c->prm.nx + (BX - 4) - 1) / (BX - 4));
         if constexpr (M == RMHD_TWO_FLUID) {   // 64 x 12 or 32 x 24: the two-fluid tile's registers without spills
             if (flux_rows_3d(c) == 24)
-                hipLaunchKernelGGL((k_flux<M, 3, 32, 24, NO>),
+                hipLaunchKernelGGL((k_flux<M, 3, 32, 24, NO, BQ>),
                                    dim3((unsigned)((c->prm.nx + 27) / 28), (unsigned)((c->prm.ny + 19) / 20),
                                         (unsigned)c->prm.nz),
                                    dim3(32, 24), 0, c->stream, Az);
             else
-                hipLaunchKernelGGL((k_flux<M, 3, BX, 12, NO>),
+                hipLaunchKernelGGL((k_flux<M, 3, BX, 12, NO, BQ>),
                                    dim3(gx, (unsigned)((c->prm.ny + 7) / 8), (unsigned)c->prm.nz), dim3(BX, 12), 0,
                                    c->stream, Az);
         } else if (flux_rows_3d(c) == 32)
-            hipLaunchKernelGGL((k_flux<M == RMHD_TWO_FLUID ? RMHD_SINGLE_FLUID : M, 3, 32, 32, NO>),
+            hipLaunchKernelGGL((k_flux<M == RMHD_TWO_FLUID ? RMHD_SINGLE_FLUID : M, 3, 32, 32, NO, BQ>),
                                dim3((unsigned)((c->prm.nx + 27) / 28), (unsigned)((c->prm.ny + 27) / 28),
                                     (unsigned)c->prm.nz),
                                dim3(32, 32), 0, c->stream, Az);
         else
-            hipLaunchKernelGGL((k_flux<M, 3, BX, 16, NO>), dim3(gx, (unsigned)((c->prm.ny + 11) / 12), (unsigned)c->prm.nz),
+            hipLaunchKernelGGL((k_flux<M, 3, BX, 16, NO, BQ>), dim3(gx, (unsigned)((c->prm.ny + 11) / 12), (unsigned)c->prm.nz),
                                dim3(BX, 16), 0, c->stream, Az);
     } else if (c->prm.ndim == 1) {
         constexpr int BX = 256;
         dim3 grid((c->prm.nx + (BX - 4) - 1) / (BX - 4));
-        hipLaunchKernelGGL((k_flux<M, 1, BX, 1, NO>), grid, dim3(BX, 1), 0, c->stream, A);
+        hipLaunchKernelGGL((k_flux<M, 1, BX, 1, NO, BQ>), grid, dim3(BX, 1), 0, c->stream, A);
     } else {
         // 64 x 16 or 32 x 32 tiles for the single-fluid and ideal models; two-fluid grids
         // choose between 64 x 12, 32 x 24 and 64 x 16 (flux_rows_2d): the 768-thread blocks fit
@@ -417,19 +417,37 @@ static void launch_flux_mo(rmhd_ctx *c, const FluxArgs &A)
         const unsigned gx = (unsigned)((c->prm.nx + (BX - 4) - 1) / (BX - 4));
         const int rows = flux_rows_2d(c);
         if (rows == 8)
-            hipLaunchKernelGGL((k_flux<M, 2, BX, 8, NO>), dim3(gx, (c->prm.ny + 3) / 4), dim3(BX, 8), 0, c->stream, A);
+            hipLaunchKernelGGL((k_flux<M, 2, BX, 8, NO, BQ>), dim3(gx, (c->prm.ny + 3) / 4), dim3(BX, 8), 0, c->stream, A);
         else if (rows == 12)
-            hipLaunchKernelGGL((k_flux<M, 2, BX, 12, NO>), dim3(gx, (c->prm.ny + 7) / 8), dim3(BX, 12), 0, c->stream, A);
+            hipLaunchKernelGGL((k_flux<M, 2, BX, 12, NO, BQ>), dim3(gx, (c->prm.ny + 7) / 8), dim3(BX, 12), 0, c->stream, A);
         else if (M == RMHD_TWO_FLUID && rows == 24)
-            hipLaunchKernelGGL((k_flux<RMHD_TWO_FLUID, 2, 32, 24, NO>),
+            hipLaunchKernelGGL((k_flux<RMHD_TWO_FLUID, 2, 32, 24, NO, BQ>),
                                dim3((c->prm.nx + 27) / 28, (c->prm.ny + 19) / 20), dim3(32, 24), 0, c->stream, A);
         else if (M != RMHD_TWO_FLUID && rows == 32)
-            hipLaunchKernelGGL((k_flux<M == RMHD_TWO_FLUID ? RMHD_SINGLE_FLUID : M, 2, 32, 32, NO>),
+            hipLaunchKernelGGL((k_flux<M == RMHD_TWO_FLUID ? RMHD_SINGLE_FLUID : M, 2, 32, 32, NO, BQ>),
                                dim3((c->prm.nx + 27) / 28, (c->prm.ny + 27) / 28), dim3(32, 32), 0, c->stream, A);
         else
-            hipLaunchKernelGGL((k_flux<M, 2, BX, 16, NO>), dim3(gx, (c->prm.ny + 11) / 12), dim3(BX, 16), 0,
+            hipLaunchKernelGGL((k_flux<M, 2, BX, 16, NO, BQ>), dim3(gx, (c->prm.ny + 11) / 12), dim3(BX, 16), 0,
                                c->stream, A);
     }
+}
+
+// Outputs that all share one base whose source-free planes are q's (the first pass of a step)
+// take those base values from the state the tile already holds (base_terms, BQ).
+template <int M, int NO>
+static void launch_flux_mo(rmhd_ctx *c, const FluxArgs &A)
+{
+    bool bq = NO >= 2 && A.o[0].base.p[0] != nullptr;
+    for (int k = 1; k < NO && bq; ++k) bq = A.o[k].base.p[0] == A.o[0].base.p[0];
+    for (int v = 0; v < c->lay.ncons && bq; ++v)
+        if (!has_source(M, v)) bq = A.o[0].base.p[0] + (long)v * c->geo.plane == A.q.p[v];
+    if constexpr (NO >= 2) {
+        if (bq) {
+            launch_flux_shape<M, NO, true>(c, A);
+            return;
+        }
+    }
+    launch_flux_shape<M, NO, false>(c, A);
 }
 
 template <int M>
