@@ -104,3 +104,51 @@ def test_zero_coefficient_stage_is_identity(R, O, model):
     assert (ost == 0).all()
     assert np.all(rel_linf(s.grid.download_all(prims), ow) < 1e-12)
     s.close()
+
+
+@pytest.mark.parametrize("case,rows", [("single fluid 4x4, outflow", 32), ("ideal 4x4, periodic", 32),
+                                       ("two fluid 4x4, outflow", 24), ("single fluid 4x4x4, periodic", 32)])
+def test_smallest_grids_other_tile_shapes_match_oracle(R, O, case, rows):
+    """The 32 x 32 (single fluid, ideal) and 32 x 24 (two fluid) tiles, which the library picks
+    only for larger grids, on the smallest grids (one tile, almost all halo and ghost cells):
+    20 steps against the oracle to 1e-9."""
+    banner(f"smallest grid, {rows}-row tile: {case}")
+    wl = SMALLEST[case]()
+    g, oc, op = initial_state(wl)
+    dt = O.dt(g, wl.cfl)
+    advance(g, oc, op, dt, steps=20)
+    s = gpu_solver(R, wl)
+    s.set_flux_rows(rows)
+    cons, prims = s.initial_state(wl.prims, wl.EB)
+    for _ in range(20):
+        s.step(dt, cons, prims)
+    st = s.stats()
+    gc, gp = s.grid.download_all(cons), s.grid.download_all(prims)
+    s.close()
+    assert st["failures"] == 0
+    err = rel_linf(g.interior(gc), g.interior(oc))
+    print("rel Linf per variable", err)
+    assert np.all(err < 1e-9)
+    assert np.all(rel_linf(g.interior(gp), g.interior(op)) < 1e-9)
+
+
+def test_flux_tile_shape_is_checked_against_the_model(R):
+    """32 x 24 tiles exist for the two-fluid model only, 32 x 32 for the other models; any
+    other height is refused."""
+    banner("flux tile shape validation")
+    sf = gpu_solver(R, WL.kelvin_helmholtz_2d(8, 8))
+    tf = gpu_solver(R, WL.two_fluid_sheet_2d(8, 8))
+    try:
+        with pytest.raises(R.RmhdError):
+            sf.set_flux_rows(24)
+        with pytest.raises(R.RmhdError):
+            tf.set_flux_rows(32)
+        with pytest.raises(R.RmhdError):
+            sf.set_flux_rows(10)
+        sf.set_flux_rows(32)
+        tf.set_flux_rows(24)
+        sf.set_flux_rows(0)
+        tf.set_flux_rows(0)
+    finally:
+        sf.close()
+        tf.close()
