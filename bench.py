@@ -402,6 +402,9 @@ def main() -> int:
     ap.add_argument("--no-ideal", action="store_true")
     ap.add_argument("--only-3d", action="store_true",
                     help="print the 3-D grid measurements alone (for profiling the 3-D flux pass)")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="time the 64-domain batched step alone at the autotuner's usual shape (one block "
+                         "per stage item, no queue, HIP graph), without tuning runs, for profiling")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (traffic calibration)")
     args = ap.parse_args()
@@ -421,6 +424,19 @@ def main() -> int:
     if args.only_3d:
         copy_calibration(args.copy_mib)
         print(json.dumps({"grid3d": grid3d_measure(max(3, args.steps // 20), args.warmup)}), flush=True)
+        return 0
+    if args.only_batched:
+        copy_calibration(args.copy_mib)
+        doms = WL.batched_domains(seed=4)
+        B = R.Batch(doms)
+        B.tune(persistent=0, newton_cap=50, flux_rows=16, use_graph=1)
+        for _ in range(args.warmup):
+            B.step()
+        ms = timed_steps(B.step, args.steps)
+        B.close()
+        cells = sum(w.cells for w in doms)
+        print(json.dumps({"batched": {"cells": cells, "ms_per_step": ms, "value": cells / (ms / 1e3),
+                                      "unit": "cell-updates/s"}}), flush=True)
         return 0
     wall0 = time.perf_counter()
     # the network, trained on the device on rows harvested from 512^2 sheets at seeds 1-4

@@ -104,7 +104,9 @@ __device__ __forceinline__ void batch_write(const DomainDev &D, int phase, long 
     qplane(sf::EZ)[idx] = x[2];
     qplane(sf::PHI)[idx] = Rb[sf::PHI * g.plane + idx] * aK;
     qplane(sf::PSI)[idx] = (Rb[sf::PSI * g.plane + idx] + a * Rb[sf::RHOE * g.plane + idx]) * aK;
-    double *wo = phase == 1 ? D.w1 : D.prims;
+    // both stages' primitives go to w1 (the second stage's in place): the second flux pass
+    // reads them as its guess and recovers the new primitives into prims itself
+    double *wo = D.w1;
 #pragma unroll
     for (int v = 0; v < sf::NP; ++v) wo[v * g.plane + idx] = w[v];
 }
@@ -239,10 +241,13 @@ __global__ void kb_reset(unsigned *counters)
 struct BatchFluxArgs {
     const DomainDev *dom;
     const int4 *tiles;
-    int pass;   // 1: L(Q1) -> R2, ACC;  2: L(Q2) -> q^{n+1}
 };
 
-template <int NDIM, int BX, int BY>
+// PASS 1: L(Q1) -> R2, ACC;  PASS 2: L(Q2) -> q^{n+1} and its primitives (recovered by the
+// thread that forms each cell, from the second stage's, with their ghost images).  One
+// kernel per pass, so that each is allocated registers of its own (the 64 x 16 tile with
+// both passes in one kernel spilled 44 bytes per lane).
+template <int NDIM, int BX, int BY, int PASS>
 __global__ __launch_bounds__(BX *BY) void kb_flux(BatchFluxArgs B)
 {
     // tiles are listed domain by domain in row-major order: the XCD-aware renumbering keeps
@@ -256,7 +261,7 @@ __global__ __launch_bounds__(BX *BY) void kb_flux(BatchFluxArgs B)
     A.P = D.P;
     A.fuse_bc = 1;
     const double dt = D.dt;
-    if (B.pass == 1) {
+    if constexpr (PASS == 1) {
         int k = 0;
         for (int v = 0; v < sf::NC; ++v) {
             A.q.p[v] = has_source(0, v) ? D.q1src + (k++) * g.plane : D.cons + v * g.plane;
@@ -276,33 +281,16 @@ __global__ __launch_bounds__(BX *BY) void kb_flux(BatchFluxArgs B)
             A.o[0].base.p[v] = D.acc + v * g.plane;
             A.o[0].out.p[v] = D.cons + v * g.plane;
         }
-        for (int v = 0; v < sf::NP; ++v) A.w.p[v] = D.prims + v * g.plane;
+        for (int v = 0; v < sf::NP; ++v) {
+            A.w.p[v] = D.w1 + v * g.plane;
+            A.wnew.p[v] = D.prims + v * g.plane;
+        }
         A.o[0].cL = 0.5 * dt;
         A.o[0].cS = 0.5 * dt;
     }
     // pass 1: both outputs have q^n as base, whose source-free planes q shares
-    if (B.pass == 1) flux_tile<0, NDIM, BX, BY, 2, false, false, true>(A, t.y, t.z);
+    if constexpr (PASS == 1) flux_tile<0, NDIM, BX, BY, 2, false, false, true>(A, t.y, t.z);
     else flux_tile<0, NDIM, BX, BY, 1>(A, t.y, t.z);
-}
-
-__global__ __launch_bounds__(256) void kb_c2p(const DomainDev *dom, const int2 *items, int nitems)
-{
-    if ((int)blockIdx.x >= nitems) return;
-    const int2 it = items[blockIdx.x];
-    const DomainDev &D = dom[it.x];
-    const Geo &g = D.g;
-    const long idx = (long)it.y + threadIdx.x;
-    const int i = (int)(idx % g.pitch), j = (int)(idx / g.pitch);
-    if (idx >= g.plane || i >= g.nxg || j >= g.nyg) return;
-    double q[sf::NC], w[sf::NP];
-#pragma unroll
-    for (int v = 0; v < sf::NC; ++v) q[v] = D.cons[v * g.plane + idx];
-#pragma unroll
-    for (int v = 0; v < sf::NP; ++v) w[v] = D.prims[v * g.plane + idx];
-    int iters = 0;
-    sf_cons2prim(q, w, D.P, iters);
-#pragma unroll
-    for (int v = 0; v < sf::NP; ++v) D.prims[v * g.plane + idx] = w[v];
 }
 
 }  // namespace rmhd
@@ -505,6 +493,23 @@ extern "C" int rmhd_batch_create(const rmhd_params *domains, int n, void *stream
 }
 
 // enqueue one step's kernels on stream s (also used while capturing the graph)
+// One flux pass over every domain: the 1-D tile list, then the 2-D list of the tuned height.
+template <int PASS>
+static void launch_batch_flux(rmhd_batch *b, BatchFluxArgs F, int rows, hipStream_t s)
+{
+    if (b->ntiles1) {
+        F.tiles = b->tiles1;
+        hipLaunchKernelGGL((kb_flux<1, 256, 1, PASS>), dim3(b->ntiles1), dim3(256, 1), 0, s, F);
+    }
+    if (rows == 8 && b->ntiles2_8) {
+        F.tiles = b->tiles2_8;
+        hipLaunchKernelGGL((kb_flux<2, 64, 8, PASS>), dim3(b->ntiles2_8), dim3(64, 8), 0, s, F);
+    } else if (b->ntiles2_16) {
+        F.tiles = b->tiles2_16;
+        hipLaunchKernelGGL((kb_flux<2, 64, 16, PASS>), dim3(b->ntiles2_16), dim3(64, 16), 0, s, F);
+    }
+}
+
 static int enqueue_step(rmhd_batch *b, hipStream_t s)
 {
     const rmhd_batch_tuning &T = b->tune;
@@ -534,21 +539,9 @@ static int enqueue_step(rmhd_batch *b, hipStream_t s)
         hipLaunchKernelGGL(kb_reset, dim3(1), dim3(64), 0, s, A.counters);
         hipLaunchKernelGGL(kb_stage, sgrid, dim3(256), 0, s, A);
         if (A.K < b->max_newton) hipLaunchKernelGGL(kb_drain, dgrid, dim3(256), 0, s, A);
-        F.pass = phase;
-        if (b->ntiles1) {
-            F.tiles = b->tiles1;
-            hipLaunchKernelGGL((kb_flux<1, 256, 1>), dim3(b->ntiles1), dim3(256, 1), 0, s, F);
-        }
-        if (T.flux_rows == 8 && b->ntiles2_8) {
-            F.tiles = b->tiles2_8;
-            hipLaunchKernelGGL((kb_flux<2, 64, 8>), dim3(b->ntiles2_8), dim3(64, 8), 0, s, F);
-        } else if (b->ntiles2_16) {
-            F.tiles = b->tiles2_16;
-            hipLaunchKernelGGL((kb_flux<2, 64, 16>), dim3(b->ntiles2_16), dim3(64, 16), 0, s, F);
-        }
+        if (phase == 1) launch_batch_flux<1>(b, F, T.flux_rows, s);
+        else launch_batch_flux<2>(b, F, T.flux_rows, s);
     }
-    hipLaunchKernelGGL(kb_c2p, dim3((unsigned)b->nitems), dim3(256), 0, s, (const DomainDev *)b->ddom,
-                       (const int2 *)b->items, b->nitems);
     return bcheck(b, hipGetLastError(), "batch step launch");
 }
 
@@ -654,7 +647,6 @@ static int time_candidate(rmhd_batch *b, const rmhd_batch_tuning &t, int reps, f
     A.counters = b->counters;
     BatchFluxArgs F{};
     F.dom = b->ddom;
-    F.pass = 1;
     float best = 1e30f;
     for (int r = 0; r < reps + 1; ++r) {
         hipEventRecord(e0, b->stream);
@@ -663,17 +655,7 @@ static int time_candidate(rmhd_batch *b, const rmhd_batch_tuning &t, int reps, f
                            dim3(256), 0, b->stream, A);
         if (A.K < b->max_newton)
             hipLaunchKernelGGL(kb_drain, dim3((unsigned)((b->qcap + 255) / 256)), dim3(256), 0, b->stream, A);
-        if (b->ntiles1) {
-            F.tiles = b->tiles1;
-            hipLaunchKernelGGL((kb_flux<1, 256, 1>), dim3(b->ntiles1), dim3(256, 1), 0, b->stream, F);
-        }
-        if (t.flux_rows == 8 && b->ntiles2_8) {
-            F.tiles = b->tiles2_8;
-            hipLaunchKernelGGL((kb_flux<2, 64, 8>), dim3(b->ntiles2_8), dim3(64, 8), 0, b->stream, F);
-        } else if (b->ntiles2_16) {
-            F.tiles = b->tiles2_16;
-            hipLaunchKernelGGL((kb_flux<2, 64, 16>), dim3(b->ntiles2_16), dim3(64, 16), 0, b->stream, F);
-        }
+        launch_batch_flux<1>(b, F, t.flux_rows, b->stream);
         hipEventRecord(e1, b->stream);
         hipEventSynchronize(e1);
         float m = 0.f;
